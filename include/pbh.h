@@ -1,0 +1,156 @@
+/*
+ * pbh.h -- C ABI of the parallel bucket heap (parBucketHeap) and of
+ * parDijkstra, for AMD Instinct MI355X (gfx950).
+ *
+ * The paper: Berney, Iacono, Karsin, Sitchinava, "A Parallel Priority Queue
+ * with Fast Updates for GPU Architectures" (arXiv 1908.09378).
+ *
+ * Conventions shared by every entry point
+ *   - Elements are (key: uint64, id: uint32) pairs: the paper's (priority,
+ *     value) of Section 1.2.  Order is lexicographic on (key, id), so ties in
+ *     priority are broken by id.  key == UINT64_MAX is reserved ("absent",
+ *     "unreached") and is rejected as input.
+ *   - Array arguments are DEVICE pointers (hipMalloc'd memory or a torch
+ *     tensor's data_ptr() on the current GPU) unless the comment says "host".
+ *     The caller owns every array; the library keeps no caller pointer after
+ *     it returns.
+ *   - Calls are synchronous: outputs are valid when the call returns.  Work
+ *     is issued on the null stream (which orders it after earlier null-stream
+ *     work, e.g. PyTorch's default stream) unless an _ex variant is given a
+ *     stream.
+ *   - Every call returns PBH_OK (0) or a negative error code and never aborts;
+ *     pbh_last_error() gives a message for the calling thread's last failure.
+ *     On PBH_EINVAL nothing was modified.
+ *   - A handle must not be used by two threads at once.
+ */
+#ifndef PBH_H
+#define PBH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PBH_OK = 0,
+  PBH_EINVAL = -1,     /* bad argument: null pointer, id >= capacity, key == UINT64_MAX, bad CSR */
+  PBH_ECAPACITY = -2,  /* the heap needed more levels than were allocated */
+  PBH_ENOMEM = -3,     /* device allocation failed */
+  PBH_EDEVICE = -4,    /* a HIP call failed */
+  PBH_ETIMEOUT = -5,   /* a bounded device-side wait ran out */
+  PBH_EINTERNAL = -6   /* a device-side consistency check failed (a bug) */
+};
+
+typedef struct pbh pbh_t; /* opaque; owned by the library */
+
+/*
+ * pbh_create: a parallel bucket heap over ids [0, id_capacity) with maximum
+ * bulk size d (Section 2.2: bucket B_i holds d*2^(2i+1) elements and signal
+ * buffer S_i holds d*2^(2i); q = ceil(log4(n/d)) + 1 levels).  Levels beyond
+ * q are added on demand.  The handle owns its device arena: the levels, the
+ * current key of every id (8 bytes x id_capacity) and scratch.
+ * Errors: PBH_EINVAL if out is NULL, id_capacity == 0 or d == 0;
+ * PBH_ENOMEM / PBH_EDEVICE.
+ */
+int pbh_create(pbh_t **out, uint32_t id_capacity, uint32_t d);
+
+/*
+ * pbh_bulk_update: BulkUpdate(U) of Section 1.2 -- update(e) for each of the
+ * count pairs (keys[i], ids[i]) (device arrays): the element with that id gets
+ * key min(current, keys[i]); an absent id is inserted.  Within a batch the
+ * smallest key per id wins and order does not matter.  Batches larger than d
+ * are applied in pieces of at most d (the paper's bound on |U|), with the same
+ * result.  Errors: PBH_EINVAL (NULL handle, NULL arrays with count > 0, any
+ * id >= id_capacity or key == UINT64_MAX; nothing is applied), PBH_ECAPACITY,
+ * PBH_EDEVICE, PBH_EINTERNAL.
+ */
+int pbh_bulk_update(pbh_t *h, const uint64_t *keys, const uint32_t *ids, uint64_t count);
+
+/*
+ * pbh_extract_min: batched ExtractMin (Section 1.2; Section 3.2 lets level 0
+ * serve many extractions per Resolve(0)).  Removes the min(k, size) smallest
+ * elements and writes them in ascending (key, id) order to keys_out[] and
+ * ids_out[] (device arrays with room for k); *count_out (host) receives their
+ * number.  Equal to k successive ExtractMins.  Errors: PBH_EINVAL (NULL handle
+ * or count_out, NULL outputs with k > 0), PBH_EDEVICE, PBH_EINTERNAL.
+ */
+int pbh_extract_min(pbh_t *h, uint64_t k, uint64_t *keys_out, uint32_t *ids_out,
+                    uint64_t *count_out);
+
+/* pbh_size: number of elements in the heap (host *size_out). */
+int pbh_size(pbh_t *h, uint64_t *size_out);
+
+/* pbh_destroy: frees the handle and its arena.  NULL is accepted. */
+int pbh_destroy(pbh_t *h);
+
+/*
+ * Heap layout snapshot for invariant checks (Algorithm 1 pre/postconditions,
+ * Theorem 1).  For each level i < *levels_out (host arrays of length
+ * max_levels): sizes of B_i and S_i, the pivot p_i as (key, id) (UINT64_MAX
+ * key = +infinity), and how many times Resolve(i) has run.  *ell_out receives
+ * the deepest non-empty level (-1 when empty).
+ */
+int pbh_debug_levels(pbh_t *h, uint32_t max_levels, uint32_t *levels_out, int32_t *ell_out,
+                     uint32_t *nB, uint32_t *nS, uint64_t *p_key, uint32_t *p_id,
+                     uint64_t *resolves);
+
+/*
+ * sssp: single-source shortest paths by parDijkstra (Section 4.1): rounds of
+ * ExtractMin of the closest vertex u, relaxation of all out-edges (u, v) in
+ * parallel, and BulkUpdate of the ones that got shorter, on a parallel bucket
+ * heap with d = maximum out-degree.  Graph in CSR form (device arrays):
+ * offsets[n+1] (uint64; offsets[0] == 0, non-decreasing, offsets[n] == m),
+ * targets[m] (uint32 < n), weights[m] (uint32, zero allowed).  Self-loops and
+ * multi-edges are allowed.  dist_out[n] (device) receives the distances
+ * (UINT64_MAX = unreachable).  Errors: PBH_EINVAL (NULL pointers, n == 0,
+ * source >= n, malformed CSR), PBH_ENOMEM, PBH_EDEVICE, PBH_ECAPACITY,
+ * PBH_ETIMEOUT, PBH_EINTERNAL.
+ */
+int sssp(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
+         uint64_t m, uint32_t source, uint64_t *dist_out);
+
+/* Options for sssp_ex.  Zero-initialised means "defaults". */
+typedef struct {
+  uint32_t d;             /* heap bulk size; 0 = maximum out-degree (the paper's choice) */
+  uint32_t team;          /* threads of the workgroup that runs the rounds: 0 = auto, 64/256/1024 */
+  uint32_t schedule;      /* 0 = Theorem 1 (Resolve(i) after every 4th Resolve(i-1)),
+                             1 = on demand only (resolve a level when its buffers require it) */
+  uint32_t lds_levels;    /* levels kept in LDS: 0 = as many as fit, k = exactly k,
+                             0xFFFFFFFF = none (all levels in HBM) */
+  uint64_t heap_capacity; /* elements the arena is sized for; 0 = auto (retried with the
+                             safe bound m+1 on PBH_ECAPACITY) */
+  uint32_t reserved[8];
+} sssp_opts;
+
+/* Statistics of one sssp_ex run (host struct). */
+typedef struct {
+  uint64_t rounds;        /* extract-relax-update rounds */
+  uint64_t relaxations;   /* edges scanned */
+  uint64_t updates;       /* (key, id) pairs inserted into the heap */
+  uint64_t heap_elems;    /* heap elements read + written by the level operations */
+  uint64_t resolves[16];  /* Resolve(i) executions per level */
+  uint32_t levels;        /* levels allocated */
+  uint32_t d;             /* bulk size used */
+  uint32_t team;          /* workgroup size used */
+  uint32_t lds_levels;    /* levels resident in LDS */
+  double kernel_ms;       /* device time of the round-loop kernel (HIP events) */
+} sssp_stats;
+
+/*
+ * sssp_ex: sssp with options, statistics (stats may be NULL) and a HIP stream
+ * (hipStream_t passed as void*, NULL = null stream).  The call still returns
+ * only when the result is in dist_out.
+ */
+int sssp_ex(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
+            uint64_t m, uint32_t source, uint64_t *dist_out, const sssp_opts *opts,
+            sssp_stats *stats, void *stream);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *pbh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBH_H */

@@ -1,0 +1,155 @@
+"""Python binding of libpbh.so: the parallel bucket heap (parBucketHeap) and
+parDijkstra for MI355X (gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of the library.
+Arrays are torch tensors on the GPU (uint64 data as int64/uint64 tensors,
+uint32 data as int32/uint32 tensors); the C entry points of include/pbh.h
+receive their device pointers.  There is no CPU fallback: if the library is
+not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbh.so")
+
+PBH_OK, PBH_EINVAL, PBH_ECAPACITY, PBH_ENOMEM, PBH_EDEVICE, PBH_ETIMEOUT, PBH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+
+class PBHError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class SsspOpts(C.Structure):
+    _fields_ = [("d", C.c_uint32), ("team", C.c_uint32), ("schedule", C.c_uint32),
+                ("lds_levels", C.c_uint32), ("heap_capacity", C.c_uint64), ("reserved", C.c_uint32 * 8)]
+
+
+class SsspStats(C.Structure):
+    _fields_ = [("rounds", C.c_uint64), ("relaxations", C.c_uint64), ("updates", C.c_uint64),
+                ("heap_elems", C.c_uint64), ("resolves", C.c_uint64 * 16), ("levels", C.c_uint32),
+                ("d", C.c_uint32), ("team", C.c_uint32), ("lds_levels", C.c_uint32), ("kernel_ms", C.c_double)]
+
+
+_lib = None
+EXPORTS = ["pbh_create", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_destroy",
+           "pbh_debug_levels", "sssp", "sssp_ex", "pbh_last_error"]
+
+
+def lib():
+    """Loads libpbh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1908_09378_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        L.pbh_create.argtypes = [C.POINTER(vp), u32, u32]
+        L.pbh_bulk_update.argtypes = [vp, vp, vp, u64]
+        L.pbh_extract_min.argtypes = [vp, u64, vp, vp, C.POINTER(u64)]
+        L.pbh_size.argtypes = [vp, C.POINTER(u64)]
+        L.pbh_destroy.argtypes = [vp]
+        L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
+        L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
+        L.sssp_ex.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
+        L.pbh_last_error.restype = C.c_char_p
+        for f in EXPORTS[:-1]:
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PBH_OK:
+        raise PBHError(rc, lib().pbh_last_error().decode())
+
+
+def _ptr(t, elem_bytes):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("arrays must be GPU tensors")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous")
+    if t.element_size() != elem_bytes:
+        raise ValueError(f"expected {elem_bytes}-byte elements, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> None:
+    """parDijkstra: dist_out[v] = shortest distance from source (UINT64_MAX if
+    unreachable); see include/pbh.h."""
+    _check(lib().sssp(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source, _ptr(dist_out, 8)))
+
+
+def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, d=0, team=0, schedule=0,
+            lds_levels=0, heap_capacity=0, stream=None) -> dict:
+    o = SsspOpts(d, team, schedule, lds_levels, heap_capacity)
+    s = SsspStats()
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sssp_ex(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source, _ptr(dist_out, 8),
+                         C.byref(o), C.byref(s), sp))
+    return dict(rounds=s.rounds, relaxations=s.relaxations, updates=s.updates, heap_elems=s.heap_elems,
+                resolves=list(s.resolves), levels=s.levels, d=s.d, team=s.team, lds_levels=s.lds_levels,
+                kernel_ms=s.kernel_ms)
+
+
+class Heap:
+    """A parallel bucket heap over ids [0, id_capacity) with bulk size d."""
+
+    def __init__(self, id_capacity: int, d: int):
+        h = C.c_void_p()
+        _check(lib().pbh_create(C.byref(h), id_capacity, d))
+        self._h = h
+        self.id_capacity = id_capacity
+        self.d = d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pbh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bulk_update(self, keys, ids) -> None:
+        count = keys.numel()
+        if ids.numel() != count:
+            raise ValueError("keys and ids differ in length")
+        _check(lib().pbh_bulk_update(self._h, _ptr(keys, 8) if count else None,
+                                     _ptr(ids, 4) if count else None, count))
+
+    def extract_min(self, k: int, keys_out, ids_out) -> int:
+        if k and (keys_out.numel() < k or ids_out.numel() < k):
+            raise ValueError("output arrays shorter than k")
+        n = C.c_uint64(0)
+        _check(lib().pbh_extract_min(self._h, k, _ptr(keys_out, 8) if k else None,
+                                     _ptr(ids_out, 4) if k else None, C.byref(n)))
+        return n.value
+
+    def size(self) -> int:
+        n = C.c_uint64(0)
+        _check(lib().pbh_size(self._h, C.byref(n)))
+        return n.value
+
+    def debug_levels(self) -> dict:
+        import numpy as np
+        cap = 16
+        q = C.c_uint32(0)
+        ell = C.c_int32(0)
+        nB = np.zeros(cap, np.uint32)
+        nS = np.zeros(cap, np.uint32)
+        pk = np.zeros(cap, np.uint64)
+        pv = np.zeros(cap, np.uint32)
+        rs = np.zeros(cap, np.uint64)
+        _check(lib().pbh_debug_levels(self._h, cap, C.byref(q), C.byref(ell), nB.ctypes.data, nS.ctypes.data,
+                                      pk.ctypes.data, pv.ctypes.data, rs.ctypes.data))
+        k = q.value
+        return dict(q=k, ell=ell.value, nB=nB[:k], nS=nS[:k], pk=pk[:k], pv=pv[:k], resolves=rs[:k])

@@ -1,0 +1,169 @@
+// Kernels of the parallel bucket heap and parDijkstra for gfx950.
+//
+//  k_sssp          one workgroup (one team) runs all parDijkstra rounds; the
+//                  small top levels of the heap live in its LDS, deeper
+//                  levels in HBM.  One kernel per query: no host round trip
+//                  per round.
+//  k_pbh_update    BulkUpdate of a host call (current keys + id bitmap,
+//                  then pieces of at most d into S_0, each followed by
+//                  Resolve(0) and the schedule).
+//  k_pbh_extract   batched ExtractMin of a host call.
+//  k_fill_dist, k_check_csr, k_check_update: grid-wide helpers.
+#include "pbh_launch.h"
+
+namespace bkt {
+
+__global__ void k_fill_dist(u64* dist, u32 n, u32 src) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    dist[i] = (i == src) ? 0ull : KINF;
+}
+
+// offsets[0] == 0, non-decreasing, offsets[n] == m, targets < n; max degree.
+__global__ void k_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out) {
+  u64 bad = 0, md = 0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  const u64 t0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  for (u64 u = t0; u < n; u += stride) {
+    u64 a = off[u], b = off[u + 1];
+    if (b < a) bad = 1;
+    else md = (b - a) > md ? (b - a) : md;
+  }
+  if (t0 == 0 && (off[0] != 0 || off[n] != m)) bad = 1;
+  for (u64 e = t0; e < m; e += stride)
+    if (tg[e] >= n) bad = 1;
+  if (bad) atomicOr(&out->bad, 1ull);
+  if (md) atomicMax(&out->maxdeg, md);
+}
+
+__global__ void k_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad) {
+  u64 b = 0;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (u64)gridDim.x * blockDim.x)
+    if (ids[i] >= id_cap || keys[i] == KINF) b = 1;
+  if (b) atomicOr(bad, 1ull);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st;
+  DevTeam<NT> t{&ts};
+  Geom g = p.g;
+  const u64 nl = lvl_off(g.d, g.qlds);
+  g.lk = reinterpret_cast<u64*>(dyn);
+  g.lv = reinterpret_cast<u32*>(dyn + nl * sizeof(u64));
+  if (threadIdx.x == 0) state_init(&st, g.d, g.q);
+  t.sync();
+  SsspCounters c;
+  sssp_rounds(t, g, &st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, &c);
+  t.sync();
+  if (threadIdx.x == 0) {
+    SsspDevStats* o = p.stats;
+    o->rounds = c.rounds;
+    o->relax = c.relax;
+    o->updates = c.updates;
+    o->elems = st.elems;
+    o->err = st.err;
+    o->ell = st.ell;
+    for (int i = 0; i < MAXL; ++i) o->resolves[i] = st.L[i].cnt;
+  }
+}
+
+template <int NT>
+__device__ void load_state(DevTeam<NT>& t, HeapState* st, const HeapState* gst) {
+  const u32* s = reinterpret_cast<const u32*>(gst);
+  u32* d = reinterpret_cast<u32*>(st);
+  for (u32 i = threadIdx.x; i < sizeof(HeapState) / 4; i += NT) d[i] = s[i];
+  t.sync();
+}
+
+template <int NT>
+__device__ void store_state(DevTeam<NT>& t, const HeapState* st, HeapState* gst) {
+  t.sync();
+  const u32* s = reinterpret_cast<const u32*>(st);
+  u32* d = reinterpret_cast<u32*>(gst);
+  for (u32 i = threadIdx.x; i < sizeof(HeapState) / 4; i += NT) d[i] = s[i];
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pbh_update(PbhParams p) {
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st;
+  DevTeam<NT> t{&ts};
+  load_state(t, &st, p.gst);
+  pbh_update_body(t, p.g, &st, p);
+  store_state(t, &st, p.gst);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pbh_extract(PbhParams p) {
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st;
+  DevTeam<NT> t{&ts};
+  load_state(t, &st, p.gst);
+  pbh_extract_body(t, p.g, &st, p);
+  store_state(t, &st, p.gst);
+}
+
+static int grid_for(u64 work, int block) {
+  u64 g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (int)g;
+}
+
+hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_dist, dim3(grid_for(n, 256)), dim3(256), 0, s, dist, n, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_csr, dim3(grid_for(m > n ? m : n, 256)), dim3(256), 0, s, off, tg, n, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_check_update, dim3(grid_for(count, 256)), dim3(256), 0, s, keys, ids, count, id_cap, bad);
+  return hipGetLastError();
+}
+
+size_t sssp_static_lds(int team) {
+  size_t hs = sizeof(HeapState);
+  switch (team) {
+    case 64: return sizeof(TeamShared<1>) + hs;
+    case 256: return sizeof(TeamShared<4>) + hs;
+    default: return sizeof(TeamShared<16>) + hs;
+  }
+}
+
+template <int NT>
+static hipError_t sssp_go(const SsspParams& p, size_t lds, hipStream_t s) {
+  if (lds > 65536 - sssp_static_lds(NT)) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sssp<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sssp<NT>, dim3(1), dim3(NT), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s) {
+  switch (team) {
+    case 64: return sssp_go<64>(p, lds_bytes, s);
+    case 256: return sssp_go<256>(p, lds_bytes, s);
+    case 1024: return sssp_go<1024>(p, lds_bytes, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_pbh_update<1024>, dim3(1), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pbh_extract(const PbhParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_pbh_extract<1024>, dim3(1), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace bkt

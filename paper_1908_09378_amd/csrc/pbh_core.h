@@ -1,0 +1,978 @@
+// Parallel bucket heap (Section 2.2) and parDijkstra rounds (Section 4.1),
+// written once against a "team" (pbh_team.h): every thread of the team runs the
+// same control flow on team-uniform values; the data-parallel steps (Merge,
+// DeleteDuplicates, Select, PrefixSums, the relaxation) are split across the
+// team's threads.
+//
+// Elements are (key u64, id u32) in structure-of-arrays form, ordered by
+// (key, id).  Level i has a bucket B_i and a signal buffer S_i, each kept
+// sorted by id (Section 2.1), nominal sizes |B_i| = 2d*4^i and |S_i| = d*4^i
+// (Section 2.2), and a pivot p_i with B_i <= p_i < every element deeper.
+#pragma once
+#include "pbh_team.h"
+
+#define PBH_HD __host__ __device__
+
+namespace bkt {
+
+constexpr u64 KINF = ~0ull;
+constexpr u32 VINF = ~0u;
+constexpr int MAXL = 16;
+
+enum { E_OK = 0, E_INVAL = -1, E_CAPACITY = -2, E_INTERNAL = -6 };
+
+struct KV {
+  u64 k;
+  u32 v;
+};
+PBH_HD inline bool kv_less(KV a, KV b) { return a.k < b.k || (a.k == b.k && a.v < b.v); }
+PBH_HD inline bool kv_le(KV a, KV b) { return !kv_less(b, a); }
+PBH_HD inline KV kv_inf() { return KV{KINF, VINF}; }
+
+struct Arr {
+  u64* k;
+  u32* v;
+};
+
+// ---------------------------------------------------------------- geometry
+// Nominal sizes from Section 2.2, and the allocated buffer sizes.  A level
+// stores two B buffers (merge ping-pong, 4d*4^i each), one temporary T (4d*4^i)
+// and two S buffers (2d*4^i each): 16d*4^i elements.  The allocated sizes
+// leave room for what Algorithm 1 can hold between two Resolve(i): B_i may
+// absorb elements of S_i that fall below p_i, and each Resolve(i-1) adds at
+// most |S_{i-1}| + |B_{i-1}| to S_i.
+PBH_HD inline u64 nomS(u32 d, int i) { return (u64)d << (2 * i); }
+PBH_HD inline u64 nomB(u32 d, int i) { return (u64)d << (2 * i + 1); }
+PBH_HD inline u64 capS(u32 d, int i) { return (u64)d << (2 * i + 1); }
+PBH_HD inline u64 capB(u32 d, int i) { return (u64)d << (2 * i + 2); }
+PBH_HD inline u64 lvl_size(u32 d, int i) { return (16ull * d) << (2 * i); }
+PBH_HD inline u64 lvl_off(u32 d, int i) { return 16ull * d * (((1ull << (2 * i)) - 1ull) / 3ull); }
+
+struct Geom {
+  u32 d;
+  int q;     // levels allocated
+  int qlds;  // levels 0..qlds-1 live in LDS
+  u64* gk;   // global arena (level qlds at offset 0)
+  u32* gv;
+  u64* lk;   // LDS arena
+  u32* lv;
+};
+
+// Buffer w of level i: 0/1 = B ping-pong, 2 = T, 3/4 = S ping-pong.
+PBH_HD inline Arr lbuf(const Geom& g, int i, int w) {
+  u64 cb = capB(g.d, i);
+  u64 off = (w < 3) ? (u64)w * cb : 3ull * cb + (u64)(w - 3) * capS(g.d, i);
+  if (i < g.qlds) {
+    u64 b = lvl_off(g.d, i) + off;
+    return Arr{g.lk + b, g.lv + b};
+  }
+  u64 b = lvl_off(g.d, i) - lvl_off(g.d, g.qlds) + off;
+  return Arr{g.gk + b, g.gv + b};
+}
+
+struct Lvl {
+  u32 nB, nS;    // sizes of B_i and S_i
+  u32 bsel;      // which B buffer (0/1) holds B_i
+  u32 ssel;      // which S buffer (0/1) holds S_i
+  u64 pk;        // pivot p_i = (pk, pv); KINF = +infinity
+  u32 pv;
+  u32 cnt;       // Resolve(i) executions
+};
+
+struct HeapState {
+  Lvl L[MAXL];
+  int ell;       // deepest non-empty level, -1 if the heap is empty
+  int err;
+  u32 d;
+  int q;
+  u64 elems;     // heap elements read + written by level operations
+  u64 live;      // elements in the heap (queue size)
+  u64 progress;  // resumable progress of a multi-piece operation
+  u64 aux[5];
+};
+
+PBH_HD inline void state_init(HeapState* st, u32 d, int q) {
+  for (int i = 0; i < MAXL; ++i) {
+    st->L[i].nB = st->L[i].nS = st->L[i].bsel = st->L[i].ssel = st->L[i].cnt = 0;
+    st->L[i].pk = KINF;
+    st->L[i].pv = VINF;
+  }
+  st->ell = -1;
+  st->err = 0;
+  st->d = d;
+  st->q = q;
+  st->elems = st->live = st->progress = 0;
+  for (int i = 0; i < 5; ++i) st->aux[i] = 0;
+}
+
+// Reads of cur[] (the current key of each id; dist[] in SSSP) must observe
+// atomicMin updates made at L2 by the same team, so they are coherent loads.
+template <class T>
+PBH_HD inline u64 load_cur(const T& t, const u64* p) {
+  return t.load_cur(p);
+}
+
+// ---------------------------------------------------------------- primitives
+
+// Merge-path split (Green, McColl, Bader 2012): how many of the first `diag`
+// elements of merge(A, B) by id come from A (A first on equal ids).
+PBH_HD inline u32 merge_path(const u32* av, u32 na, const u32* bv, u32 nb, u32 diag) {
+  u32 lo = diag > nb ? diag - nb : 0u, hi = diag < na ? diag : na;
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1;
+    if (av[mid] <= bv[diag - 1 - mid])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Merge + DeleteDuplicates (Algorithm 1; DeleteDuplicates by scan + prefix
+// sums as in Lemma 2's proof).  A and B are sorted by id with unique ids; the
+// output C (not aliasing A or B) is sorted by id with unique ids.  For a pair
+// of copies of one id the one whose key equals cur[id] (the live one) is kept;
+// if neither is live both are dropped; without cur the smaller key is kept
+// (Section 2.1: duplicates keep the smaller priority).  With filterB, B
+// elements that are not live are dropped as well (used when elements move up
+// into B_0, so that B_0 holds only live elements).
+template <class T, int E = 4>
+PBH_HD u32 merge_dedup(T& t, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, bool filterB) {
+  const u32 total = na + nb;
+  u32 out = 0;
+  for (u32 base = 0; base < total; base += (u32)T::kNT * E) {
+    u32 d0 = base + (u32)t.tid() * E;
+    d0 = d0 < total ? d0 : total;
+    u32 d1 = d0 + E < total ? d0 + E : total;
+    u32 i = merge_path(A.v, na, B.v, nb, d0), j = d0 - i;
+    u64 ko[E];
+    u32 vo[E];
+    u32 keep = 0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      ko[s] = 0;
+      vo[s] = 0;
+      if (d0 + s < d1) {
+        bool takeA = i < na && (j >= nb || A.v[i] <= B.v[j]);
+        if (takeA) {
+          u64 ka = A.k[i];
+          u32 va = A.v[i];
+          bool kp = true;
+          if (j < nb && B.v[j] == va) {
+            u64 kb = B.k[j];
+            if (kb != ka) {
+              if (cur) {
+                u64 c = load_cur(t, cur + va);
+                if (ka == c) {
+                } else if (kb == c) {
+                  ka = kb;
+                } else {
+                  kp = false;
+                }
+              } else if (kb < ka) {
+                ka = kb;
+              }
+            }
+          }
+          ko[s] = ka;
+          vo[s] = va;
+          keep |= (u32)kp << s;
+          ++i;
+        } else {
+          u64 kb = B.k[j];
+          u32 vb = B.v[j];
+          bool kp = !(i > 0 && A.v[i - 1] == vb);
+          if (kp && filterB && load_cur(t, cur + vb) != kb) kp = false;
+          ko[s] = kb;
+          vo[s] = vb;
+          keep |= (u32)kp << s;
+          ++j;
+        }
+      }
+    }
+    u32 tot;
+    u32 w = out + t.scan_excl((u32)__builtin_popcount(keep), &tot);
+#pragma unroll
+    for (int s = 0; s < E; ++s)
+      if ((keep >> s) & 1u) {
+        C.k[w] = ko[s];
+        C.v[w] = vo[s];
+        ++w;
+      }
+    out += tot;
+  }
+  t.sync();
+  return out;
+}
+
+// |{e in A : e <= p}|
+template <class T>
+PBH_HD u32 count_le(T& t, Arr A, u32 n, KV p) {
+  if (p.k == KINF) return n;
+  u32 c = 0;
+  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) c += kv_le(KV{A.k[x], A.v[x]}, p) ? 1u : 0u;
+  return t.sum(c);
+}
+
+// Finds the histogram bin where the r-th element (1-based) falls.
+template <class T>
+PBH_HD void hist_pick(T& t, u32 r, u32* D, u32* below, u32* cnt) {
+  constexpr int BPT = (256 + T::kNT - 1) / T::kNT;
+  u32 b0 = (u32)t.tid() * BPT;
+  u32 loc = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q)
+    if (b0 + q < 256) loc += t.sh->hist[b0 + q];
+  u32 tot;
+  u32 pre = t.scan_excl(loc, &tot);
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    u32 b = b0 + q;
+    if (b < 256) {
+      u32 h = t.sh->hist[b];
+      if (pre < r && r <= pre + h) {
+        t.sh->b32[0] = b;
+        t.sh->b32[1] = pre;
+        t.sh->b32[2] = h;
+      }
+      pre += h;
+    }
+  }
+  t.sync();
+  *D = t.sh->b32[0];
+  *below = t.sh->b32[1];
+  *cnt = t.sh->b32[2];
+  t.sync();
+}
+
+// Select(A, r): the r-th smallest (key, id) of A, 1 <= r <= n.  Radix select,
+// most significant byte first, over key - min(key) (only the bytes the key
+// range needs), then over the id among elements with the selected key.  The
+// paper sorted with a radix sort to select (Section 4.1); a radix select reads
+// the candidates once per byte and sorts nothing.
+template <class T>
+PBH_HD KV select_kth(T& t, Arr A, u32 n, u32 r) {
+  u64 lo = KINF, hi = 0;
+  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
+    u64 k = A.k[x];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  t.minmax64(lo, hi);
+  u64 span = hi - lo;
+  int nb = span ? 64 - __builtin_clzll(span) : 0;
+  int top = (nb + 7) & ~7;
+  u64 prefix = 0;
+  u32 cnt = n;
+  for (int s = top - 8; s >= 0; s -= 8) {
+    for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
+    t.sync();
+    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
+      u64 dk = A.k[x] - lo;
+      bool m = (s + 8 >= 64) ? true : ((dk >> (s + 8)) == prefix);
+      if (m) t.hist_add(t.sh->hist, (u32)(dk >> s) & 255u);
+    }
+    t.sync();
+    u32 D, below;
+    hist_pick(t, r, &D, &below, &cnt);
+    prefix = (prefix << 8) | D;
+    r -= below;
+  }
+  const u64 K = lo + prefix;
+  if (cnt == 1) {
+    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT)
+      if (A.k[x] == K) t.sh->b32[3] = A.v[x];
+    t.sync();
+    u32 id = t.sh->b32[3];
+    t.sync();
+    return KV{K, id};
+  }
+  u32 idp = 0;
+  for (int s = 24; s >= 0; s -= 8) {
+    for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
+    t.sync();
+    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
+      u32 v = A.v[x];
+      if (A.k[x] == K && (s == 24 || (v >> (s + 8)) == idp)) t.hist_add(t.sh->hist, (v >> s) & 255u);
+    }
+    t.sync();
+    u32 D, below, c2;
+    hist_pick(t, r, &D, &below, &c2);
+    idp = (idp << 8) | D;
+    r -= below;
+  }
+  return KV{K, idp};
+}
+
+// Stable three-way split of A (order by id is kept in each part):
+// e <= p1 -> O0, p1 < e <= p2 -> O1, e > p2 -> O2.
+template <class T, int E = 4>
+PBH_HD void partition3(T& t, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, u32* n0, u32* n1,
+                       u32* n2) {
+  u32 c0t = 0, c1t = 0, c2t = 0;
+  for (u32 base = 0; base < n; base += (u32)T::kNT * E) {
+    u32 x0 = base + (u32)t.tid() * E;
+    u64 kk[E];
+    u32 vv[E];
+    u32 cl[E];
+    u32 c0 = 0, c1 = 0;
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      kk[s] = 0;
+      vv[s] = 0;
+      cl[s] = 3;
+      if (x0 + s < n) {
+        kk[s] = A.k[x0 + s];
+        vv[s] = A.v[x0 + s];
+        KV e{kk[s], vv[s]};
+        cl[s] = kv_le(e, p1) ? 0u : (kv_le(e, p2) ? 1u : 2u);
+        c0 += cl[s] == 0;
+        c1 += cl[s] == 1;
+      }
+    }
+    u32 tot;
+    u32 pre = t.scan_excl(c0 | (c1 << 16), &tot);
+    u32 before = x0 < n ? x0 - base : n - base;
+    u32 o0 = c0t + (pre & 0xFFFFu), o1 = c1t + (pre >> 16);
+    u32 o2 = c2t + (before - (pre & 0xFFFFu) - (pre >> 16));
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      if (cl[s] == 0) {
+        O0.k[o0] = kk[s];
+        O0.v[o0] = vv[s];
+        ++o0;
+      } else if (cl[s] == 1) {
+        O1.k[o1] = kk[s];
+        O1.v[o1] = vv[s];
+        ++o1;
+      } else if (cl[s] == 2) {
+        O2.k[o2] = kk[s];
+        O2.v[o2] = vv[s];
+        ++o2;
+      }
+    }
+    u32 tile = n - base < (u32)T::kNT * E ? n - base : (u32)T::kNT * E;
+    u32 t0 = tot & 0xFFFFu, t1 = tot >> 16;
+    c0t += t0;
+    c1t += t1;
+    c2t += tile - t0 - t1;
+  }
+  t.sync();
+  *n0 = c0t;
+  *n1 = c1t;
+  *n2 = c2t;
+}
+
+struct DigitId {
+  int s;
+  PBH_HD u32 operator()(u64, u32 v) const { return (v >> s) & 255u; }
+};
+struct DigitKey {
+  int s;
+  u64 lo;
+  PBH_HD u32 operator()(u64 k, u32) const { return (u32)((k - lo) >> s) & 255u; }
+};
+
+// One stable counting-sort pass on an 8-bit digit (LSD radix sort).  Ranks
+// among equal digits inside a wavefront come from ballots (peer masks), and
+// across wavefronts from per-wave digit counts in LDS.
+template <class T, class F>
+PBH_HD void radix_pass(T& t, Arr src, Arr dst, u32 n, F dig) {
+  for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
+  t.sync();
+  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) t.hist_add(t.sh->hist, dig(src.k[x], src.v[x]));
+  t.sync();
+  {
+    constexpr int BPT = (256 + T::kNT - 1) / T::kNT;
+    u32 b0 = (u32)t.tid() * BPT, loc = 0;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q)
+      if (b0 + q < 256) loc += t.sh->hist[b0 + q];
+    u32 tot;
+    u32 pre = t.scan_excl(loc, &tot);
+#pragma unroll
+    for (int q = 0; q < BPT; ++q)
+      if (b0 + q < 256) {
+        t.sh->base[b0 + q] = pre;
+        pre += t.sh->hist[b0 + q];
+      }
+  }
+  t.sync();
+  for (u32 tb = 0; tb < n; tb += (u32)T::kNT) {
+    u32 x = tb + (u32)t.tid();
+    bool valid = x < n;
+    u64 k = valid ? src.k[x] : 0;
+    u32 v = valid ? src.v[x] : 0;
+    u32 dg = valid ? dig(k, v) : 0;
+    u64 m = t.ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dg >> b) & 1u;
+      u64 bb = t.ballot(valid && bit);
+      m &= bit ? bb : ~bb;
+    }
+    u32 rank = (u32)__builtin_popcountll(m & t.lanemask_lt());
+    u32 cnt = (u32)__builtin_popcountll(m);
+    for (u32 z = (u32)t.tid(); z < (u32)T::kNW * 256; z += (u32)T::kNT) t.sh->wcnt[z >> 8][z & 255] = 0;
+    t.sync();
+    if (valid && rank == 0) t.sh->wcnt[t.wave()][dg] = cnt;
+    t.sync();
+    for (u32 gd = (u32)t.tid(); gd < 256; gd += (u32)T::kNT) {
+      u32 run = t.sh->base[gd];
+      for (int w = 0; w < T::kNW; ++w) {
+        u32 c = t.sh->wcnt[w][gd];
+        t.sh->wcnt[w][gd] = run;
+        run += c;
+      }
+      t.sh->base[gd] = run;
+    }
+    t.sync();
+    if (valid) {
+      u32 pos = t.sh->wcnt[t.wave()][dg] + rank;
+      dst.k[pos] = k;
+      dst.v[pos] = v;
+    }
+    t.sync();
+  }
+}
+
+// Sorts n elements by id (idbits significant bits).  Returns the buffer that
+// holds the result (a or tmp).
+template <class T>
+PBH_HD Arr sort_by_id(T& t, Arr a, Arr tmp, u32 n, int idbits) {
+  Arr src = a, dst = tmp;
+  for (int s = 0; s < idbits; s += 8) {
+    radix_pass(t, src, dst, n, DigitId{s});
+    Arr x = src;
+    src = dst;
+    dst = x;
+  }
+  return src;
+}
+
+// Sorts n elements by (key, id).
+template <class T>
+PBH_HD Arr sort_kv(T& t, Arr a, Arr tmp, u32 n, int idbits) {
+  Arr src = sort_by_id(t, a, tmp, n, idbits);
+  Arr dst = (src.k == a.k) ? tmp : a;
+  u64 lo = KINF, hi = 0;
+  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
+    u64 k = src.k[x];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  t.minmax64(lo, hi);
+  if (n == 0) return src;
+  u64 span = hi - lo;
+  int nb = span ? 64 - __builtin_clzll(span) : 0;
+  for (int s = 0; s < nb; s += 8) {
+    radix_pass(t, src, dst, n, DigitKey{s, lo});
+    Arr x = src;
+    src = dst;
+    dst = x;
+  }
+  return src;
+}
+
+template <class T>
+PBH_HD void copy_arr(T& t, Arr src, Arr dst, u32 n) {
+  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
+    dst.k[x] = src.k[x];
+    dst.v[x] = src.v[x];
+  }
+  t.sync();
+}
+
+// ---------------------------------------------------------------- the heap
+
+// Recomputes ell (deepest non-empty level) and sets p_j = +inf for j >= ell:
+// the deepest non-empty level has nothing below it to separate from.
+PBH_HD inline void fix_ell(HeapState* st, int q) {
+  int e = -1;
+  for (int j = q - 1; j >= 0; --j)
+    if (st->L[j].nB + st->L[j].nS) {
+      e = j;
+      break;
+    }
+  st->ell = e;
+  for (int j = e < 0 ? 0 : e; j < MAXL; ++j) {
+    st->L[j].pk = KINF;
+    st->L[j].pv = VINF;
+  }
+}
+
+// Algorithm 1, Resolve(i): empty S_i and fill B_i.
+//   EMPTY: B_i <- DeleteDuplicates(Merge(S_i, B_i)); if more than 2d*4^i
+//          elements are <= p_i, p_i <- Select(B_i, 2d*4^i); elements > p_i move
+//          to S_{i+1} <- Merge(S_{i+1}, B'_i).
+//   FILL (if |B_i| < 2d*4^i and i is not the deepest non-empty level):
+//          B_{i+1} <- DeleteDuplicates(Merge(B_{i+1}, S_{i+1}));
+//          p_i <- Select(B_{i+1}, 2d*4^i - |B_i|); elements <= p_i move up into
+//          B_i <- Merge(B_i, B'_{i+1}); elements > p_{i+1} go back to S_{i+1}.
+// Readings (documented with the others): EMPTY also runs when B_i holds more
+// than 2d*4^i elements with S_i empty (B_i can absorb elements of S_i during
+// FILL of level i-1); the new p_i in FILL never exceeds p_{i+1}, so nothing
+// deeper than level i+1 can be smaller than an element moved up; the two
+// splits at the end of FILL are one three-way split.
+template <class T>
+PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
+  Lvl a = st->L[i];
+  const bool nx = i + 1 < g.q;
+  Lvl b = nx ? st->L[i + 1] : Lvl{0, 0, 0, 0, KINF, VINF, 0};
+  int ell = st->ell;
+  KV pi{a.pk, a.pv}, pn{b.pk, b.pv};
+  const u32 cB = (u32)nomB(g.d, i);
+  u64 touched = 0;
+  int err = 0;
+  if (a.nS > 0 || a.nB > cB) {
+    Arr S = lbuf(g, i, 3 + a.ssel), B = lbuf(g, i, a.bsel), M = lbuf(g, i, a.bsel ^ 1);
+    if ((u64)a.nS + a.nB > capB(g.d, i)) {
+      err = E_INTERNAL;
+      goto done;
+    }
+    u32 m = merge_dedup(t, S, a.nS, B, a.nB, M, cur, false);
+    touched += 2ull * (a.nS + a.nB) + m;
+    a.bsel ^= 1;
+    a.nS = 0;
+    a.ssel = 0;
+    u32 num = count_le(t, M, m, pi);
+    if (num > cB) {
+      pi = select_kth(t, M, m, cB);
+      num = cB;
+      touched += m;
+    }
+    if (num < m) {
+      if (!nx) {
+        err = E_CAPACITY;
+        goto done;
+      }
+      Arr Lo = lbuf(g, i, a.bsel ^ 1), Hi = lbuf(g, i, 2);
+      u32 n0, n1, n2;
+      partition3(t, M, m, pi, kv_inf(), Lo, Hi, Arr{nullptr, nullptr}, &n0, &n1, &n2);
+      touched += 3ull * m;
+      a.bsel ^= 1;
+      a.nB = n0;
+      if ((u64)b.nS + n1 > capS(g.d, i + 1)) {
+        err = E_INTERNAL;
+        goto done;
+      }
+      Arr Sn = lbuf(g, i + 1, 3 + b.ssel), Sn2 = lbuf(g, i + 1, 3 + (b.ssel ^ 1));
+      u32 ms = merge_dedup(t, Sn, b.nS, Hi, n1, Sn2, cur, false);
+      touched += 2ull * (b.nS + n1) + ms;
+      b.ssel ^= 1;
+      b.nS = ms;
+      if (ell < i + 1) ell = i + 1;
+    } else {
+      a.nB = m;
+    }
+  }
+  if (a.nB < cB && i < ell && nx) {
+    Arr Bn = lbuf(g, i + 1, b.bsel), Sn = lbuf(g, i + 1, 3 + b.ssel), M2 = lbuf(g, i + 1, b.bsel ^ 1);
+    if ((u64)b.nB + b.nS > capB(g.d, i + 1)) {
+      err = E_INTERNAL;
+      goto done;
+    }
+    u32 m2 = merge_dedup(t, Bn, b.nB, Sn, b.nS, M2, cur, false);
+    touched += 2ull * (b.nB + b.nS) + m2;
+    b.nS = 0;
+    b.ssel = 0;
+    b.bsel ^= 1;
+    b.nB = m2;
+    if (m2 > 0) {
+      u32 r = cB - a.nB;
+      KV pnew = (r >= m2) ? kv_inf() : select_kth(t, M2, m2, r);
+      if (r < m2) touched += m2;
+      if (kv_less(pn, pnew)) pnew = pn;
+      Arr Up = lbuf(g, i, 2), Bk = lbuf(g, i + 1, b.bsel ^ 1), Sk = lbuf(g, i + 1, 3);
+      u32 nu, nb1, ns1;
+      partition3(t, M2, m2, pnew, pn, Up, Bk, Sk, &nu, &nb1, &ns1);
+      touched += 3ull * m2;
+      b.bsel ^= 1;
+      b.nB = nb1;
+      b.nS = ns1;
+      b.ssel = 0;
+      Arr Bi = lbuf(g, i, a.bsel), Bi2 = lbuf(g, i, a.bsel ^ 1);
+      u32 mb = merge_dedup(t, Bi, a.nB, Up, nu, Bi2, cur, i == 0 && cur != nullptr);
+      touched += 2ull * (a.nB + nu) + mb;
+      a.bsel ^= 1;
+      a.nB = mb;
+      pi = pnew;
+    }
+  }
+  a.cnt++;
+  a.pk = pi.k;
+  a.pv = pi.v;
+done:
+  t.sync();
+  if (t.tid() == 0) {
+    if (err) {
+      st->err = err;
+    } else {
+      st->L[i] = a;
+      if (nx) st->L[i + 1] = b;
+      st->elems += touched;
+      fix_ell(st, g.q);
+    }
+  }
+  t.sync();
+}
+
+// Can Resolve(j) move its worst case (all of S_j and B_j) into level j+1?
+PBH_HD inline bool room_below(const Geom& g, const HeapState* st, int j) {
+  if (j + 1 >= g.q) return true;
+  u64 push = (u64)st->L[j].nS + st->L[j].nB;
+  const Lvl& b = st->L[j + 1];
+  return (u64)b.nS + push <= capS(g.d, j + 1) && (u64)b.nB + b.nS + push <= capB(g.d, j + 1);
+}
+
+// Resolve(i), after first resolving the levels below that lack room for what
+// Resolve(i) may push down.  After Resolve(j), level j has S_j empty and
+// |B_j| <= 2d*4^j, which always leaves room for level j-1.
+template <class T>
+PBH_HD void resolve_safe(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
+  int j = i;
+  while (j + 1 < g.q && !room_below(g, st, j)) ++j;
+  for (int k = j; k > i && !st->err; --k) resolve(t, g, st, cur, k);
+  if (!st->err) resolve(t, g, st, cur, i);
+}
+
+// After every operation: Resolve(0), then the resolution schedule.
+//   sched 0 = Theorem 1: Resolve(i) after every fourth Resolve(i-1).
+//   sched 1 = on demand (as the sequential bucket heap does): Resolve(i+1)
+//             only when the next Resolve(i) would otherwise violate its
+//             preconditions on level i+1.
+template <class T>
+PBH_HD void after_op(T& t, const Geom& g, HeapState* st, const u64* cur, int sched) {
+  resolve_safe(t, g, st, cur, 0);
+  for (int i = 0; i + 1 < g.q && !st->err; ++i) {
+    if (i + 1 > st->ell) break;
+    bool go;
+    if (sched == 0) {
+      go = (st->L[i].cnt & 3u) == 0;
+    } else {
+      const Lvl& b = st->L[i + 1];
+      go = b.nS > nomS(g.d, i + 1) - nomS(g.d, i) ||
+           (i + 1 < st->ell && b.nB < nomS(g.d, i + 1) + nomS(g.d, i));
+    }
+    if (!go) break;
+    resolve_safe(t, g, st, cur, i + 1);
+  }
+}
+
+// Brings at least one element into B_0 if the heap is not empty (B_0 can run
+// dry when duplicates or dead copies thin out the levels below).
+template <class T>
+PBH_HD void ensure_b0(T& t, const Geom& g, HeapState* st, const u64* cur) {
+  for (int j = 1; st->L[0].nB == 0 && j <= st->ell && !st->err; ++j)
+    for (int k = j; k >= 0 && !st->err; --k) resolve_safe(t, g, st, cur, k);
+}
+
+// ---------------------------------------------------------------- parDijkstra
+struct SsspCounters {
+  u64 rounds, relax, updates;
+};
+
+PBH_HD inline int bits_for(u32 n) {
+  int b = 0;
+  while (b < 32 && ((u64)1 << b) < (u64)n) ++b;
+  return b < 1 ? 1 : b;
+}
+
+// U (relaxation output, n pairs in S) -> sorted by id with one pair per id.
+// With rows sorted by target the pairs already are strictly increasing in id
+// and nothing is done.  Otherwise each id keeps the pair whose key equals
+// dist[id] (the minimum, since dist was lowered by atomicMin) and the rest is
+// sorted by id.
+template <class T>
+PBH_HD u32 intake(T& t, Arr S, u32 n, Arr tmp, Arr tmp2, const u64* dist, int idbits) {
+  u32 bad = 0;
+  for (u32 x = (u32)t.tid() + 1; x < n; x += (u32)T::kNT) bad += S.v[x - 1] >= S.v[x];
+  bad = t.sum(bad);
+  if (bad == 0) return n;
+  u32 out = 0;
+  for (u32 base = 0; base < n; base += (u32)T::kNT) {
+    u32 x = base + (u32)t.tid();
+    bool keep = x < n && load_cur(t, dist + S.v[x]) == S.k[x];
+    u64 k = x < n ? S.k[x] : 0;
+    u32 v = x < n ? S.v[x] : 0;
+    u32 tot;
+    u32 o = out + t.scan_excl(keep ? 1u : 0u, &tot);
+    if (keep) {
+      tmp.k[o] = k;
+      tmp.v[o] = v;
+    }
+    out += tot;
+  }
+  t.sync();
+  Arr r = sort_by_id(t, tmp, tmp2, out, idbits);
+  copy_arr(t, r, S, out);
+  return out;
+}
+
+// parDijkstra (Section 4.1): each round extracts the minimum (key, id) from
+// B_0 -- B_0 holds only live elements, so this is the closest unsettled
+// vertex u -- relaxes all out-edges of u in parallel (atomicMin on dist),
+// compacts the improved (dist, v) pairs with a prefix sum straight into S_0
+// (BulkUpdate of at most d = max out-degree elements) and runs Resolve(0) and
+// the schedule.  The extraction and the bulk update of a round share one
+// Resolve(0): S_0 is empty and B_0 keeps at least d elements in between, so
+// Algorithm 1's preconditions hold.
+template <class T>
+PBH_HD void sssp_rounds(T& t, const Geom& g, HeapState* st, const u64* off, const u32* tg, const u32* wt,
+                        u64* dist, u32 n, u32 src, int sched, SsspCounters* cnt) {
+  const int idbits = bits_for(n);
+  if (t.tid() == 0) {
+    Arr S = lbuf(g, 0, 3);
+    S.k[0] = 0;
+    S.v[0] = src;
+    st->L[0].nS = 1;
+    st->L[0].ssel = 0;
+    st->ell = 0;
+  }
+  t.sync();
+  after_op(t, g, st, dist, sched);
+  u64 rounds = 0, relax = 0, upd = 1;
+  for (;;) {
+    ensure_b0(t, g, st, dist);
+    if (st->err) break;
+    const Lvl a0 = st->L[0];
+    if (a0.nB == 0) break;
+    // Every extraction consumes one insertion and every insertion comes from
+    // one scanned edge (or the source), so rounds <= 1 + relax always holds.
+    if (rounds > relax + 1) {
+      if (t.tid() == 0) st->err = E_INTERNAL;
+      t.sync();
+      break;
+    }
+    Arr B = lbuf(g, 0, a0.bsel);
+    u64 mk = KINF;
+    u32 mv = VINF;
+    for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) {
+      u64 k = B.k[x];
+      u32 v = B.v[x];
+      if (k < mk || (k == mk && v < mv)) {
+        mk = k;
+        mv = v;
+      }
+    }
+    t.minkv(mk, mv);
+    u32 n0, n1, n2;
+    partition3(t, B, a0.nB, KV{mk, mv}, kv_inf(), lbuf(g, 0, 2), lbuf(g, 0, a0.bsel ^ 1),
+               Arr{nullptr, nullptr}, &n0, &n1, &n2);
+    const u64 e0 = off[mv], e1 = off[mv + 1];
+    Arr S = lbuf(g, 0, 3);
+    u32 nu = 0;
+    for (u64 eb = e0; eb < e1; eb += (u64)T::kNT) {
+      u64 e = eb + (u64)t.tid();
+      bool imp = false;
+      u64 cand = 0;
+      u32 v = 0;
+      if (e < e1) {
+        v = tg[e];
+        cand = mk + (u64)wt[e];
+        imp = cand < t.atomic_min(dist + v, cand);
+      }
+      u32 tot;
+      u32 p = t.scan_excl(imp ? 1u : 0u, &tot);
+      if (imp) {
+        S.k[nu + p] = cand;
+        S.v[nu + p] = v;
+      }
+      nu += tot;
+    }
+    t.sync();
+    nu = intake(t, S, nu, lbuf(g, 0, 2), lbuf(g, 0, 4), dist, idbits);
+    if (t.tid() == 0) {
+      Lvl& L0 = st->L[0];
+      L0.bsel ^= 1;
+      L0.nB = n1;
+      L0.nS = nu;
+      L0.ssel = 0;
+      st->elems += 3ull * a0.nB + nu;
+      if (st->ell < 0 && (n1 + nu) > 0) st->ell = 0;
+    }
+    t.sync();
+    after_op(t, g, st, dist, sched);
+    ++rounds;
+    relax += e1 - e0;
+    upd += nu;
+  }
+  cnt->rounds = rounds;
+  cnt->relax = relax;
+  cnt->updates = upd;
+}
+
+// ---------------------------------------------------------------- pbh_* calls
+struct PbhParams {
+  Geom g;
+  HeapState* gst;  // heap state in device memory, loaded into LDS per kernel
+  u64* cur;        // current key of every id
+  u32* bitmap;     // one bit per id, all zero between calls
+  u32 nwords;
+  u32 id_cap;
+  int sched;
+  int idbits;
+  // bulk update
+  const u64* keys;
+  const u32* ids;
+  u64 count;
+  u64* ukeys;  // compacted update list
+  u32* uids;
+  // extract
+  u64 k;
+  u64* okeys;
+  u32* oids;
+};
+
+// Could the next operation push elements out of the deepest allocated level?
+// Then the caller adds a level first (growing the arena keeps the offsets of
+// the existing levels).
+PBH_HD inline bool need_grow(const Geom& g, const HeapState* st) {
+  const int q = g.q;
+  const Lvl& b = st->L[q - 1];
+  u64 have = (u64)b.nB + b.nS;
+  u64 in = (q == 1) ? (u64)g.d : capB(g.d, q - 2) + capS(g.d, q - 2);
+  return have + in > nomB(g.d, q - 1);
+}
+
+// BulkUpdate of one call.  First pass: cur[id] = min(cur[id], key) with
+// atomicMin (duplicates in the batch: the smallest key wins), ids whose key
+// dropped are marked in a bitmap; compacting the bitmap gives the changed ids
+// in increasing id order with their new keys, i.e. U sorted by value as
+// Section 2.2 requires.  Then pieces of at most d go into S_0, each followed
+// by Resolve(0) and the schedule.  Resumable: st->aux[0] = list length,
+// aux[1] = list built, aux[3] = stopped because a level must be added,
+// progress = list position reached.
+template <class T>
+PBH_HD void pbh_update_body(T& t, const Geom& g, HeapState* st, const PbhParams& p) {
+  if (st->aux[1] == 0) {
+    u32 newly = 0;
+    for (u64 x = (u64)t.tid(); x < p.count; x += (u64)T::kNT) {
+      u32 id = p.ids[x];
+      u64 k = p.keys[x];
+      u64 old = t.atomic_min(p.cur + id, k);
+      if (k < old) {
+        t.atomic_or32(p.bitmap + (id >> 5), 1u << (id & 31));
+        newly += (old == KINF);
+      }
+    }
+    newly = t.sum(newly);
+    t.fence();
+    t.sync();
+    u64 nu = 0;
+    for (u32 wb = 0; wb < p.nwords; wb += (u32)T::kNT) {
+      u32 w = wb + (u32)t.tid();
+      u32 bits = 0;
+      if (w < p.nwords) {
+        bits = t.load32(p.bitmap + w);
+        if (bits) p.bitmap[w] = 0u;
+      }
+      u32 tot;
+      u64 o = nu + t.scan_excl((u32)__builtin_popcount(bits), &tot);
+      while (bits) {
+        u32 b = (u32)__builtin_ctz(bits);
+        bits &= bits - 1;
+        u32 id = w * 32u + b;
+        p.uids[o] = id;
+        p.ukeys[o] = t.load_cur(p.cur + id);
+        ++o;
+      }
+      nu += tot;
+    }
+    t.sync();
+    if (t.tid() == 0) {
+      st->aux[0] = nu;
+      st->aux[1] = 1;
+      st->live += newly;
+      st->progress = 0;
+    }
+    t.sync();
+  }
+  const u64 nu = st->aux[0];
+  if (t.tid() == 0) st->aux[3] = 0;
+  t.sync();
+  for (u64 c0 = st->progress; c0 < nu;) {
+    if (need_grow(g, st)) {
+      if (t.tid() == 0) st->aux[3] = 1;
+      t.sync();
+      break;
+    }
+    u32 len = (u32)((nu - c0) < g.d ? (nu - c0) : g.d);
+    Arr S = lbuf(g, 0, 3);
+    for (u32 x = (u32)t.tid(); x < len; x += (u32)T::kNT) {
+      S.k[x] = p.ukeys[c0 + x];
+      S.v[x] = p.uids[c0 + x];
+    }
+    t.sync();
+    if (t.tid() == 0) {
+      st->L[0].nS = len;
+      st->L[0].ssel = 0;
+      if (st->ell < 0) st->ell = 0;
+      st->elems += 2ull * len;
+    }
+    t.sync();
+    after_op(t, g, st, p.cur, p.sched);
+    if (st->err) break;
+    c0 += len;
+    if (t.tid() == 0) st->progress = c0;
+    t.sync();
+  }
+}
+
+// Batched ExtractMin of one call: repeatedly take the smallest min(k_left,
+// |B_0|) elements of B_0 (B_0 <= p_0 < everything else, and B_0 holds only
+// live elements), output them sorted by (key, id), mark their ids absent, then
+// Resolve(0) and the schedule.  Resumable: progress = elements written,
+// aux[3] = stopped for growth, aux[4] = heap ran empty.
+template <class T>
+PBH_HD void pbh_extract_body(T& t, const Geom& g, HeapState* st, const PbhParams& p) {
+  if (t.tid() == 0) {
+    st->aux[3] = 0;
+    st->aux[4] = 0;
+  }
+  t.sync();
+  for (;;) {
+    const u64 outpos = st->progress;
+    if (outpos >= p.k) break;
+    if (need_grow(g, st)) {
+      if (t.tid() == 0) st->aux[3] = 1;
+      t.sync();
+      break;
+    }
+    ensure_b0(t, g, st, p.cur);
+    if (st->err) break;
+    const Lvl a0 = st->L[0];
+    if (a0.nB == 0) {
+      if (t.tid() == 0) st->aux[4] = 1;
+      t.sync();
+      break;
+    }
+    u32 take = (u32)((p.k - outpos) < a0.nB ? (p.k - outpos) : a0.nB);
+    Arr B = lbuf(g, 0, a0.bsel);
+    KV thr = (take == a0.nB) ? kv_inf() : select_kth(t, B, a0.nB, take);
+    u32 n0, n1, n2;
+    Arr X = lbuf(g, 0, 2);
+    partition3(t, B, a0.nB, thr, kv_inf(), X, lbuf(g, 0, a0.bsel ^ 1), Arr{nullptr, nullptr}, &n0, &n1, &n2);
+    Arr R = sort_kv(t, X, B, take, p.idbits);
+    for (u32 x = (u32)t.tid(); x < take; x += (u32)T::kNT) {
+      u32 id = R.v[x];
+      p.okeys[outpos + x] = R.k[x];
+      p.oids[outpos + x] = id;
+      t.store_cur(p.cur + id, KINF);
+    }
+    t.fence();
+    t.sync();
+    if (t.tid() == 0) {
+      st->L[0].bsel ^= 1;
+      st->L[0].nB = n1;
+      st->live -= take;
+      st->progress = outpos + take;
+      st->elems += 6ull * a0.nB;
+    }
+    t.sync();
+    after_op(t, g, st, p.cur, p.sched);
+    if (st->err) break;
+  }
+}
+
+}  // namespace bkt

@@ -1,0 +1,44 @@
+// Host-side interface between the C ABI (abi.hip) and the kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pbh_core.h"
+
+namespace bkt {
+
+// Device statistics block written by the SSSP kernel.
+struct SsspDevStats {
+  u64 rounds, relax, updates, elems;
+  long long err;
+  long long ell;
+  u64 resolves[MAXL];
+};
+
+struct SsspParams {
+  const u64* off;
+  const u32* tg;
+  const u32* wt;
+  u64* dist;
+  u32 n;
+  u32 src;
+  int sched;
+  Geom g;  // lk/lv are set inside the kernel
+  SsspDevStats* stats;
+};
+
+
+struct CsrCheck {
+  u64 bad;        // any malformed entry
+  u64 maxdeg;
+};
+
+hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s);
+hipError_t launch_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out, hipStream_t s);
+hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s);
+size_t sssp_static_lds(int team);
+hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s);
+hipError_t launch_pbh_extract(const PbhParams& p, hipStream_t s);
+hipError_t launch_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad,
+                               hipStream_t s);
+
+}  // namespace bkt

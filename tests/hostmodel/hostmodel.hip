@@ -1,0 +1,202 @@
+// CPU driver for the heap and parDijkstra logic of the GPU kernels, for tests.
+//
+// It instantiates the same team-templated code as kernels.hip with a
+// one-thread team on host memory, so that CPU tests can run adversarial
+// operation scripts through the exact schedule, capacity and growth logic.
+// It is not part of the library and the library never calls it; results from
+// here are checked against the oracle like any other implementation.
+#include <cstring>
+#include <vector>
+
+#include "../../paper_1908_09378_amd/csrc/pbh_core.h"
+
+using namespace bkt;
+
+namespace {
+
+int levels_for(u32 d, u64 elems, int qmin) {
+  int q = qmin;
+  while (q < MAXL && nomB(d, q - 1) < elems) ++q;
+  return q;
+}
+
+int ceil_log2(u64 x) {
+  int b = 0;
+  while (b < 63 && (1ull << b) < x) ++b;
+  return b < 1 ? 1 : b;
+}
+
+struct HM {
+  u32 id_cap, d;
+  int q, sched;
+  std::vector<u64> cur, ak, uk;
+  std::vector<u32> bitmap, av, ui;
+  HeapState st;
+  TeamShared<1> ts;
+};
+
+Geom geom(HM* h) {
+  Geom g;
+  g.d = h->d;
+  g.q = h->q;
+  g.qlds = 0;
+  g.gk = h->ak.data();
+  g.gv = h->av.data();
+  g.lk = nullptr;
+  g.lv = nullptr;
+  return g;
+}
+
+void grow(HM* h) {
+  h->q += 1;
+  h->st.q = h->q;
+  h->ak.resize(lvl_off(h->d, h->q));
+  h->av.resize(lvl_off(h->d, h->q));
+}
+
+}  // namespace
+
+extern "C" {
+
+void* hm_create(u32 id_cap, u32 d, int sched) {
+  HM* h = new HM;
+  h->id_cap = id_cap;
+  h->d = d;
+  h->sched = sched;
+  h->q = levels_for(d, id_cap, 1);
+  h->cur.assign(id_cap, KINF);
+  h->bitmap.assign((id_cap + 31) / 32, 0u);
+  h->ak.resize(lvl_off(d, h->q));
+  h->av.resize(lvl_off(d, h->q));
+  state_init(&h->st, d, h->q);
+  return h;
+}
+
+void hm_destroy(void* p) { delete static_cast<HM*>(p); }
+
+int hm_update(void* hp, const u64* keys, const u32* ids, u64 count) {
+  HM* h = static_cast<HM*>(hp);
+  for (u64 i = 0; i < count; ++i)
+    if (ids[i] >= h->id_cap || keys[i] == KINF) return -1;
+  if (count == 0) return 0;
+  u64 need = count < h->id_cap ? count : h->id_cap;
+  h->uk.resize(need);
+  h->ui.resize(need);
+  h->st.aux[0] = h->st.aux[1] = h->st.aux[3] = 0;
+  h->st.progress = 0;
+  for (;;) {
+    PbhParams p{};
+    p.g = geom(h);
+    p.cur = h->cur.data();
+    p.bitmap = h->bitmap.data();
+    p.nwords = (u32)h->bitmap.size();
+    p.id_cap = h->id_cap;
+    p.sched = h->sched;
+    p.idbits = ceil_log2(h->id_cap);
+    p.keys = keys;
+    p.ids = ids;
+    p.count = count;
+    p.ukeys = h->uk.data();
+    p.uids = h->ui.data();
+    HostTeam t{&h->ts};
+    pbh_update_body(t, p.g, &h->st, p);
+    if (h->st.err) return h->st.err;
+    if (h->st.aux[3] == 0) return 0;
+    if (h->q >= MAXL) return -2;
+    grow(h);
+  }
+}
+
+int hm_extract(void* hp, u64 k, u64* ko, u32* io, u64* count) {
+  HM* h = static_cast<HM*>(hp);
+  h->st.progress = 0;
+  *count = 0;
+  if (k == 0) return 0;
+  for (;;) {
+    PbhParams p{};
+    p.g = geom(h);
+    p.cur = h->cur.data();
+    p.id_cap = h->id_cap;
+    p.sched = h->sched;
+    p.idbits = ceil_log2(h->id_cap);
+    p.k = k;
+    p.okeys = ko;
+    p.oids = io;
+    HostTeam t{&h->ts};
+    pbh_extract_body(t, p.g, &h->st, p);
+    if (h->st.err) return h->st.err;
+    if (h->st.aux[3] == 0) break;
+    if (h->q >= MAXL) return -2;
+    grow(h);
+  }
+  *count = h->st.progress;
+  return 0;
+}
+
+int hm_levels(void* hp, u32* q, int* ell, u32* nB, u32* nS, u64* pk, u32* pv, u64* cnt, u64* live) {
+  HM* h = static_cast<HM*>(hp);
+  *q = (u32)h->q;
+  *ell = h->st.ell;
+  *live = h->st.live;
+  for (int i = 0; i < h->q; ++i) {
+    nB[i] = h->st.L[i].nB;
+    nS[i] = h->st.L[i].nS;
+    pk[i] = h->st.L[i].pk;
+    pv[i] = h->st.L[i].pv;
+    cnt[i] = h->st.L[i].cnt;
+  }
+  return 0;
+}
+
+// Dumps level i's B and S contents (for invariant checks).
+int hm_level_items(void* hp, int i, u64* bk, u32* bv, u64* sk, u32* sv) {
+  HM* h = static_cast<HM*>(hp);
+  Geom g = geom(h);
+  const Lvl& L = h->st.L[i];
+  Arr B = lbuf(g, i, L.bsel), S = lbuf(g, i, 3 + L.ssel);
+  std::memcpy(bk, B.k, L.nB * 8);
+  std::memcpy(bv, B.v, L.nB * 4);
+  std::memcpy(sk, S.k, L.nS * 8);
+  std::memcpy(sv, S.v, L.nS * 4);
+  return 0;
+}
+
+// parDijkstra with the kernel's round loop.  qlds levels are placed in a
+// separate buffer, standing in for LDS.  stats: rounds, relaxations, updates,
+// heap element touches, levels, resolves[0..15].
+int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src, u64* dist, u32 d_opt,
+            int sched, u64 hcap, int qlds, u64* stats) {
+  u64 md = 0;
+  for (u32 u = 0; u < n; ++u) md = off[u + 1] - off[u] > md ? off[u + 1] - off[u] : md;
+  u32 d = d_opt ? d_opt : (u32)(md ? md : 1);
+  if (hcap == 0) hcap = m + 1;
+  int q = levels_for(d, hcap, 2);
+  if (qlds > q) qlds = q;
+  std::vector<u64> gk(lvl_off(d, q) - lvl_off(d, qlds)), lk(lvl_off(d, qlds));
+  std::vector<u32> gv(gk.size()), lv(lk.size());
+  Geom g;
+  g.d = d;
+  g.q = q;
+  g.qlds = qlds;
+  g.gk = gk.data();
+  g.gv = gv.data();
+  g.lk = lk.data();
+  g.lv = lv.data();
+  HeapState st;
+  state_init(&st, d, q);
+  TeamShared<1> ts;
+  HostTeam t{&ts};
+  for (u32 v = 0; v < n; ++v) dist[v] = KINF;
+  dist[src] = 0;
+  SsspCounters c;
+  sssp_rounds(t, g, &st, off, tg, wt, dist, n, src, sched, &c);
+  stats[0] = c.rounds;
+  stats[1] = c.relax;
+  stats[2] = c.updates;
+  stats[3] = st.elems;
+  stats[4] = (u64)q;
+  for (int i = 0; i < MAXL; ++i) stats[5 + i] = st.L[i].cnt;
+  return st.err;
+}
+
+}  // extern "C"

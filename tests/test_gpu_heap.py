@@ -1,0 +1,101 @@
+"""GPU parity of the parallel bucket heap (pbh_* through the C ABI) with the
+sorted-multiset oracle: every extracted (key, id) sequence bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1908_09378_amd as pkg
+import workloads as W
+from gpu_util import DEV, dev32, dev64, host32, host64
+
+pytestmark = pytest.mark.gpu
+INF = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _script(cap, d, ops):
+    h = pkg.Heap(cap, d)
+    o = oracle.PQ(cap)
+    kmax = max([op[1] for op in ops if op[0] == "extract"] + [1])
+    ko = torch.empty(kmax, dtype=torch.int64, device=DEV)
+    io = torch.empty(kmax, dtype=torch.int32, device=DEV)
+    for op in ops:
+        if op[0] == "update":
+            h.bulk_update(dev64(op[1]), dev32(op[2]))
+            o.bulk_update(op[1], op[2])
+        else:
+            n = h.extract_min(op[1], ko, io)
+            ek, ei = o.extract_min(op[1])
+            assert n == ek.shape[0]
+            assert np.array_equal(host64(ko[:n]), ek) and np.array_equal(host32(io[:n]), ei)
+        assert h.size() == o.size()
+    return h
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_scripts(seed):
+    d = [1, 3, 8, 32, 100][seed % 5]
+    cap = [7, 100, 2000][seed % 3]
+    print(f"[heap] script seed={seed} d={d} cap={cap}", flush=True)
+    _script(cap, d, W.random_script(50, cap, [d, 4 * d][seed % 2], [5, 10 ** 12][seed % 2], 900 + seed))
+
+
+def test_worked_example():
+    import json, os
+    ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pq_worked_example.json")))
+    ops = []
+    for st in ex["steps"]:
+        if st["op"] == "update":
+            p = np.array(st["pairs"], dtype=np.uint64).reshape(-1, 2)
+            ops.append(("update", p[:, 0].copy(), p[:, 1].astype(np.uint32)))
+        else:
+            ops.append(("extract", st["k"]))
+    _script(ex["id_capacity"], 2, ops)
+
+
+def test_invariants_after_ops():
+    h = _script(500, 4, W.random_script(40, 500, 30, 1000, 77))
+    L = h.debug_levels()
+    assert L["nS"][0] == 0
+    for i in range(L["q"]):
+        assert L["nB"][i] <= 4 * 4 * 4 ** i and L["nS"][i] <= 2 * 4 * 4 ** i
+
+
+def test_decrease_key_workload_reduced():
+    """The standalone-heap workload at reduced scale: 2^18 ids loaded in pieces
+    of d = 2^14, then rounds of 2^14 decrease-keys on live ids (new = old -
+    uniform[0, old/2]) and extracts of 2^10."""
+    n_ids, d, rounds, ext = 1 << 18, 1 << 14, 16, 1 << 10
+    keys, ids = W.heap_init_pairs(n_ids, seed=3)
+    h = pkg.Heap(n_ids, d)
+    o = oracle.PQArrays(n_ids)
+    for c in range(0, n_ids, d):
+        h.bulk_update(dev64(keys[c:c + d]), dev32(ids[c:c + d]))
+    o.bulk_update(keys, ids)
+    ko = torch.empty(ext, dtype=torch.int64, device=DEV)
+    io = torch.empty(ext, dtype=torch.int32, device=DEV)
+    for r in range(rounds):
+        live = np.nonzero(o.cur != INF)[0].astype(np.uint32)
+        bk, bi = W.decrease_batch(live, lambda x: o.cur[x], d, 3, r)
+        h.bulk_update(dev64(bk), dev32(bi))
+        o.bulk_update(bk, bi)
+        n = h.extract_min(ext, ko, io)
+        ek, ei = o.extract_min(ext)
+        assert n == ext
+        assert np.array_equal(host64(ko[:n]), ek) and np.array_equal(host32(io[:n]), ei)
+    assert h.size() == o.size()
+
+
+def test_invalid_updates_change_nothing():
+    h = pkg.Heap(10, 2)
+    h.bulk_update(dev64(np.array([5], np.uint64)), dev32(np.array([3], np.uint32)))
+    with pytest.raises(pkg.PBHError) as e:
+        h.bulk_update(dev64(np.array([1, 2], np.uint64)), dev32(np.array([1, 10], np.uint32)))
+    assert e.value.code == pkg.PBH_EINVAL
+    with pytest.raises(pkg.PBHError):
+        h.bulk_update(dev64(np.array([INF], np.uint64)), dev32(np.array([1], np.uint32)))
+    ko = torch.empty(5, dtype=torch.int64, device=DEV)
+    io = torch.empty(5, dtype=torch.int32, device=DEV)
+    assert h.extract_min(5, ko, io) == 1
+    assert host64(ko[:1])[0] == 5 and host32(io[:1])[0] == 3
+    assert h.extract_min(5, ko, io) == 0

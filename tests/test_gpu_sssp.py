@@ -1,0 +1,104 @@
+"""GPU parity of parDijkstra (sssp through the C ABI) with the oracle:
+distances bit-exact, element by element, and the plain-rule round and
+relaxation counts (one round per settled vertex, every out-edge of a settled
+vertex scanned once)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1908_09378_amd as pkg
+import workloads as W
+from gpu_util import run_sssp
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(g, src, **kw):
+    print(f"[sssp] {g.name} n={g.n} m={g.m} src={src} {kw}", flush=True)
+    ref, order, nrelax = oracle.dijkstra(g, src, want_order=True)
+    got, st = run_sssp(pkg, g, src, **kw)
+    assert np.array_equal(got, ref), f"{int((got != ref).sum())} distances differ"
+    if st is not None:
+        assert st["rounds"] == order.shape[0]
+        assert st["relaxations"] == nrelax
+    return st
+
+
+def test_grid_64x64_weights_1_100():
+    _check(W.grid4(64, 64, 1, 100, seed=1), 0)
+
+
+@pytest.mark.parametrize("team", [64, 256, 1024])
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_grid_teams_and_schedules(team, schedule):
+    _check(W.grid4(64, 64, 1, 100, seed=1), 0, team=team, schedule=schedule)
+
+
+@pytest.mark.parametrize("lds", [0, 1, 2, 0xFFFFFFFF])
+def test_ring_lds_levels(lds):
+    _check(W.ring_lattice(1 << 12, 16, 1, 1000, seed=2), 5, lds_levels=lds)
+
+
+def test_small_heap_capacity_retries_exactly():
+    _check(W.ring_lattice(1 << 12, 16, 1, 1000, seed=2), 0, heap_capacity=64)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_multigraphs_zero_weights_selfloops(seed):
+    n = [1, 2, 17, 300, 1000, 5000][seed % 6]
+    m = [0, 3, 50, 4000, 20000, 60000][seed % 6]
+    wl, wh = [(0, 0), (0, 3), (1, 1000)][seed % 3]
+    g = W.random_graph(n, m, wl, wh, 70 + seed)
+    _check(g, seed % n, team=[64, 256, 1024][seed % 3])
+
+
+def test_unreachable_and_isolated():
+    g = W.path_graph(200, seed=3)
+    _check(g, 100)   # vertices 0..99 unreachable
+
+
+def test_grid8_loguniform():
+    _check(W.grid8(128, 128, wmax=10000, seed=4), 0)
+
+
+def test_unit_weights_many_ties():
+    _check(W.grid4(100, 100, 1, 1, seed=5), 0)
+    _check(W.ring_lattice(1 << 13, 16, 1, 1, seed=5), 0)
+
+
+def test_rgg():
+    _check(W.rgg(1 << 14, seed=6), 3)
+
+
+def test_paper_dag_high_degree():
+    n = 3000
+    g = W.paper_dag(n, 400000, seed=7)
+    st = _check(g, 0)
+
+
+def test_ring_lattice_full_size():
+    """The full-size ring lattice: n = 2^20, 16 neighbours per side,
+    weights uniform in [1, 1000], source 0 -- every distance compared."""
+    g = W.ring_lattice(1 << 20, 16, 1, 1000, seed=2)
+    st = _check(g, 0, team=64)
+    print(f"[sssp] ring 2^20: {st['kernel_ms']:.1f} ms, rounds {st['rounds']}", flush=True)
+
+
+def test_invalid_inputs():
+    import torch
+    from gpu_util import DEV, dev32, dev64
+    g = W.grid4(4, 4)
+    off, tg, wt = dev64(g.offsets), dev32(g.targets), dev32(g.weights)
+    dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+    with pytest.raises(pkg.PBHError) as e:
+        pkg.sssp(off, tg, wt, g.n, g.m, g.n, dist)
+    assert e.value.code == pkg.PBH_EINVAL
+    bad = g.targets.copy()
+    bad[3] = 999
+    with pytest.raises(pkg.PBHError) as e:
+        pkg.sssp(off, dev32(bad), wt, g.n, g.m, 0, dist)
+    assert e.value.code == pkg.PBH_EINVAL
+    badoff = g.offsets.copy()
+    badoff[2], badoff[3] = badoff[3], badoff[2]
+    with pytest.raises(pkg.PBHError):
+        pkg.sssp(dev64(badoff), tg, wt, g.n, g.m, 0, dist)
