@@ -13,6 +13,13 @@
 
 namespace bkt {
 
+// GPU placement of the heap: LDS levels, HBM levels and the state in LDS.
+struct DevPolicy {
+  using L = ArrT<u64 PBH_LDS*, u32 PBH_LDS*>;
+  using G = ArrT<u64 PBH_GLB*, u32 PBH_GLB*>;
+  using SP = HeapState PBH_LDS*;
+};
+
 __global__ void k_fill_dist(u64* dist, u32 n, u32 src) {
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
     dist[i] = (i == src) ? 0ull : KINF;
@@ -46,41 +53,42 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ TeamShared<NT / 64> ts;
-  __shared__ HeapState st;
-  DevTeam<NT> t{&ts};
+  __shared__ HeapState st_lds;
+  HeapState PBH_LDS* st = (HeapState PBH_LDS*)&st_lds;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
   Geom g = p.g;
   const u64 nl = lvl_off(g.d, g.qlds);
   g.lk = reinterpret_cast<u64*>(dyn);
   g.lv = reinterpret_cast<u32*>(dyn + nl * sizeof(u64));
-  if (threadIdx.x == 0) state_init(&st, g.d, g.q);
+  if (threadIdx.x == 0) state_init(st, g.d, g.q);
   t.sync();
   SsspCounters c;
-  sssp_rounds(t, g, &st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, &c);
+  sssp_rounds<DevTeam<NT>, DevPolicy>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, &c);
   t.sync();
   if (threadIdx.x == 0) {
     SsspDevStats* o = p.stats;
     o->rounds = c.rounds;
     o->relax = c.relax;
     o->updates = c.updates;
-    o->elems = st.elems;
-    o->err = st.err;
-    o->ell = st.ell;
-    for (int i = 0; i < MAXL; ++i) o->resolves[i] = st.L[i].cnt;
+    o->elems = st->elems;
+    o->err = st->err;
+    o->ell = st->ell;
+    for (int i = 0; i < MAXL; ++i) o->resolves[i] = st->L[i].cnt;
   }
 }
 
 template <int NT>
-__device__ void load_state(DevTeam<NT>& t, HeapState* st, const HeapState* gst) {
+__device__ void load_state(DevTeam<NT>& t, HeapState PBH_LDS* st, const HeapState* gst) {
   const u32* s = reinterpret_cast<const u32*>(gst);
-  u32* d = reinterpret_cast<u32*>(st);
+  u32 PBH_LDS* d = reinterpret_cast<u32 PBH_LDS*>(st);
   for (u32 i = threadIdx.x; i < sizeof(HeapState) / 4; i += NT) d[i] = s[i];
   t.sync();
 }
 
 template <int NT>
-__device__ void store_state(DevTeam<NT>& t, const HeapState* st, HeapState* gst) {
+__device__ void store_state(DevTeam<NT>& t, const HeapState PBH_LDS* st, HeapState* gst) {
   t.sync();
-  const u32* s = reinterpret_cast<const u32*>(st);
+  const u32 PBH_LDS* s = reinterpret_cast<const u32 PBH_LDS*>(st);
   u32* d = reinterpret_cast<u32*>(gst);
   for (u32 i = threadIdx.x; i < sizeof(HeapState) / 4; i += NT) d[i] = s[i];
 }
@@ -88,21 +96,23 @@ __device__ void store_state(DevTeam<NT>& t, const HeapState* st, HeapState* gst)
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pbh_update(PbhParams p) {
   __shared__ TeamShared<NT / 64> ts;
-  __shared__ HeapState st;
-  DevTeam<NT> t{&ts};
-  load_state(t, &st, p.gst);
-  pbh_update_body(t, p.g, &st, p);
-  store_state(t, &st, p.gst);
+  __shared__ HeapState st_lds;
+  HeapState PBH_LDS* st = (HeapState PBH_LDS*)&st_lds;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  load_state(t, st, p.gst);
+  pbh_update_body<DevTeam<NT>, DevPolicy>(t, p.g, st, p);
+  store_state(t, st, p.gst);
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_pbh_extract(PbhParams p) {
   __shared__ TeamShared<NT / 64> ts;
-  __shared__ HeapState st;
-  DevTeam<NT> t{&ts};
-  load_state(t, &st, p.gst);
-  pbh_extract_body(t, p.g, &st, p);
-  store_state(t, &st, p.gst);
+  __shared__ HeapState st_lds;
+  HeapState PBH_LDS* st = (HeapState PBH_LDS*)&st_lds;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  load_state(t, st, p.gst);
+  pbh_extract_body<DevTeam<NT>, DevPolicy>(t, p.g, st, p);
+  store_state(t, st, p.gst);
 }
 
 static int grid_for(u64 work, int block) {

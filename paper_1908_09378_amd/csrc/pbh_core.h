@@ -12,6 +12,8 @@
 #include "pbh_team.h"
 
 #define PBH_HD __host__ __device__
+#define PBH_INL __host__ __device__ __forceinline__
+#define PBH_NOINL __host__ __device__ __attribute__((noinline))
 
 namespace bkt {
 
@@ -29,10 +31,23 @@ PBH_HD inline bool kv_less(KV a, KV b) { return a.k < b.k || (a.k == b.k && a.v 
 PBH_HD inline bool kv_le(KV a, KV b) { return !kv_less(b, a); }
 PBH_HD inline KV kv_inf() { return KV{KINF, VINF}; }
 
-struct Arr {
-  u64* k;
-  u32* v;
+// A view of an element array: keys and ids.  The pointer types carry the
+// address space on the GPU (LDS levels -> ds_* instructions, HBM levels ->
+// global_* instructions); the geometry hands out generic views (Arr) that are
+// cast to the typed view of the level's placement.
+template <class KP, class VP>
+struct ArrT {
+  KP k;
+  VP v;
 };
+using Arr = ArrT<u64*, u32*>;
+template <class A>
+PBH_INL A as_arr(Arr a) {
+  A r;
+  r.k = (decltype(r.k))a.k;
+  r.v = (decltype(r.v))a.v;
+  return r;
+}
 
 // ---------------------------------------------------------------- geometry
 // Nominal sizes from Section 2.2, and the allocated buffer sizes.  A level
@@ -91,7 +106,8 @@ struct HeapState {
   u64 aux[5];
 };
 
-PBH_HD inline void state_init(HeapState* st, u32 d, int q) {
+template <class SP>
+PBH_HD inline void state_init(SP st, u32 d, int q) {
   for (int i = 0; i < MAXL; ++i) {
     st->L[i].nB = st->L[i].nS = st->L[i].bsel = st->L[i].ssel = st->L[i].cnt = 0;
     st->L[i].pk = KINF;
@@ -105,18 +121,46 @@ PBH_HD inline void state_init(HeapState* st, u32 d, int q) {
   for (int i = 0; i < 5; ++i) st->aux[i] = 0;
 }
 
-// Reads of cur[] (the current key of each id; dist[] in SSSP) must observe
-// atomicMin updates made at L2 by the same team, so they are coherent loads.
-template <class T>
-PBH_HD inline u64 load_cur(const T& t, const u64* p) {
-  return t.load_cur(p);
+// Field-wise copies of a level's state (the state may live in LDS, whose
+// objects have no implicit copy into generic memory).
+template <class SP>
+PBH_INL Lvl lvl_load(SP st, int i) {
+  Lvl a;
+  a.nB = st->L[i].nB;
+  a.nS = st->L[i].nS;
+  a.bsel = st->L[i].bsel;
+  a.ssel = st->L[i].ssel;
+  a.pk = st->L[i].pk;
+  a.pv = st->L[i].pv;
+  a.cnt = st->L[i].cnt;
+  return a;
 }
+template <class SP>
+PBH_INL void lvl_store(SP st, int i, const Lvl& a) {
+  st->L[i].nB = a.nB;
+  st->L[i].nS = a.nS;
+  st->L[i].bsel = a.bsel;
+  st->L[i].ssel = a.ssel;
+  st->L[i].pk = a.pk;
+  st->L[i].pv = a.pv;
+  st->L[i].cnt = a.cnt;
+}
+
+// Host-side policy: every array and the state live in ordinary memory.  The
+// GPU policy (kernels.hip) types LDS levels, HBM levels and the state with
+// their address spaces.
+struct HostPolicy {
+  using L = Arr;
+  using G = Arr;
+  using SP = HeapState*;
+};
 
 // ---------------------------------------------------------------- primitives
 
 // Merge-path split (Green, McColl, Bader 2012): how many of the first `diag`
 // elements of merge(A, B) by id come from A (A first on equal ids).
-PBH_HD inline u32 merge_path(const u32* av, u32 na, const u32* bv, u32 nb, u32 diag) {
+template <class VA, class VB>
+PBH_INL u32 merge_path(VA av, u32 na, VB bv, u32 nb, u32 diag) {
   u32 lo = diag > nb ? diag - nb : 0u, hi = diag < na ? diag : na;
   while (lo < hi) {
     u32 mid = (lo + hi) >> 1;
@@ -136,8 +180,10 @@ PBH_HD inline u32 merge_path(const u32* av, u32 na, const u32* bv, u32 nb, u32 d
 // (Section 2.1: duplicates keep the smaller priority).  With filterB, B
 // elements that are not live are dropped as well (used when elements move up
 // into B_0, so that B_0 holds only live elements).
-template <class T, int E = 4>
-PBH_HD u32 merge_dedup(T& t, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, bool filterB) {
+enum { PREFER_LIVE = 0, PREFER_A = 1, PREFER_B = 2 };
+
+template <class T, int E, class AA, class AB, class AC>
+PBH_INL u32 merge_dedup_e(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64* cur, bool filterB, int prefer) {
   const u32 total = na + nb;
   u32 out = 0;
   for (u32 base = 0; base < total; base += (u32)T::kNT * E) {
@@ -160,9 +206,12 @@ PBH_HD u32 merge_dedup(T& t, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur
           bool kp = true;
           if (j < nb && B.v[j] == va) {
             u64 kb = B.k[j];
-            if (kb != ka) {
+            if (prefer == PREFER_B) {
+              ka = kb;
+            } else if (prefer == PREFER_A) {
+            } else if (kb != ka) {
               if (cur) {
-                u64 c = load_cur(t, cur + va);
+                u64 c = t.load_cur(cur + va);
                 if (ka == c) {
                 } else if (kb == c) {
                   ka = kb;
@@ -182,7 +231,7 @@ PBH_HD u32 merge_dedup(T& t, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur
           u64 kb = B.k[j];
           u32 vb = B.v[j];
           bool kp = !(i > 0 && A.v[i - 1] == vb);
-          if (kp && filterB && load_cur(t, cur + vb) != kb) kp = false;
+          if (kp && filterB && t.load_cur(cur + vb) != kb) kp = false;
           ko[s] = kb;
           vo[s] = vb;
           keep |= (u32)kp << s;
@@ -205,9 +254,20 @@ PBH_HD u32 merge_dedup(T& t, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur
   return out;
 }
 
+// Merge with the per-thread walk length chosen by size: a long walk amortises
+// the merge-path search on big arrays, a short one keeps the chain of
+// dependent reads short on the small top levels.
+template <class T, class AA, class AB, class AC>
+PBH_INL u32 merge_dedup(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64* cur, bool filterB,
+                        int prefer = PREFER_LIVE) {
+  if (T::kE > 2 && na + nb <= 2u * (u32)T::kNT)
+    return merge_dedup_e<T, 2>(t, A, na, B, nb, C, cur, filterB, prefer);
+  return merge_dedup_e<T, T::kE>(t, A, na, B, nb, C, cur, filterB, prefer);
+}
+
 // |{e in A : e <= p}|
-template <class T>
-PBH_HD u32 count_le(T& t, Arr A, u32 n, KV p) {
+template <class T, class AA>
+PBH_INL u32 count_le(const T& t, AA A, u32 n, KV p) {
   if (p.k == KINF) return n;
   u32 c = 0;
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) c += kv_le(KV{A.k[x], A.v[x]}, p) ? 1u : 0u;
@@ -216,7 +276,7 @@ PBH_HD u32 count_le(T& t, Arr A, u32 n, KV p) {
 
 // Finds the histogram bin where the r-th element (1-based) falls.
 template <class T>
-PBH_HD void hist_pick(T& t, u32 r, u32* D, u32* below, u32* cnt) {
+PBH_INL void hist_pick(const T& t, u32 r, u32* D, u32* below, u32* cnt) {
   constexpr int BPT = (256 + T::kNT - 1) / T::kNT;
   u32 b0 = (u32)t.tid() * BPT;
   u32 loc = 0;
@@ -245,13 +305,56 @@ PBH_HD void hist_pick(T& t, u32 r, u32* D, u32* below, u32* cnt) {
   t.sync();
 }
 
+// r-th smallest by repeated team minima (or the (n-r+1)-th largest by
+// repeated maxima) over at most 8 elements per thread held in registers; for
+// the small ranks that Resolve asks for when one element leaves B_0.
+template <class T, class AA>
+PBH_INL KV select_small(const T& t, AA A, u32 n, u32 r) {
+  const bool top = (n - r + 1) < r;
+  u32 it = top ? n - r + 1 : r;
+  u64 kk[8];
+  u32 vv[8];
+  u32 live = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    u32 x = (u32)t.tid() + (u32)j * (u32)T::kNT;
+    kk[j] = 0;
+    vv[j] = 0;
+    if (x < n) {
+      kk[j] = top ? ~A.k[x] : A.k[x];
+      vv[j] = top ? ~A.v[x] : A.v[x];
+      live |= 1u << j;
+    }
+  }
+  u64 bk = KINF;
+  u32 bv = VINF;
+  for (u32 s = 0; s < it; ++s) {
+    bk = KINF;
+    bv = VINF;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if ((live >> j) & 1u) {
+        bool lt = kk[j] < bk || (kk[j] == bk && vv[j] < bv);
+        bk = lt ? kk[j] : bk;
+        bv = lt ? vv[j] : bv;
+      }
+    t.minkv(bk, bv);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (((live >> j) & 1u) && kk[j] == bk && vv[j] == bv) live &= ~(1u << j);
+  }
+  return top ? KV{~bk, ~bv} : KV{bk, bv};
+}
+
 // Select(A, r): the r-th smallest (key, id) of A, 1 <= r <= n.  Radix select,
 // most significant byte first, over key - min(key) (only the bytes the key
 // range needs), then over the id among elements with the selected key.  The
 // paper sorted with a radix sort to select (Section 4.1); a radix select reads
-// the candidates once per byte and sorts nothing.
-template <class T>
-PBH_HD KV select_kth(T& t, Arr A, u32 n, u32 r) {
+// the candidates once per byte and sorts nothing.  Ranks within two of either
+// end of a small array use select_small.
+template <class T, class AA>
+PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
+  if (n <= 8u * (u32)T::kNT && (r <= 2 || n - r + 1 <= 2)) return select_small(t, A, n, r);
   u64 lo = KINF, hi = 0;
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
     u64 k = A.k[x];
@@ -306,16 +409,17 @@ PBH_HD KV select_kth(T& t, Arr A, u32 n, u32 r) {
 
 // Stable three-way split of A (order by id is kept in each part):
 // e <= p1 -> O0, p1 < e <= p2 -> O1, e > p2 -> O2.
-template <class T, int E = 4>
-PBH_HD void partition3(T& t, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, u32* n0, u32* n1,
-                       u32* n2) {
+template <class T, class AA, class A0, class A1, class A2>
+PBH_INL void partition3(const T& t, AA A, u32 n, KV p1, KV p2, A0 O0, A1 O1, A2 O2, u32* n0, u32* n1,
+                        u32* n2, const u64* live0 = nullptr) {
+  constexpr int E = T::kE;
   u32 c0t = 0, c1t = 0, c2t = 0;
   for (u32 base = 0; base < n; base += (u32)T::kNT * E) {
     u32 x0 = base + (u32)t.tid() * E;
     u64 kk[E];
     u32 vv[E];
     u32 cl[E];
-    u32 c0 = 0, c1 = 0;
+    u32 c0 = 0, c1 = 0, c2 = 0;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       kk[s] = 0;
@@ -326,15 +430,20 @@ PBH_HD void partition3(T& t, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2,
         vv[s] = A.v[x0 + s];
         KV e{kk[s], vv[s]};
         cl[s] = kv_le(e, p1) ? 0u : (kv_le(e, p2) ? 1u : 2u);
+        // With live0, class-0 elements that are not live are dropped.
+        if (cl[s] == 0 && live0 && t.load_cur(live0 + vv[s]) != kk[s]) cl[s] = 3;
         c0 += cl[s] == 0;
         c1 += cl[s] == 1;
+        c2 += cl[s] == 2;
       }
     }
     u32 tot;
     u32 pre = t.scan_excl(c0 | (c1 << 16), &tot);
+    u32 tot2;
+    u32 pre2 = live0 ? t.scan_excl(c2, &tot2) : 0u;
     u32 before = x0 < n ? x0 - base : n - base;
     u32 o0 = c0t + (pre & 0xFFFFu), o1 = c1t + (pre >> 16);
-    u32 o2 = c2t + (before - (pre & 0xFFFFu) - (pre >> 16));
+    u32 o2 = c2t + (live0 ? pre2 : (before - (pre & 0xFFFFu) - (pre >> 16)));
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       if (cl[s] == 0) {
@@ -355,7 +464,7 @@ PBH_HD void partition3(T& t, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2,
     u32 t0 = tot & 0xFFFFu, t1 = tot >> 16;
     c0t += t0;
     c1t += t1;
-    c2t += tile - t0 - t1;
+    c2t += live0 ? tot2 : tile - t0 - t1;
   }
   t.sync();
   *n0 = c0t;
@@ -365,19 +474,19 @@ PBH_HD void partition3(T& t, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2,
 
 struct DigitId {
   int s;
-  PBH_HD u32 operator()(u64, u32 v) const { return (v >> s) & 255u; }
+  PBH_INL u32 operator()(u64, u32 v) const { return (v >> s) & 255u; }
 };
 struct DigitKey {
   int s;
   u64 lo;
-  PBH_HD u32 operator()(u64 k, u32) const { return (u32)((k - lo) >> s) & 255u; }
+  PBH_INL u32 operator()(u64 k, u32) const { return (u32)((k - lo) >> s) & 255u; }
 };
 
 // One stable counting-sort pass on an 8-bit digit (LSD radix sort).  Ranks
 // among equal digits inside a wavefront come from ballots (peer masks), and
 // across wavefronts from per-wave digit counts in LDS.
-template <class T, class F>
-PBH_HD void radix_pass(T& t, Arr src, Arr dst, u32 n, F dig) {
+template <class T, class AS, class AD, class F>
+PBH_INL void radix_pass(const T& t, AS src, AD dst, u32 n, F dig) {
   for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
   t.sync();
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) t.hist_add(t.sh->hist, dig(src.k[x], src.v[x]));
@@ -411,7 +520,7 @@ PBH_HD void radix_pass(T& t, Arr src, Arr dst, u32 n, F dig) {
       u64 bb = t.ballot(valid && bit);
       m &= bit ? bb : ~bb;
     }
-    u32 rank = (u32)__builtin_popcountll(m & t.lanemask_lt());
+    u32 rank = t.count_below(m);
     u32 cnt = (u32)__builtin_popcountll(m);
     for (u32 z = (u32)t.tid(); z < (u32)T::kNW * 256; z += (u32)T::kNT) t.sh->wcnt[z >> 8][z & 255] = 0;
     t.sync();
@@ -436,25 +545,27 @@ PBH_HD void radix_pass(T& t, Arr src, Arr dst, u32 n, F dig) {
   }
 }
 
-// Sorts n elements by id (idbits significant bits).  Returns the buffer that
-// holds the result (a or tmp).
-template <class T>
-PBH_HD Arr sort_by_id(T& t, Arr a, Arr tmp, u32 n, int idbits) {
-  Arr src = a, dst = tmp;
+// Sorts n elements by id (idbits significant bits).  Returns true when the
+// result ended in tmp (false: in a).
+template <class T, class A>
+PBH_INL bool sort_by_id(const T& t, A a, A tmp, u32 n, int idbits) {
+  bool in_tmp = false;
   for (int s = 0; s < idbits; s += 8) {
-    radix_pass(t, src, dst, n, DigitId{s});
-    Arr x = src;
-    src = dst;
-    dst = x;
+    if (in_tmp)
+      radix_pass(t, tmp, a, n, DigitId{s});
+    else
+      radix_pass(t, a, tmp, n, DigitId{s});
+    in_tmp = !in_tmp;
   }
-  return src;
+  return in_tmp;
 }
 
-// Sorts n elements by (key, id).
-template <class T>
-PBH_HD Arr sort_kv(T& t, Arr a, Arr tmp, u32 n, int idbits) {
-  Arr src = sort_by_id(t, a, tmp, n, idbits);
-  Arr dst = (src.k == a.k) ? tmp : a;
+// Sorts n elements by (key, id); returns true when the result is in tmp.
+template <class T, class A>
+PBH_INL bool sort_kv(const T& t, A a, A tmp, u32 n, int idbits) {
+  bool in_tmp = sort_by_id(t, a, tmp, n, idbits);
+  if (n == 0) return in_tmp;
+  A src = in_tmp ? tmp : a;
   u64 lo = KINF, hi = 0;
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
     u64 k = src.k[x];
@@ -462,20 +573,20 @@ PBH_HD Arr sort_kv(T& t, Arr a, Arr tmp, u32 n, int idbits) {
     hi = k > hi ? k : hi;
   }
   t.minmax64(lo, hi);
-  if (n == 0) return src;
   u64 span = hi - lo;
   int nb = span ? 64 - __builtin_clzll(span) : 0;
   for (int s = 0; s < nb; s += 8) {
-    radix_pass(t, src, dst, n, DigitKey{s, lo});
-    Arr x = src;
-    src = dst;
-    dst = x;
+    if (in_tmp)
+      radix_pass(t, tmp, a, n, DigitKey{s, lo});
+    else
+      radix_pass(t, a, tmp, n, DigitKey{s, lo});
+    in_tmp = !in_tmp;
   }
-  return src;
+  return in_tmp;
 }
 
-template <class T>
-PBH_HD void copy_arr(T& t, Arr src, Arr dst, u32 n) {
+template <class T, class AS, class AD>
+PBH_INL void copy_arr(const T& t, AS src, AD dst, u32 n) {
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
     dst.k[x] = src.k[x];
     dst.v[x] = src.v[x];
@@ -487,7 +598,8 @@ PBH_HD void copy_arr(T& t, Arr src, Arr dst, u32 n) {
 
 // Recomputes ell (deepest non-empty level) and sets p_j = +inf for j >= ell:
 // the deepest non-empty level has nothing below it to separate from.
-PBH_HD inline void fix_ell(HeapState* st, int q) {
+template <class SP>
+PBH_INL void fix_ell(SP st, int q) {
   int e = -1;
   for (int j = q - 1; j >= 0; --j)
     if (st->L[j].nB + st->L[j].nS) {
@@ -501,7 +613,8 @@ PBH_HD inline void fix_ell(HeapState* st, int q) {
   }
 }
 
-// Algorithm 1, Resolve(i): empty S_i and fill B_i.
+// Algorithm 1, Resolve(i): empty S_i and fill B_i, with level i's arrays of
+// type AI and level i+1's of type AN.
 //   EMPTY: B_i <- DeleteDuplicates(Merge(S_i, B_i)); if more than 2d*4^i
 //          elements are <= p_i, p_i <- Select(B_i, 2d*4^i); elements > p_i move
 //          to S_{i+1} <- Merge(S_{i+1}, B'_i).
@@ -514,23 +627,25 @@ PBH_HD inline void fix_ell(HeapState* st, int q) {
 // FILL of level i-1); the new p_i in FILL never exceeds p_{i+1}, so nothing
 // deeper than level i+1 can be smaller than an element moved up; the two
 // splits at the end of FILL are one three-way split.
-template <class T>
-PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
-  Lvl a = st->L[i];
+template <class T, class P, class AI, class AN>
+PBH_INL void resolve_t(T t, Geom g, typename P::SP st, const u64* cur, int i) {
+  Lvl a = lvl_load(st, i);
   const bool nx = i + 1 < g.q;
-  Lvl b = nx ? st->L[i + 1] : Lvl{0, 0, 0, 0, KINF, VINF, 0};
+  Lvl b = nx ? lvl_load(st, i + 1) : Lvl{0, 0, 0, 0, KINF, VINF, 0};
   int ell = st->ell;
   KV pi{a.pk, a.pv}, pn{b.pk, b.pv};
   const u32 cB = (u32)nomB(g.d, i);
   u64 touched = 0;
   int err = 0;
   if (a.nS > 0 || a.nB > cB) {
-    Arr S = lbuf(g, i, 3 + a.ssel), B = lbuf(g, i, a.bsel), M = lbuf(g, i, a.bsel ^ 1);
+    AI S = as_arr<AI>(lbuf(g, i, 3 + a.ssel)), B = as_arr<AI>(lbuf(g, i, a.bsel)),
+       M = as_arr<AI>(lbuf(g, i, a.bsel ^ 1));
     if ((u64)a.nS + a.nB > capB(g.d, i)) {
       err = E_INTERNAL;
       goto done;
     }
-    u32 m = merge_dedup(t, S, a.nS, B, a.nB, M, cur, false);
+    // S_0 holds the latest updates, so at level 0 its copy of an id is the live one.
+    u32 m = merge_dedup(t, S, a.nS, B, a.nB, M, cur, false, i == 0 ? PREFER_A : PREFER_LIVE);
     touched += 2ull * (a.nS + a.nB) + m;
     a.bsel ^= 1;
     a.nS = 0;
@@ -546,9 +661,9 @@ PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
         err = E_CAPACITY;
         goto done;
       }
-      Arr Lo = lbuf(g, i, a.bsel ^ 1), Hi = lbuf(g, i, 2);
+      AI Lo = as_arr<AI>(lbuf(g, i, a.bsel ^ 1)), Hi = as_arr<AI>(lbuf(g, i, 2));
       u32 n0, n1, n2;
-      partition3(t, M, m, pi, kv_inf(), Lo, Hi, Arr{nullptr, nullptr}, &n0, &n1, &n2);
+      partition3(t, M, m, pi, kv_inf(), Lo, Hi, Hi, &n0, &n1, &n2);
       touched += 3ull * m;
       a.bsel ^= 1;
       a.nB = n0;
@@ -556,7 +671,7 @@ PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
         err = E_INTERNAL;
         goto done;
       }
-      Arr Sn = lbuf(g, i + 1, 3 + b.ssel), Sn2 = lbuf(g, i + 1, 3 + (b.ssel ^ 1));
+      AN Sn = as_arr<AN>(lbuf(g, i + 1, 3 + b.ssel)), Sn2 = as_arr<AN>(lbuf(g, i + 1, 3 + (b.ssel ^ 1)));
       u32 ms = merge_dedup(t, Sn, b.nS, Hi, n1, Sn2, cur, false);
       touched += 2ull * (b.nS + n1) + ms;
       b.ssel ^= 1;
@@ -567,7 +682,8 @@ PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
     }
   }
   if (a.nB < cB && i < ell && nx) {
-    Arr Bn = lbuf(g, i + 1, b.bsel), Sn = lbuf(g, i + 1, 3 + b.ssel), M2 = lbuf(g, i + 1, b.bsel ^ 1);
+    AN Bn = as_arr<AN>(lbuf(g, i + 1, b.bsel)), Sn = as_arr<AN>(lbuf(g, i + 1, 3 + b.ssel)),
+       M2 = as_arr<AN>(lbuf(g, i + 1, b.bsel ^ 1));
     if ((u64)b.nB + b.nS > capB(g.d, i + 1)) {
       err = E_INTERNAL;
       goto done;
@@ -583,16 +699,18 @@ PBH_HD void resolve(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
       KV pnew = (r >= m2) ? kv_inf() : select_kth(t, M2, m2, r);
       if (r < m2) touched += m2;
       if (kv_less(pn, pnew)) pnew = pn;
-      Arr Up = lbuf(g, i, 2), Bk = lbuf(g, i + 1, b.bsel ^ 1), Sk = lbuf(g, i + 1, 3);
+      AI Up = as_arr<AI>(lbuf(g, i, 2));
+      AN Bk = as_arr<AN>(lbuf(g, i + 1, b.bsel ^ 1)), Sk = as_arr<AN>(lbuf(g, i + 1, 3));
       u32 nu, nb1, ns1;
-      partition3(t, M2, m2, pnew, pn, Up, Bk, Sk, &nu, &nb1, &ns1);
+      // Elements moving up into B_0 are checked for liveness here, all at once.
+      partition3(t, M2, m2, pnew, pn, Up, Bk, Sk, &nu, &nb1, &ns1, i == 0 ? cur : nullptr);
       touched += 3ull * m2;
       b.bsel ^= 1;
       b.nB = nb1;
       b.nS = ns1;
       b.ssel = 0;
-      Arr Bi = lbuf(g, i, a.bsel), Bi2 = lbuf(g, i, a.bsel ^ 1);
-      u32 mb = merge_dedup(t, Bi, a.nB, Up, nu, Bi2, cur, i == 0 && cur != nullptr);
+      AI Bi = as_arr<AI>(lbuf(g, i, a.bsel)), Bi2 = as_arr<AI>(lbuf(g, i, a.bsel ^ 1));
+      u32 mb = merge_dedup(t, Bi, a.nB, Up, nu, Bi2, cur, false, i == 0 && cur != nullptr ? PREFER_B : PREFER_LIVE);
       touched += 2ull * (a.nB + nu) + mb;
       a.bsel ^= 1;
       a.nB = mb;
@@ -608,8 +726,8 @@ done:
     if (err) {
       st->err = err;
     } else {
-      st->L[i] = a;
-      if (nx) st->L[i + 1] = b;
+      lvl_store(st, i, a);
+      if (nx) lvl_store(st, i + 1, b);
       st->elems += touched;
       fix_ell(st, g.q);
     }
@@ -617,54 +735,97 @@ done:
   t.sync();
 }
 
+template <class T, class P>
+PBH_INL void resolve(const T& t, const Geom& g, typename P::SP st, const u64* cur, int i) {
+  if (i + 1 < g.qlds)
+    resolve_t<T, P, typename P::L, typename P::L>(t, g, st, cur, i);
+  else if (i < g.qlds)
+    resolve_t<T, P, typename P::L, typename P::G>(t, g, st, cur, i);
+  else
+    resolve_t<T, P, typename P::G, typename P::G>(t, g, st, cur, i);
+}
+
 // Can Resolve(j) move its worst case (all of S_j and B_j) into level j+1?
-PBH_HD inline bool room_below(const Geom& g, const HeapState* st, int j) {
+template <class SP>
+PBH_INL bool room_below(const Geom& g, SP st, int j) {
   if (j + 1 >= g.q) return true;
   u64 push = (u64)st->L[j].nS + st->L[j].nB;
-  const Lvl& b = st->L[j + 1];
-  return (u64)b.nS + push <= capS(g.d, j + 1) && (u64)b.nB + b.nS + push <= capB(g.d, j + 1);
+  u64 bS = st->L[j + 1].nS, bB = st->L[j + 1].nB;
+  return bS + push <= capS(g.d, j + 1) && bB + bS + push <= capB(g.d, j + 1);
 }
 
-// Resolve(i), after first resolving the levels below that lack room for what
-// Resolve(i) may push down.  After Resolve(j), level j has S_j empty and
-// |B_j| <= 2d*4^j, which always leaves room for level j-1.
-template <class T>
-PBH_HD void resolve_safe(T& t, const Geom& g, HeapState* st, const u64* cur, int i) {
-  int j = i;
-  while (j + 1 < g.q && !room_below(g, st, j)) ++j;
-  for (int k = j; k > i && !st->err; --k) resolve(t, g, st, cur, k);
-  if (!st->err) resolve(t, g, st, cur, i);
-}
+enum { DRIVE_AFTER = 1, DRIVE_ENSURE = 2 };
 
-// After every operation: Resolve(0), then the resolution schedule.
-//   sched 0 = Theorem 1: Resolve(i) after every fourth Resolve(i-1).
-//   sched 1 = on demand (as the sequential bucket heap does): Resolve(i+1)
-//             only when the next Resolve(i) would otherwise violate its
-//             preconditions on level i+1.
-template <class T>
-PBH_HD void after_op(T& t, const Geom& g, HeapState* st, const u64* cur, int sched) {
-  resolve_safe(t, g, st, cur, 0);
-  for (int i = 0; i + 1 < g.q && !st->err; ++i) {
-    if (i + 1 > st->ell) break;
-    bool go;
-    if (sched == 0) {
-      go = (st->L[i].cnt & 3u) == 0;
+// The resolution schedule, as one loop with a single call of Resolve (so each
+// placement variant of Resolve is instantiated once per kernel).  Requests:
+//
+// * DRIVE_AFTER -- after an operation: Resolve(0), then the schedule:
+//     sched 0 = Theorem 1: Resolve(i+1) after every fourth Resolve(i);
+//     sched 1 = on demand (as the sequential bucket heap of Section 2.1 does):
+//               Resolve(i+1) only when the next Resolve(i) would otherwise
+//               violate its preconditions on level i+1.
+// * DRIVE_ENSURE -- then, if B_0 is empty while the heap is not (possible when
+//     deleted duplicates or dead copies thin out the levels below), resolve
+//     levels j, j-1, ..., 0 for j = 1, 2, ... until B_0 has an element.
+//
+// Every requested Resolve(x) first resolves the levels below x that lack
+// room for what Resolve(x) may push down: find the first j >= x whose next
+// level can take all of S_j and B_j, then resolve j, j-1, ..., x.  After
+// Resolve(j), level j has S_j empty and |B_j| <= 2d*4^j, which always leaves
+// room for level j-1.
+template <class T, class P>
+PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur, int sched, int what) {
+  int tgt = -1, chain = -1;  // pending chain: levels chain, chain-1, ..., tgt
+  int stage = (what & DRIVE_AFTER) ? 0 : 2;
+  int si = 0;                // schedule position
+  int ej = 1, ek = -1;       // refill position
+  for (;;) {
+    if (st->err) break;
+    int lvl;
+    if (chain >= 0) {
+      lvl = chain;
+      chain = chain > tgt ? chain - 1 : -1;
     } else {
-      const Lvl& b = st->L[i + 1];
-      go = b.nS > nomS(g.d, i + 1) - nomS(g.d, i) ||
-           (i + 1 < st->ell && b.nB < nomS(g.d, i + 1) + nomS(g.d, i));
+      int x = -1;
+      if (stage == 0) {
+        x = 0;
+        stage = 1;
+        si = 0;
+      } else if (stage == 1) {
+        bool go = si + 1 < g.q && si + 1 <= st->ell;
+        if (go) {
+          if (sched == 0) {
+            go = (st->L[si].cnt & 3u) == 0;
+          } else {
+            u64 bS = st->L[si + 1].nS, bB = st->L[si + 1].nB;
+            go = bS > nomS(g.d, si + 1) - nomS(g.d, si) ||
+                 (si + 1 < st->ell && bB < nomS(g.d, si + 1) + nomS(g.d, si));
+          }
+        }
+        if (go) {
+          x = si + 1;
+          ++si;
+        } else {
+          stage = 2;
+        }
+      }
+      if (x < 0 && stage == 2) {
+        if (!(what & DRIVE_ENSURE)) break;
+        if (ek < 0) {
+          if (st->L[0].nB != 0 || ej > st->ell) break;
+          ek = ej;
+          ++ej;
+        }
+        x = ek--;
+      }
+      int j = x;
+      while (j + 1 < g.q && !room_below(g, st, j)) ++j;
+      tgt = x;
+      lvl = j;
+      chain = j > x ? j - 1 : -1;
     }
-    if (!go) break;
-    resolve_safe(t, g, st, cur, i + 1);
+    resolve<T, P>(t, g, st, cur, lvl);
   }
-}
-
-// Brings at least one element into B_0 if the heap is not empty (B_0 can run
-// dry when duplicates or dead copies thin out the levels below).
-template <class T>
-PBH_HD void ensure_b0(T& t, const Geom& g, HeapState* st, const u64* cur) {
-  for (int j = 1; st->L[0].nB == 0 && j <= st->ell && !st->err; ++j)
-    for (int k = j; k >= 0 && !st->err; --k) resolve_safe(t, g, st, cur, k);
 }
 
 // ---------------------------------------------------------------- parDijkstra
@@ -683,8 +844,8 @@ PBH_HD inline int bits_for(u32 n) {
 // and nothing is done.  Otherwise each id keeps the pair whose key equals
 // dist[id] (the minimum, since dist was lowered by atomicMin) and the rest is
 // sorted by id.
-template <class T>
-PBH_HD u32 intake(T& t, Arr S, u32 n, Arr tmp, Arr tmp2, const u64* dist, int idbits) {
+template <class T, class A>
+PBH_INL u32 intake(const T& t, A S, u32 n, A tmp, A tmp2, const u64* dist, int idbits) {
   u32 bad = 0;
   for (u32 x = (u32)t.tid() + 1; x < n; x += (u32)T::kNT) bad += S.v[x - 1] >= S.v[x];
   bad = t.sum(bad);
@@ -692,7 +853,7 @@ PBH_HD u32 intake(T& t, Arr S, u32 n, Arr tmp, Arr tmp2, const u64* dist, int id
   u32 out = 0;
   for (u32 base = 0; base < n; base += (u32)T::kNT) {
     u32 x = base + (u32)t.tid();
-    bool keep = x < n && load_cur(t, dist + S.v[x]) == S.k[x];
+    bool keep = x < n && t.load_cur(dist + S.v[x]) == S.k[x];
     u64 k = x < n ? S.k[x] : 0;
     u32 v = x < n ? S.v[x] : 0;
     u32 tot;
@@ -704,39 +865,107 @@ PBH_HD u32 intake(T& t, Arr S, u32 n, Arr tmp, Arr tmp2, const u64* dist, int id
     out += tot;
   }
   t.sync();
-  Arr r = sort_by_id(t, tmp, tmp2, out, idbits);
-  copy_arr(t, r, S, out);
+  bool in2 = sort_by_id(t, tmp, tmp2, out, idbits);
+  if (in2)
+    copy_arr(t, tmp2, S, out);
+  else
+    copy_arr(t, tmp, S, out);
   return out;
 }
 
-// parDijkstra (Section 4.1): each round extracts the minimum (key, id) from
-// B_0 -- B_0 holds only live elements, so this is the closest unsettled
-// vertex u -- relaxes all out-edges of u in parallel (atomicMin on dist),
-// compacts the improved (dist, v) pairs with a prefix sum straight into S_0
-// (BulkUpdate of at most d = max out-degree elements) and runs Resolve(0) and
-// the schedule.  The extraction and the bulk update of a round share one
-// Resolve(0): S_0 is empty and B_0 keeps at least d elements in between, so
-// Algorithm 1's preconditions hold.
-template <class T>
-PBH_HD void sssp_rounds(T& t, const Geom& g, HeapState* st, const u64* off, const u32* tg, const u32* wt,
-                        u64* dist, u32 n, u32 src, int sched, SsspCounters* cnt) {
+// One parDijkstra round (Section 4.1) with level 0 of type A0: extract the
+// minimum (key, id) of B_0 -- B_0 holds only live elements, so this is the
+// closest unsettled vertex u -- relax all out-edges of u in parallel
+// (atomicMin on dist) and compact the improved (dist, v) pairs with a prefix
+// sum straight into S_0 (a BulkUpdate of at most d = max out-degree pairs).
+// Returns false when the heap is empty.
+template <class T, class P, class A0>
+PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
+                        const u32* wt, u64* dist, int idbits, u64* relax, u64* upd) {
+  const Lvl a0 = lvl_load(st, 0);
+  if (a0.nB == 0) return false;
+  A0 B = as_arr<A0>(lbuf(g, 0, a0.bsel));
+  u64 mk = KINF;
+  u32 mv = VINF;
+  for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) {
+    u64 k = B.k[x];
+    u32 v = B.v[x];
+    if (k < mk || (k == mk && v < mv)) {
+      mk = k;
+      mv = v;
+    }
+  }
+  t.minkv(mk, mv);
+  const u64 e0 = off[mv], e1 = off[mv + 1];
+  u32 n0, n1, n2;
+  A0 T0 = as_arr<A0>(lbuf(g, 0, 2));
+  partition3(t, B, a0.nB, KV{mk, mv}, kv_inf(), T0, as_arr<A0>(lbuf(g, 0, a0.bsel ^ 1)), T0, &n0, &n1, &n2);
+  A0 S = as_arr<A0>(lbuf(g, 0, 3));
+  u32 nu = 0;
+  for (u64 eb = e0; eb < e1; eb += (u64)T::kNT) {
+    u64 e = eb + (u64)t.tid();
+    bool imp = false;
+    u64 cand = 0;
+    u32 v = 0;
+    if (e < e1) {
+      v = tg[e];
+      cand = mk + (u64)wt[e];
+      imp = cand < t.atomic_min(dist + v, cand);
+    }
+    u32 tot;
+    u32 p = t.scan_excl(imp ? 1u : 0u, &tot);
+    if (imp) {
+      S.k[nu + p] = cand;
+      S.v[nu + p] = v;
+    }
+    nu += tot;
+  }
+  t.sync();
+  nu = intake(t, S, nu, T0, as_arr<A0>(lbuf(g, 0, 4)), dist, idbits);
+  if (t.tid() == 0) {
+    st->L[0].bsel = a0.bsel ^ 1;
+    st->L[0].nB = n1;
+    st->L[0].nS = nu;
+    st->L[0].ssel = 0;
+    st->elems += 3ull * a0.nB + nu;
+    if (st->ell < 0 && (n1 + nu) > 0) st->ell = 0;
+  }
+  t.sync();
+  *relax += e1 - e0;
+  *upd += nu;
+  return true;
+}
+
+// parDijkstra: rounds until the heap is empty.  The extraction and the bulk
+// update of a round share one Resolve(0) and the schedule: between them S_0 is
+// empty and B_0 keeps at least d elements, so Algorithm 1's preconditions hold.
+template <class T, class P>
+PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
+                         const u32* wt, u64* dist, u32 n, u32 src, int sched, SsspCounters* cnt) {
   const int idbits = bits_for(n);
   if (t.tid() == 0) {
     Arr S = lbuf(g, 0, 3);
-    S.k[0] = 0;
-    S.v[0] = src;
+    if (g.qlds > 0) {
+      typename P::L s = as_arr<typename P::L>(S);
+      s.k[0] = 0;
+      s.v[0] = src;
+    } else {
+      typename P::G s = as_arr<typename P::G>(S);
+      s.k[0] = 0;
+      s.v[0] = src;
+    }
     st->L[0].nS = 1;
     st->L[0].ssel = 0;
     st->ell = 0;
   }
   t.sync();
-  after_op(t, g, st, dist, sched);
   u64 rounds = 0, relax = 0, upd = 1;
   for (;;) {
-    ensure_b0(t, g, st, dist);
+    // Resolve(0) and the schedule after the previous operation (the source's
+    // insertion, or the last round's bulk update), then make sure B_0 holds
+    // the minimum if the heap is not empty.
+    drive<T, P>(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
     if (st->err) break;
-    const Lvl a0 = st->L[0];
-    if (a0.nB == 0) break;
     // Every extraction consumes one insertion and every insertion comes from
     // one scanned edge (or the source), so rounds <= 1 + relax always holds.
     if (rounds > relax + 1) {
@@ -744,58 +973,10 @@ PBH_HD void sssp_rounds(T& t, const Geom& g, HeapState* st, const u64* off, cons
       t.sync();
       break;
     }
-    Arr B = lbuf(g, 0, a0.bsel);
-    u64 mk = KINF;
-    u32 mv = VINF;
-    for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) {
-      u64 k = B.k[x];
-      u32 v = B.v[x];
-      if (k < mk || (k == mk && v < mv)) {
-        mk = k;
-        mv = v;
-      }
-    }
-    t.minkv(mk, mv);
-    u32 n0, n1, n2;
-    partition3(t, B, a0.nB, KV{mk, mv}, kv_inf(), lbuf(g, 0, 2), lbuf(g, 0, a0.bsel ^ 1),
-               Arr{nullptr, nullptr}, &n0, &n1, &n2);
-    const u64 e0 = off[mv], e1 = off[mv + 1];
-    Arr S = lbuf(g, 0, 3);
-    u32 nu = 0;
-    for (u64 eb = e0; eb < e1; eb += (u64)T::kNT) {
-      u64 e = eb + (u64)t.tid();
-      bool imp = false;
-      u64 cand = 0;
-      u32 v = 0;
-      if (e < e1) {
-        v = tg[e];
-        cand = mk + (u64)wt[e];
-        imp = cand < t.atomic_min(dist + v, cand);
-      }
-      u32 tot;
-      u32 p = t.scan_excl(imp ? 1u : 0u, &tot);
-      if (imp) {
-        S.k[nu + p] = cand;
-        S.v[nu + p] = v;
-      }
-      nu += tot;
-    }
-    t.sync();
-    nu = intake(t, S, nu, lbuf(g, 0, 2), lbuf(g, 0, 4), dist, idbits);
-    if (t.tid() == 0) {
-      Lvl& L0 = st->L[0];
-      L0.bsel ^= 1;
-      L0.nB = n1;
-      L0.nS = nu;
-      L0.ssel = 0;
-      st->elems += 3ull * a0.nB + nu;
-      if (st->ell < 0 && (n1 + nu) > 0) st->ell = 0;
-    }
-    t.sync();
-    after_op(t, g, st, dist, sched);
+    bool more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &relax, &upd)
+                           : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &relax, &upd);
+    if (!more) break;
     ++rounds;
-    relax += e1 - e0;
-    upd += nu;
   }
   cnt->rounds = rounds;
   cnt->relax = relax;
@@ -827,10 +1008,10 @@ struct PbhParams {
 // Could the next operation push elements out of the deepest allocated level?
 // Then the caller adds a level first (growing the arena keeps the offsets of
 // the existing levels).
-PBH_HD inline bool need_grow(const Geom& g, const HeapState* st) {
+template <class SP>
+PBH_INL bool need_grow(const Geom& g, SP st) {
   const int q = g.q;
-  const Lvl& b = st->L[q - 1];
-  u64 have = (u64)b.nB + b.nS;
+  u64 have = (u64)st->L[q - 1].nB + st->L[q - 1].nS;
   u64 in = (q == 1) ? (u64)g.d : capB(g.d, q - 2) + capS(g.d, q - 2);
   return have + in > nomB(g.d, q - 1);
 }
@@ -842,9 +1023,10 @@ PBH_HD inline bool need_grow(const Geom& g, const HeapState* st) {
 // Section 2.2 requires.  Then pieces of at most d go into S_0, each followed
 // by Resolve(0) and the schedule.  Resumable: st->aux[0] = list length,
 // aux[1] = list built, aux[3] = stopped because a level must be added,
-// progress = list position reached.
-template <class T>
-PBH_HD void pbh_update_body(T& t, const Geom& g, HeapState* st, const PbhParams& p) {
+// progress = list position reached.  All levels are in HBM (type P::G).
+template <class T, class P>
+PBH_INL void pbh_update_body(const T& t, const Geom& g, typename P::SP st, const PbhParams& p) {
+  using G = typename P::G;
   if (st->aux[1] == 0) {
     u32 newly = 0;
     for (u64 x = (u64)t.tid(); x < p.count; x += (u64)T::kNT) {
@@ -898,7 +1080,7 @@ PBH_HD void pbh_update_body(T& t, const Geom& g, HeapState* st, const PbhParams&
       break;
     }
     u32 len = (u32)((nu - c0) < g.d ? (nu - c0) : g.d);
-    Arr S = lbuf(g, 0, 3);
+    G S = as_arr<G>(lbuf(g, 0, 3));
     for (u32 x = (u32)t.tid(); x < len; x += (u32)T::kNT) {
       S.k[x] = p.ukeys[c0 + x];
       S.v[x] = p.uids[c0 + x];
@@ -911,7 +1093,7 @@ PBH_HD void pbh_update_body(T& t, const Geom& g, HeapState* st, const PbhParams&
       st->elems += 2ull * len;
     }
     t.sync();
-    after_op(t, g, st, p.cur, p.sched);
+    drive<T, P>(t, g, st, p.cur, p.sched, DRIVE_AFTER);
     if (st->err) break;
     c0 += len;
     if (t.tid() == 0) st->progress = c0;
@@ -923,37 +1105,42 @@ PBH_HD void pbh_update_body(T& t, const Geom& g, HeapState* st, const PbhParams&
 // |B_0|) elements of B_0 (B_0 <= p_0 < everything else, and B_0 holds only
 // live elements), output them sorted by (key, id), mark their ids absent, then
 // Resolve(0) and the schedule.  Resumable: progress = elements written,
-// aux[3] = stopped for growth, aux[4] = heap ran empty.
-template <class T>
-PBH_HD void pbh_extract_body(T& t, const Geom& g, HeapState* st, const PbhParams& p) {
+// aux[2] = an extraction awaits its Resolve(0), aux[3] = stopped for growth,
+// aux[4] = heap ran empty.
+template <class T, class P>
+PBH_INL void pbh_extract_body(const T& t, const Geom& g, typename P::SP st, const PbhParams& p) {
+  using G = typename P::G;
   if (t.tid() == 0) {
     st->aux[3] = 0;
     st->aux[4] = 0;
   }
   t.sync();
   for (;;) {
+    const bool pending = st->aux[2] != 0;  // the last extraction still needs its Resolve(0)
     const u64 outpos = st->progress;
-    if (outpos >= p.k) break;
+    if (!pending && outpos >= p.k) break;
     if (need_grow(g, st)) {
       if (t.tid() == 0) st->aux[3] = 1;
       t.sync();
       break;
     }
-    ensure_b0(t, g, st, p.cur);
-    if (st->err) break;
-    const Lvl a0 = st->L[0];
+    drive<T, P>(t, g, st, p.cur, p.sched, (pending ? DRIVE_AFTER : 0) | (outpos < p.k ? DRIVE_ENSURE : 0));
+    if (t.tid() == 0) st->aux[2] = 0;
+    t.sync();
+    if (st->err || outpos >= p.k) break;
+    const Lvl a0 = lvl_load(st, 0);
     if (a0.nB == 0) {
       if (t.tid() == 0) st->aux[4] = 1;
       t.sync();
       break;
     }
     u32 take = (u32)((p.k - outpos) < a0.nB ? (p.k - outpos) : a0.nB);
-    Arr B = lbuf(g, 0, a0.bsel);
+    G B = as_arr<G>(lbuf(g, 0, a0.bsel));
     KV thr = (take == a0.nB) ? kv_inf() : select_kth(t, B, a0.nB, take);
     u32 n0, n1, n2;
-    Arr X = lbuf(g, 0, 2);
-    partition3(t, B, a0.nB, thr, kv_inf(), X, lbuf(g, 0, a0.bsel ^ 1), Arr{nullptr, nullptr}, &n0, &n1, &n2);
-    Arr R = sort_kv(t, X, B, take, p.idbits);
+    G X = as_arr<G>(lbuf(g, 0, 2));
+    partition3(t, B, a0.nB, thr, kv_inf(), X, as_arr<G>(lbuf(g, 0, a0.bsel ^ 1)), X, &n0, &n1, &n2);
+    G R = sort_kv(t, X, B, take, p.idbits) ? B : X;
     for (u32 x = (u32)t.tid(); x < take; x += (u32)T::kNT) {
       u32 id = R.v[x];
       p.okeys[outpos + x] = R.k[x];
@@ -968,10 +1155,9 @@ PBH_HD void pbh_extract_body(T& t, const Geom& g, HeapState* st, const PbhParams
       st->live -= take;
       st->progress = outpos + take;
       st->elems += 6ull * a0.nB;
+      st->aux[2] = 1;
     }
     t.sync();
-    after_op(t, g, st, p.cur, p.sched);
-    if (st->err) break;
   }
 }
 

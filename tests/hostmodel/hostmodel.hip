@@ -99,7 +99,7 @@ int hm_update(void* hp, const u64* keys, const u32* ids, u64 count) {
     p.ukeys = h->uk.data();
     p.uids = h->ui.data();
     HostTeam t{&h->ts};
-    pbh_update_body(t, p.g, &h->st, p);
+    pbh_update_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) return 0;
     if (h->q >= MAXL) return -2;
@@ -123,7 +123,7 @@ int hm_extract(void* hp, u64 k, u64* ko, u32* io, u64* count) {
     p.okeys = ko;
     p.oids = io;
     HostTeam t{&h->ts};
-    pbh_extract_body(t, p.g, &h->st, p);
+    pbh_extract_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) break;
     if (h->q >= MAXL) return -2;
@@ -189,7 +189,7 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   for (u32 v = 0; v < n; ++v) dist[v] = KINF;
   dist[src] = 0;
   SsspCounters c;
-  sssp_rounds(t, g, &st, off, tg, wt, dist, n, src, sched, &c);
+  sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, &c);
   stats[0] = c.rounds;
   stats[1] = c.relax;
   stats[2] = c.updates;
