@@ -39,6 +39,73 @@ def make_graph(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_multi(args):
+    """The batched workload: 256 queries (64 random geometric graphs with
+    uneven n in 2^12..2^18, mean degree 24, 4 sources each) in one launch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1908_09378_amd as pkg
+    import workloads as W
+
+    batch = W.rgg_batch(64, 4)
+    dev = torch.device("cuda:0")
+    qs, keep = [], []
+    for g, srcs in batch:
+        off = torch.from_numpy(g.offsets.view(np.int64)).to(dev)
+        tg = torch.from_numpy(g.targets.view(np.int32)).to(dev)
+        wt = torch.from_numpy(g.weights.view(np.int32)).to(dev)
+        keep.append((off, tg, wt))
+        for s in srcs:
+            qs.append((off, tg, wt, g.n, g.m, s, torch.empty(g.n, dtype=torch.int64, device=dev)))
+    sum_m = sum(q[4] for q in qs)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        pkg.sssp_batch(qs)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(pkg.sssp_batch(qs))
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    st = stats[-1]
+    kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
+    abytes = algorithmic_bytes(st)
+    achieved = abytes / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": sum_m / sec / 1e9, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "256 queries: 64 random geometric graphs (n = floor(2^(12+6u)), mean degree 24, "
+                               "w = round(1000 len)+1), 4 sources each, one launch",
+                   "method": "batched plain parDijkstra, one parBucketHeap per query", "queries": len(qs),
+                   "sum_n": sum(g.n for g, _ in batch), "sum_m_over_queries": sum_m, "team": st["team"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp_multi",
+                     "kernel_ms": kern_ms, "algorithmic_bytes": abytes},
+        "rounds": st["rounds"], "relaxations": st["relaxations"],
+    }
+    ok = True
+    for (g, srcs), j in zip(batch, range(0, len(qs), 4)):
+        for k, s in enumerate(srcs):
+            ok &= bool(np.array_equal(qs[j + k][6].cpu().numpy().view(np.uint64), oracle.dijkstra(g, s)))
+    line["exact"] = ok
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        runs = 0
+        for g, srcs in batch:
+            for s in srcs:
+                oracle.dijkstra(g, s)
+                runs += 1
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": sum_m / el / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                                "sample": f"all {runs} queries, single-thread binary-heap Dijkstra ({el:.1f} s), "
+                                          f"host {os.cpu_count()} cpus"}
+    print(json.dumps(line), flush=True)
+
+
 def algorithmic_bytes(st):
     """Bytes the method must move per launch: per settled vertex its two CSR
     offsets (16 B); per scanned edge its target and weight (8 B) and the 8-byte
@@ -60,6 +127,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
         sys.exit(2)
+
+    if args.workload == "multi":
+        return run_multi(args)
 
     import numpy as np
     import torch

@@ -110,7 +110,7 @@ int pbh_debug_levels(pbh_t *h, uint32_t max_levels, uint32_t *levels_out, int32_
 int sssp(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
          uint64_t m, uint32_t source, uint64_t *dist_out);
 
-/* Options for sssp_ex.  Zero-initialised means "defaults". */
+/* Options for sssp_ex and sssp_batch.  Zero-initialised means "defaults". */
 typedef struct {
   uint32_t d;             /* heap bulk size; 0 = maximum out-degree (the paper's choice) */
   uint32_t team;          /* threads of the workgroup that runs the rounds: 0 = auto, 64/256/1024 */
@@ -120,15 +120,42 @@ typedef struct {
                              0xFFFFFFFF = none (all levels in HBM) */
   uint64_t heap_capacity; /* elements the arena is sized for; 0 = auto (retried with the
                              safe bound m+1 on PBH_ECAPACITY) */
-  uint32_t reserved[8];
+  /* How many minima each round extracts.  Rounds with k > 1 relax all out-edges
+   * of the k vertices and re-insert any vertex whose distance later improves,
+   * so distances stay exact for every rule. */
+  uint32_t k_rule;        /* 0 = plain parDijkstra (k = 1, Section 4.1); 1 = k_fixed;
+                             2 = learned: the MLP in k_model chooses k each round;
+                             3 = k_seq[round % k_seq_len] */
+  uint32_t k_fixed;
+  uint32_t k_max;         /* cap on k (0 = 2d; never above 256) */
+  uint32_t k_seq_len;
+  const uint32_t *k_seq;  /* device array (rule 3) */
+  const float *k_model;   /* device array of PBH_MLP_BLOB floats (rule 2): W1[8][64], b1[64],
+                             W2[64][64], b2[64], w3[64], b3, mu[8], sd[8], scale
+                             (weights input-major, already rounded to bfloat16); the
+                             model maps 8 per-round features to y, k = 2^(scale*y) */
+  /* Training traces (sssp_ex only): every trace_every-th round writes 8 features
+   * to trace_features[8*i], and the 32 smallest (key, id) of B_0 in key order to
+   * trace_keys[32*i] / trace_ids[32*i], i = (*trace_count)++ while i < trace_cap. */
+  float *trace_features;
+  uint64_t *trace_keys;
+  uint32_t *trace_ids;
+  uint32_t *trace_count;
+  uint32_t trace_every;
+  uint32_t trace_cap;
+  uint32_t reserved[4];
 } sssp_opts;
+
+#define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+#define PBH_MLP_BLOB (PBH_MLP_PARAMS + 2 * 8 + 1)
 
 /* Statistics of one sssp_ex run (host struct). */
 typedef struct {
-  uint64_t rounds;        /* extract-relax-update rounds */
+  uint64_t rounds;        /* rounds (one extraction each) */
   uint64_t relaxations;   /* edges scanned */
   uint64_t updates;       /* (key, id) pairs inserted into the heap */
   uint64_t heap_elems;    /* heap elements read + written by the level operations */
+  uint64_t extracted;     /* elements extracted (= rounds for the plain rule) */
   uint64_t resolves[16];  /* Resolve(i) executions per level */
   uint32_t levels;        /* levels allocated */
   uint32_t d;             /* bulk size used */
@@ -145,6 +172,33 @@ typedef struct {
 int sssp_ex(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
             uint64_t m, uint32_t source, uint64_t *dist_out, const sssp_opts *opts,
             sssp_stats *stats, void *stream);
+
+/* One query of sssp_batch: a CSR graph (device arrays, same rules as sssp),
+ * a source and the distance output (device, n entries).  Queries may share
+ * a graph. */
+typedef struct {
+  const uint64_t *offsets;
+  const uint32_t *targets;
+  const uint32_t *weights;
+  uint64_t m;
+  uint32_t n;
+  uint32_t source;
+  uint64_t *dist_out;
+} sssp_query;
+
+/*
+ * sssp_batch: many independent parDijkstra queries in one persistent launch
+ * (each query runs the rounds of Section 4.1 on its own parallel bucket heap;
+ * every heap lives in one device arena; workgroups take queries from a queue,
+ * largest first).  queries is a HOST array of nq descriptors.  opts as for
+ * sssp_ex (d = 0 means each query uses its graph's maximum out-degree); stats
+ * (may be NULL) receives totals over all queries and the launch's kernel
+ * time.  Each dist_out is exactly what sssp would return for that query.
+ * Errors: PBH_EINVAL (NULL or malformed query, nq == 0 is allowed and does
+ * nothing), PBH_ENOMEM, PBH_EDEVICE, PBH_EINTERNAL.
+ */
+int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, sssp_stats *stats,
+               void *stream);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char *pbh_last_error(void);

@@ -24,20 +24,36 @@ class PBHError(RuntimeError):
         self.code = code
 
 
+MLP_PARAMS = 8 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+MLP_BLOB = MLP_PARAMS + 2 * 8 + 1
+K_PLAIN, K_FIXED, K_LEARNED, K_SEQ = 0, 1, 2, 3
+
+
 class SsspOpts(C.Structure):
     _fields_ = [("d", C.c_uint32), ("team", C.c_uint32), ("schedule", C.c_uint32),
-                ("lds_levels", C.c_uint32), ("heap_capacity", C.c_uint64), ("reserved", C.c_uint32 * 8)]
+                ("lds_levels", C.c_uint32), ("heap_capacity", C.c_uint64),
+                ("k_rule", C.c_uint32), ("k_fixed", C.c_uint32), ("k_max", C.c_uint32), ("k_seq_len", C.c_uint32),
+                ("k_seq", C.c_void_p), ("k_model", C.c_void_p),
+                ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
+                ("trace_count", C.c_void_p), ("trace_every", C.c_uint32), ("trace_cap", C.c_uint32),
+                ("reserved", C.c_uint32 * 4)]
 
 
 class SsspStats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("relaxations", C.c_uint64), ("updates", C.c_uint64),
-                ("heap_elems", C.c_uint64), ("resolves", C.c_uint64 * 16), ("levels", C.c_uint32),
-                ("d", C.c_uint32), ("team", C.c_uint32), ("lds_levels", C.c_uint32), ("kernel_ms", C.c_double)]
+                ("heap_elems", C.c_uint64), ("extracted", C.c_uint64), ("resolves", C.c_uint64 * 16),
+                ("levels", C.c_uint32), ("d", C.c_uint32), ("team", C.c_uint32), ("lds_levels", C.c_uint32),
+                ("kernel_ms", C.c_double)]
+
+
+class SsspQuery(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("targets", C.c_void_p), ("weights", C.c_void_p), ("m", C.c_uint64),
+                ("n", C.c_uint32), ("source", C.c_uint32), ("dist_out", C.c_void_p)]
 
 
 _lib = None
 EXPORTS = ["pbh_create", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_destroy",
-           "pbh_debug_levels", "sssp", "sssp_ex", "pbh_last_error"]
+           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "pbh_last_error"]
 
 
 def lib():
@@ -56,6 +72,7 @@ def lib():
         L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
         L.sssp_ex.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
+        L.sssp_batch.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.pbh_last_error.restype = C.c_char_p
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = C.c_int
@@ -80,22 +97,61 @@ def _ptr(t, elem_bytes):
     return C.c_void_p(t.data_ptr())
 
 
+def _stats_dict(s):
+    return dict(rounds=s.rounds, relaxations=s.relaxations, updates=s.updates, heap_elems=s.heap_elems,
+                extracted=s.extracted, resolves=list(s.resolves), levels=s.levels, d=s.d, team=s.team,
+                lds_levels=s.lds_levels, kernel_ms=s.kernel_ms)
+
+
 def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> None:
     """parDijkstra: dist_out[v] = shortest distance from source (UINT64_MAX if
     unreachable); see include/pbh.h."""
     _check(lib().sssp(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source, _ptr(dist_out, 8)))
 
 
-def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, d=0, team=0, schedule=0,
-            lds_levels=0, heap_capacity=0, stream=None) -> dict:
-    o = SsspOpts(d, team, schedule, lds_levels, heap_capacity)
+def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
+          k_model=None, trace=None):
+    o = SsspOpts()
+    o.d, o.team, o.schedule, o.lds_levels, o.heap_capacity = d, team, schedule, lds_levels, heap_capacity
+    o.k_rule, o.k_fixed, o.k_max = k_rule, k_fixed, k_max
+    if k_seq is not None:
+        o.k_seq, o.k_seq_len = _ptr(k_seq, 4), k_seq.numel()
+    if k_model is not None:
+        if k_model.numel() != MLP_BLOB or k_model.element_size() != 4:
+            raise ValueError(f"k_model must hold {MLP_BLOB} float32 values")
+        o.k_model = _ptr(k_model, 4)
+    if trace is not None:
+        f, k, v, cnt, every = trace
+        o.trace_features, o.trace_keys, o.trace_ids, o.trace_count = _ptr(f, 4), _ptr(k, 8), _ptr(v, 4), _ptr(cnt, 4)
+        o.trace_every, o.trace_cap = every, f.numel() // 8
+    return o
+
+
+def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:
+    """sssp with options (see sssp_opts in include/pbh.h): d, team, schedule,
+    lds_levels, heap_capacity, k_rule, k_fixed, k_max, k_seq (int32 tensor),
+    k_model (float32 tensor of MLP_BLOB values), trace=(features, keys, ids,
+    count, every)."""
+    o = _opts(**kw)
     s = SsspStats()
     sp = None if stream is None else C.c_void_p(stream.cuda_stream)
     _check(lib().sssp_ex(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source, _ptr(dist_out, 8),
                          C.byref(o), C.byref(s), sp))
-    return dict(rounds=s.rounds, relaxations=s.relaxations, updates=s.updates, heap_elems=s.heap_elems,
-                resolves=list(s.resolves), levels=s.levels, d=s.d, team=s.team, lds_levels=s.lds_levels,
-                kernel_ms=s.kernel_ms)
+    return _stats_dict(s)
+
+
+def sssp_batch(queries, *, stream=None, **kw) -> dict:
+    """Many independent parDijkstra queries in one launch.  queries: sequence
+    of (offsets, targets, weights, n, m, source, dist_out)."""
+    arr = (SsspQuery * max(1, len(queries)))()
+    for i, (off, tg, wt, n, m, src, dist) in enumerate(queries):
+        arr[i] = SsspQuery(_ptr(off, 8), _ptr(tg, 4) if m else None, _ptr(wt, 4) if m else None, m, n, src,
+                           _ptr(dist, 8))
+    o = _opts(**kw)
+    s = SsspStats()
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sssp_batch(arr, len(queries), C.byref(o), C.byref(s), sp))
+    return _stats_dict(s)
 
 
 class Heap:

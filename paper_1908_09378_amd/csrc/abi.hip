@@ -7,8 +7,12 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <numeric>
+#include <vector>
 
 #include "../../include/pbh.h"
 #include "pbh_launch.h"
@@ -141,6 +145,27 @@ int state_error(const HeapState& s) {
   if (s.err) return fail(PBH_EINTERNAL, "device-side heap check failed (code %d)", s.err);
   return PBH_OK;
 }
+
+// k rule of sssp_opts -> SpecCfg (the list buffers are filled in by the caller).
+int spec_from_opts(const sssp_opts& o, u32 d, SpecCfg* sc, u32* kmax_out) {
+  std::memset(sc, 0, sizeof *sc);
+  if (o.k_rule > 3) return fail(PBH_EINVAL, "sssp: k_rule must be 0..3");
+  u32 kmax = o.k_max ? o.k_max : 2 * d;
+  if (kmax > (u32)KMAX_ROUND) kmax = KMAX_ROUND;
+  if (kmax < 1) kmax = 1;
+  sc->rule = (int)o.k_rule;
+  sc->kfix = o.k_fixed ? o.k_fixed : 1;
+  sc->kmax = kmax;
+  if (o.k_rule == 2 && !o.k_model) return fail(PBH_EINVAL, "sssp: k_rule 2 needs k_model");
+  if (o.k_rule == 3 && (!o.k_seq || o.k_seq_len == 0)) return fail(PBH_EINVAL, "sssp: k_rule 3 needs k_seq");
+  sc->kseq = o.k_seq;
+  sc->kseq_len = o.k_seq_len;
+  sc->model = o.k_model;
+  *kmax_out = kmax;
+  return PBH_OK;
+}
+
+bool spec_needs_list(const sssp_opts& o) { return o.k_rule != 0 || o.trace_features != nullptr; }
 
 }  // namespace
 
@@ -304,6 +329,7 @@ int pbh_debug_levels(pbh_t* h, uint32_t max_levels, uint32_t* levels_out, int32_
 
 static std::mutex g_sssp_mu;
 static Arena g_sssp_arena;        // reused across calls
+static Arena g_sssp_list;         // round update lists of speculative rounds
 static SsspDevStats* g_sssp_stats = nullptr;
 static CsrCheck* g_csr = nullptr;
 
@@ -359,6 +385,33 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       if (rc) return rc;
     }
     SsspParams p{};
+    u32 kmax = 1;
+    {
+      int rc = spec_from_opts(o, d, &p.spec, &kmax);
+      if (rc) return rc;
+    }
+    if (spec_needs_list(o)) {
+      u64 le = 2ull * kmax * (u64)d;
+      if (g_sssp_list.elems < le) {
+        arena_free(&g_sssp_list);
+        int rc = arena_alloc(&g_sssp_list, le);
+        if (rc) return rc;
+      }
+      p.spec.uk = g_sssp_list.k;
+      p.spec.uv = g_sssp_list.v;
+      p.spec.tk = g_sssp_list.k + (u64)kmax * d;
+      p.spec.tv = g_sssp_list.v + (u64)kmax * d;
+    }
+    if (o.trace_features) {
+      if (!o.trace_keys || !o.trace_ids || !o.trace_count || o.trace_every == 0)
+        return fail(PBH_EINVAL, "sssp: trace needs keys, ids, count and trace_every");
+      p.spec.trace_f = o.trace_features;
+      p.spec.trace_k = (u64*)o.trace_keys;
+      p.spec.trace_v = o.trace_ids;
+      p.spec.trace_count = o.trace_count;
+      p.spec.trace_every = o.trace_every;
+      p.spec.trace_cap = o.trace_cap;
+    }
     p.off = (const u64*)offsets;
     p.tg = targets;
     p.wt = weights;
@@ -398,6 +451,7 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       stats->relaxations = ds.relax;
       stats->updates = ds.updates;
       stats->heap_elems = ds.elems;
+      stats->extracted = ds.extracted;
       for (int i = 0; i < 16 && i < MAXL; ++i) stats->resolves[i] = ds.resolves[i];
       stats->levels = (u32)q;
       stats->d = d;
@@ -407,6 +461,241 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
     }
     return PBH_OK;
   }
+}
+
+// ------------------------------------------------------------ sssp_batch
+
+static Arena g_batch_arena;
+static Arena g_batch_list;
+static SsspParams* g_batch_desc = nullptr;
+static u32 g_batch_desc_cap = 0;
+static SsspDevStats* g_batch_stats = nullptr;
+static CsrCheck* g_batch_csr = nullptr;
+static u32 g_batch_csr_cap = 0;
+static u32* g_batch_counter = nullptr;
+
+int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, sssp_stats* stats, void* stream) {
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  if (nq == 0) return PBH_OK;
+  if (!queries) return fail(PBH_EINVAL, "sssp_batch: queries is NULL");
+  for (u32 i = 0; i < nq; ++i) {
+    const sssp_query& q = queries[i];
+    if (!q.offsets || !q.dist_out || (q.m > 0 && (!q.targets || !q.weights)))
+      return fail(PBH_EINVAL, "sssp_batch: query %u has a NULL array", i);
+    if (q.n == 0 || q.source >= q.n) return fail(PBH_EINVAL, "sssp_batch: query %u has n == 0 or source >= n", i);
+  }
+  sssp_opts o{};
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_sssp_mu);
+  // distinct graphs: validate each once and get its maximum out-degree
+  std::map<const uint64_t*, u32> gid;
+  std::vector<u32> qg(nq);
+  std::vector<u32> grep;
+  for (u32 i = 0; i < nq; ++i) {
+    auto it = gid.find(queries[i].offsets);
+    if (it == gid.end()) {
+      it = gid.emplace(queries[i].offsets, (u32)grep.size()).first;
+      grep.push_back(i);
+    }
+    qg[i] = it->second;
+  }
+  const u32 ng = (u32)grep.size();
+  if (ng > g_batch_csr_cap) {
+    if (g_batch_csr) (void)hipFree(g_batch_csr);
+    g_batch_csr = nullptr;
+    g_batch_csr_cap = 0;
+    HIPCHK(hipMalloc(&g_batch_csr, ng * sizeof(CsrCheck)));
+    g_batch_csr_cap = ng;
+  }
+  HIPCHK(hipMemsetAsync(g_batch_csr, 0, ng * sizeof(CsrCheck), s));
+  for (u32 k = 0; k < ng; ++k) {
+    const sssp_query& q = queries[grep[k]];
+    HIPCHK(launch_check_csr((const u64*)q.offsets, q.targets, q.n, q.m, g_batch_csr + k, s));
+  }
+  std::vector<CsrCheck> cc(ng);
+  HIPCHK(hipMemcpyAsync(cc.data(), g_batch_csr, ng * sizeof(CsrCheck), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (u32 i = 0; i < nq; ++i) {
+    const CsrCheck& c = cc[qg[i]];
+    if (c.bad) return fail(PBH_EINVAL, "sssp_batch: query %u: malformed CSR", i);
+    if (o.d && c.maxdeg > o.d) return fail(PBH_EINVAL, "sssp_batch: opts.d below a maximum out-degree");
+    // every query of a graph must agree on n and m
+    const sssp_query& r = queries[grep[qg[i]]];
+    if (queries[i].n != r.n || queries[i].m != r.m)
+      return fail(PBH_EINVAL, "sssp_batch: queries %u and %u share offsets but not n/m", i, grep[qg[i]]);
+  }
+  u32 dmax = 1;
+  std::vector<u32> qd(nq);
+  for (u32 i = 0; i < nq; ++i) {
+    u64 md = cc[qg[i]].maxdeg;
+    qd[i] = o.d ? o.d : (u32)(md ? md : 1);
+    dmax = std::max(dmax, qd[i]);
+  }
+  int team = (int)o.team;
+  if (team == 0) team = dmax <= 256 ? 64 : (dmax <= 4096 ? 256 : 1024);
+  if (team != 64 && team != 256 && team != 1024) return fail(PBH_EINVAL, "sssp_batch: team must be 64, 256 or 1024");
+  int dev = 0, max_lds = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // LDS per team: leave room for two teams per compute unit.
+  size_t budget = std::min((size_t)max_lds, (size_t)80 * 1024) - sssp_static_lds(team) - 256;
+  // order: largest graphs first (they have the longest round chains)
+  std::vector<u32> order(nq);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](u32 a, u32 b) { return queries[a].m > queries[b].m; });
+  std::vector<SsspParams> desc(nq);
+  std::vector<u64> gel(nq);
+  u64 total_gel = 0;
+  size_t lds = 0;
+  u32 maxn = 0;
+  for (u32 j = 0; j < nq; ++j) {
+    const u32 i = order[j];
+    const sssp_query& q = queries[i];
+    const u32 d = qd[i];
+    // The heap of one query holds its frontier plus copies awaiting deletion;
+    // start from max(4096, n) elements and rerun a query alone with the safe
+    // bound m + 1 if a level would overflow.
+    u64 hcap = o.heap_capacity ? o.heap_capacity : std::min<u64>(q.m + 1, std::max<u64>(4096, q.n));
+    int qv = levels_for(d, hcap, 2);
+    int qlds = 0;
+    if (o.lds_levels == 0) {
+      while (qlds < qv && lvl_off(d, qlds + 1) * 12ull <= budget) ++qlds;
+    } else if (o.lds_levels != 0xFFFFFFFFu) {
+      qlds = std::min((int)o.lds_levels, qv);
+      if (lvl_off(d, qlds) * 12ull > budget) return fail(PBH_EINVAL, "sssp_batch: LDS levels do not fit");
+    }
+    lds = std::max(lds, (size_t)(lvl_off(d, qlds) * 12ull));
+    gel[j] = lvl_off(d, qv) - lvl_off(d, qlds);
+    total_gel += gel[j];
+    maxn = std::max(maxn, q.n);
+    SsspParams& p = desc[j];
+    p.off = (const u64*)q.offsets;
+    p.tg = q.targets;
+    p.wt = q.weights;
+    p.dist = (u64*)q.dist_out;
+    p.n = q.n;
+    p.src = q.source;
+    p.sched = (int)o.schedule;
+    p.g.d = d;
+    p.g.q = qv;
+    p.g.qlds = qlds;
+  }
+  if (o.trace_features) return fail(PBH_EINVAL, "sssp_batch: traces are recorded by sssp_ex only");
+  std::vector<u64> lel(nq, 0);
+  u64 total_lel = 0;
+  for (u32 j = 0; j < nq; ++j) {
+    u32 kmax = 1;
+    int rc = spec_from_opts(o, desc[j].g.d, &desc[j].spec, &kmax);
+    if (rc) return rc;
+    if (spec_needs_list(o)) lel[j] = 2ull * kmax * desc[j].g.d;
+    total_lel += lel[j];
+  }
+  if (g_batch_list.elems < total_lel) {
+    arena_free(&g_batch_list);
+    int rc = arena_alloc(&g_batch_list, total_lel);
+    if (rc) return rc;
+  }
+  {
+    u64 lat = 0;
+    for (u32 j = 0; j < nq; ++j) {
+      if (!lel[j]) continue;
+      desc[j].spec.uk = g_batch_list.k + lat;
+      desc[j].spec.uv = g_batch_list.v + lat;
+      desc[j].spec.tk = g_batch_list.k + lat + lel[j] / 2;
+      desc[j].spec.tv = g_batch_list.v + lat + lel[j] / 2;
+      lat += lel[j];
+    }
+  }
+  if (g_batch_arena.elems < total_gel) {
+    arena_free(&g_batch_arena);
+    int rc = arena_alloc(&g_batch_arena, total_gel);
+    if (rc) return rc;
+  }
+  if (nq > g_batch_desc_cap) {
+    if (g_batch_desc) (void)hipFree(g_batch_desc);
+    if (g_batch_stats) (void)hipFree(g_batch_stats);
+    g_batch_desc = nullptr;
+    g_batch_stats = nullptr;
+    g_batch_desc_cap = 0;
+    HIPCHK(hipMalloc(&g_batch_desc, nq * sizeof(SsspParams)));
+    HIPCHK(hipMalloc(&g_batch_stats, nq * sizeof(SsspDevStats)));
+    g_batch_desc_cap = nq;
+  }
+  if (!g_batch_counter) HIPCHK(hipMalloc(&g_batch_counter, sizeof(u32)));
+  u64 at = 0;
+  for (u32 j = 0; j < nq; ++j) {
+    desc[j].g.gk = g_batch_arena.k + at;
+    desc[j].g.gv = g_batch_arena.v + at;
+    desc[j].stats = g_batch_stats + j;
+    at += gel[j];
+  }
+  HIPCHK(hipMemcpyAsync(g_batch_desc, desc.data(), nq * sizeof(SsspParams), hipMemcpyHostToDevice, s));
+  int occ = multi_occupancy(team, lds);
+  if (occ < 1) return fail(PBH_EDEVICE, "sssp_batch: kernel cannot be resident with %zu bytes of LDS", lds);
+  int grid = (int)std::min<u64>(nq, (u64)occ * (u64)cus);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(launch_fill_multi(g_batch_desc, nq, maxn, g_batch_counter, s));
+  HIPCHK(hipEventRecord(e0, s));
+  HIPCHK(launch_sssp_multi(team, g_batch_desc, nq, g_batch_counter, lds, grid, s));
+  HIPCHK(hipEventRecord(e1, s));
+  std::vector<SsspDevStats> ds(nq);
+  HIPCHK(hipMemcpyAsync(ds.data(), g_batch_stats, nq * sizeof(SsspDevStats), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::vector<u32> redo;
+  for (u32 j = 0; j < nq; ++j) {
+    if (ds[j].err == E_CAPACITY) {
+      redo.push_back(order[j]);
+    } else if (ds[j].err) {
+      return fail(PBH_EINTERNAL, "sssp_batch: query %u: device-side heap check failed (code %lld)", order[j],
+                  ds[j].err);
+    }
+  }
+  if (stats) {
+    for (u32 j = 0; j < nq; ++j) {
+      if (ds[j].err) continue;  // rerun below
+      stats->rounds += ds[j].rounds;
+      stats->relaxations += ds[j].relax;
+      stats->updates += ds[j].updates;
+      stats->heap_elems += ds[j].elems;
+      stats->extracted += ds[j].extracted;
+      for (int i = 0; i < 16 && i < MAXL; ++i) stats->resolves[i] += ds[j].resolves[i];
+    }
+    stats->levels = 0;
+    stats->d = dmax;
+    stats->team = (u32)team;
+    stats->lds_levels = (u32)(lds / 12);
+    stats->kernel_ms = ms;
+  }
+  // Queries whose heap outgrew its slice run again alone with the safe bound.
+  for (u32 i : redo) {
+    const sssp_query& q = queries[i];
+    sssp_opts o2 = o;
+    o2.d = qd[i];
+    o2.team = (u32)team;
+    o2.heap_capacity = q.m + 1;
+    sssp_stats s2;
+    g_sssp_mu.unlock();
+    int rc = sssp_ex(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, &o2, &s2, stream);
+    g_sssp_mu.lock();
+    if (rc) return rc;
+    if (stats) {
+      stats->rounds += s2.rounds;
+      stats->relaxations += s2.relaxations;
+      stats->updates += s2.updates;
+      stats->heap_elems += s2.heap_elems;
+      stats->extracted += s2.extracted;
+      stats->kernel_ms += s2.kernel_ms;
+    }
+  }
+  return PBH_OK;
 }
 
 int sssp(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,

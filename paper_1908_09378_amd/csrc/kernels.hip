@@ -49,13 +49,10 @@ __global__ void k_check_update(const u64* keys, const u32* ids, u64 count, u32 i
   if (b) atomicOr(bad, 1ull);
 }
 
+// One parDijkstra query on one team: heap state in LDS, levels 0..qlds-1 in
+// the dynamic LDS block, deeper levels in the query's slice of the HBM arena.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
-  extern __shared__ __align__(16) unsigned char dyn[];
-  __shared__ TeamShared<NT / 64> ts;
-  __shared__ HeapState st_lds;
-  HeapState PBH_LDS* st = (HeapState PBH_LDS*)&st_lds;
-  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+__device__ void sssp_query(DevTeam<NT>& t, HeapState PBH_LDS* st, unsigned char* dyn, const SsspParams& p) {
   Geom g = p.g;
   const u64 nl = lvl_off(g.d, g.qlds);
   g.lk = reinterpret_cast<u64*>(dyn);
@@ -63,18 +60,61 @@ __global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
   if (threadIdx.x == 0) state_init(st, g.d, g.q);
   t.sync();
   SsspCounters c;
-  sssp_rounds<DevTeam<NT>, DevPolicy>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, &c);
+  sssp_rounds<DevTeam<NT>, DevPolicy>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, p.spec, &c);
   t.sync();
   if (threadIdx.x == 0) {
     SsspDevStats* o = p.stats;
     o->rounds = c.rounds;
     o->relax = c.relax;
     o->updates = c.updates;
+    o->extracted = c.extracted;
     o->elems = st->elems;
     o->err = st->err;
     o->ell = st->ell;
     for (int i = 0; i < MAXL; ++i) o->resolves[i] = st->L[i].cnt;
   }
+  t.sync();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st_lds;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  sssp_query(t, (HeapState PBH_LDS*)&st_lds, dyn, p);
+}
+
+// Many independent queries in one launch: persistent teams take queries from
+// a counter (queries are ordered by decreasing size, so the long ones start
+// first); every team leaves once the counter passes the last query.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sssp_multi(const SsspParams* qs, u32 nq, u32* counter) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st_lds;
+  __shared__ u32 qnext;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  for (;;) {
+    if (threadIdx.x == 0) qnext = atomicAdd(counter, 1u);
+    t.sync();
+    const u32 qi = qnext;
+    t.sync();
+    if (qi >= nq) break;
+    const SsspParams p = qs[qi];
+    sssp_query(t, (HeapState PBH_LDS*)&st_lds, dyn, p);
+  }
+}
+
+// dist = INF except dist[src] = 0, for every query (blockIdx.y = query).
+__global__ void k_fill_multi(const SsspParams* qs, u32 nq, u32* counter) {
+  const u32 qi = blockIdx.y;
+  if (qi == 0 && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+  if (qi >= nq) return;
+  u64* dist = qs[qi].dist;
+  const u32 n = qs[qi].n, s = qs[qi].src;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    dist[i] = (i == s) ? 0ull : KINF;
 }
 
 template <int NT>
@@ -155,6 +195,45 @@ static hipError_t sssp_go(const SsspParams& p, size_t lds, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_sssp<NT>, dim3(1), dim3(NT), lds, s, p);
   return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t multi_go(const SsspParams* qs, u32 nq, u32* counter, size_t lds, int grid, hipStream_t s) {
+  if (lds > 65536 - sssp_static_lds(NT)) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_sssp_multi<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sssp_multi<NT>, dim3(grid), dim3(NT), lds, s, qs, nq, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_sssp_multi(int team, const SsspParams* qs, u32 nq, u32* counter, size_t lds, int grid,
+                             hipStream_t s) {
+  switch (team) {
+    case 64: return multi_go<64>(qs, nq, counter, lds, grid, s);
+    case 256: return multi_go<256>(qs, nq, counter, lds, grid, s);
+    case 1024: return multi_go<1024>(qs, nq, counter, lds, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill_multi(const SsspParams* qs, u32 nq, u32 maxn, u32* counter, hipStream_t s) {
+  u32 bx = (maxn + 255) / 256;
+  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+  hipLaunchKernelGGL(k_fill_multi, dim3(bx, nq > 0 ? nq : 1), dim3(256), 0, s, qs, nq, counter);
+  return hipGetLastError();
+}
+
+int multi_occupancy(int team, size_t lds) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (team) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sssp_multi<64>, 64, lds); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sssp_multi<256>, 256, lds); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sssp_multi<1024>, 1024, lds); break;
+  }
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s) {

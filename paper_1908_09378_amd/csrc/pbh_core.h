@@ -829,9 +829,6 @@ PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur,
 }
 
 // ---------------------------------------------------------------- parDijkstra
-struct SsspCounters {
-  u64 rounds, relax, updates;
-};
 
 PBH_HD inline int bits_for(u32 n) {
   int b = 0;
@@ -936,12 +933,320 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
   return true;
 }
 
+// ------------------------------------------------------------ speculative rounds
+// A round may extract the k >= 1 smallest live elements of B_0 instead of one
+// (the plain rule of Section 4.1 is k = 1).  All out-edges of the k vertices
+// are relaxed; any vertex whose distance later improves is re-inserted into the
+// heap and relaxed again, so the distances are exact for every choice of k.
+// The k of each round comes from a rule: plain, fixed, a given sequence, or a
+// small learned model (see mlp_forward).
+
+constexpr int KMAX_ROUND = 256;  // cap on k per round (extracted vertices kept in LDS)
+constexpr int TRACE_K = 32;      // key-ordered prefix of B_0 recorded per traced round
+constexpr int NFEAT = 8;
+constexpr int MLP_H = 64;
+// MLP parameters (float32, weights already rounded to bfloat16), in order:
+// W1[NFEAT][MLP_H] (input-major), b1[MLP_H], W2[MLP_H][MLP_H] (input-major),
+// b2[MLP_H], w3[MLP_H], b3, then the feature normalisation mu[NFEAT],
+// sd[NFEAT] and the output scale s (k = 2^(s * y)).
+constexpr int MLP_PARAMS = NFEAT * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;
+constexpr int MLP_BLOB = MLP_PARAMS + 2 * NFEAT + 1;
+
+struct SpecCfg {
+  int rule;           // 0 plain, 1 fixed, 2 learned, 3 sequence
+  u32 kfix, kmax;
+  const u32* kseq;
+  u32 kseq_len;
+  const float* model;  // MLP_BLOB floats (learned rule)
+  u64* uk;             // round update list (capacity kmax * d) and a temporary of the same size
+  u32* uv;
+  u64* tk;
+  u32* tv;
+  // training traces: every trace_every-th round records NFEAT features and the
+  // TRACE_K smallest (key, id) of B_0 in key order
+  float* trace_f;
+  u64* trace_k;
+  u32* trace_v;
+  u32 trace_every, trace_cap;
+  u32* trace_count;
+};
+
+struct SsspCounters {
+  u64 rounds, relax, updates, extracted;
+};
+
+struct RoundMemo {  // team-uniform facts about the previous round
+  float avgdeg;
+};
+
+PBH_INL float flog2p1(float x) { return __builtin_log2f(1.0f + x); }
+
+// The 8 model features, identical in plain and speculative runs: heap size,
+// |B_0|, key spread of B_0, the pivots p_0 and p_1 relative to the minimum
+// key (a quantile sketch of the queue: the level boundaries), the minimum key
+// itself, the mean out-degree of the previous round's vertices, and d.
+template <class T, class SP, class A0>
+PBH_INL void round_features(const T& t, const Geom& g, SP st, A0 B, u32 nB, const RoundMemo& memo, float* f) {
+  u64 lo = KINF, hi = 0;
+  for (u32 x = (u32)t.tid(); x < nB; x += (u32)T::kNT) {
+    u64 k = B.k[x];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  t.minmax64(lo, hi);
+  u64 tot = 0;
+  for (int i = 0; i < g.q; ++i) tot += (u64)st->L[i].nB + st->L[i].nS;
+  const float spread = (float)(hi - lo);
+  f[0] = flog2p1((float)tot);
+  f[1] = flog2p1((float)nB);
+  f[2] = flog2p1(spread);
+  const u64 p0 = st->L[0].pk, p1 = st->L[1].pk;
+  f[3] = p0 == KINF ? f[2] + 1.0f : flog2p1((float)(p0 - lo));
+  f[4] = (g.q < 2 || p1 == KINF) ? f[3] + 1.0f : flog2p1((float)(p1 - lo));
+  f[5] = flog2p1((float)lo) * 0.125f;
+  f[6] = flog2p1(memo.avgdeg);
+  f[7] = flog2p1((float)g.d);
+}
+
+// Rounds a float to bfloat16 (round to nearest even) and back: the model's
+// weights are used at BF16 precision with FP32 accumulation.
+PBH_INL float bf16r(float x) {
+  u32 u = __builtin_bit_cast(u32, x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(float, u & 0xFFFF0000u);
+}
+
+PBH_INL float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+// MLP 8 -> 64 -> 64 -> 1 with GELU (exact, x * Phi(x)); thread j computes
+// hidden unit j of each layer (weights stored input-major, so the loads of
+// one input row are contiguous), the output is reduced through LDS.  BF16
+// weights, FP32 accumulation.  Returns y (k = 2^(s * y)).
+template <class T>
+PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
+  const float* W1 = m;
+  const float* b1 = W1 + NFEAT * MLP_H;
+  const float* W2 = b1 + MLP_H;
+  const float* b2 = W2 + MLP_H * MLP_H;
+  const float* w3 = b2 + MLP_H;
+  const float* b3 = w3 + MLP_H;
+  const float* mu = b3 + 1;
+  const float* sd = mu + NFEAT;
+  float x[NFEAT];
+#pragma unroll
+  for (int i = 0; i < NFEAT; ++i) x[i] = (f[i] - mu[i]) / sd[i];
+  for (int j = t.tid(); j < MLP_H; j += T::kNT) {
+    float a = b1[j];
+#pragma unroll
+    for (int i = 0; i < NFEAT; ++i) a += bf16r(W1[i * MLP_H + j]) * x[i];
+    t.sh->mlp_h[j] = gelu(a);
+  }
+  t.sync();
+  for (int j = t.tid(); j < MLP_H; j += T::kNT) {
+    float a = b2[j];
+    for (int i = 0; i < MLP_H; ++i) a += bf16r(W2[i * MLP_H + j]) * t.sh->mlp_h[i];
+    t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
+  }
+  t.sync();
+  float y = b3[0];
+  for (int j = 0; j < MLP_H; ++j) y += t.sh->mlp_z[j];
+  t.sync();
+  return y * sd[NFEAT];
+}
+
+template <class T, class SP, class A0>
+PBH_INL u32 propose_k(const T& t, const Geom& g, SP st, const SpecCfg& sc, A0 B, u32 nB, u64 round,
+                      const RoundMemo& memo) {
+  u32 k = 1;
+  if (sc.rule == 1) {
+    k = sc.kfix;
+  } else if (sc.rule == 3) {
+    k = sc.kseq[round % sc.kseq_len];
+  } else if (sc.rule == 2) {
+    float f[NFEAT];
+    round_features(t, g, st, B, nB, memo, f);
+    float y = mlp_forward(t, sc.model, f);
+    // fall back to the plain rule on anything that is not a finite number
+    if (y == y && y > -64.0f && y < 64.0f) {
+      float kk = __builtin_exp2f(y);
+      k = kk < 1.0f ? 1u : (kk > (float)sc.kmax ? sc.kmax : (u32)(kk + 0.5f));
+    }
+  }
+  k = k < 1 ? 1 : k;
+  k = k > sc.kmax ? sc.kmax : k;
+  return k > (u32)KMAX_ROUND ? (u32)KMAX_ROUND : k;
+}
+
+// Records one training trace: features and the TRACE_K smallest (key, id) of
+// B_0 in key order (by repeated team minima; traced rounds are sparse).
+template <class T, class SP, class A0>
+PBH_INL void record_trace(const T& t, const Geom& g, SP st, const SpecCfg& sc, A0 B, u32 nB,
+                          const RoundMemo& memo) {
+  float f[NFEAT];
+  round_features(t, g, st, B, nB, memo, f);
+  u32 slot = 0;
+  if (t.tid() == 0) slot = (*sc.trace_count)++;
+  slot = t.sum(slot);
+  if (slot >= sc.trace_cap) return;
+  if (t.tid() == 0)
+    for (int i = 0; i < NFEAT; ++i) sc.trace_f[(u64)slot * NFEAT + i] = f[i];
+  u64 lastk = 0;
+  u32 lastv = 0;
+  bool have = false;
+  for (int r = 0; r < TRACE_K; ++r) {
+    u64 bk = KINF;
+    u32 bv = VINF;
+    for (u32 x = (u32)t.tid(); x < nB; x += (u32)T::kNT) {
+      u64 k = B.k[x];
+      u32 v = B.v[x];
+      bool after = !have || k > lastk || (k == lastk && v > lastv);
+      if (after && (k < bk || (k == bk && v < bv))) {
+        bk = k;
+        bv = v;
+      }
+    }
+    t.minkv(bk, bv);
+    if (t.tid() == 0) {
+      sc.trace_k[(u64)slot * TRACE_K + r] = bk;
+      sc.trace_v[(u64)slot * TRACE_K + r] = bv;
+    }
+    lastk = bk;
+    lastv = bv;
+    have = true;
+  }
+  t.sync();
+}
+
+// Round update list U (n pairs, global) -> one pair per id, sorted by id: keep
+// the pairs whose key equals dist[id] (the minimum, by atomicMin), sort by id,
+// drop equal neighbours (equal candidates from two sources).
+template <class T, class GA>
+PBH_INL u32 intake_list(const T& t, GA U, u32 n, GA W, const u64* dist, int idbits) {
+  u32 out = 0;
+  for (u32 base = 0; base < n; base += (u32)T::kNT) {
+    u32 x = base + (u32)t.tid();
+    bool keep = x < n && t.load_cur(dist + U.v[x]) == U.k[x];
+    u64 k = x < n ? U.k[x] : 0;
+    u32 v = x < n ? U.v[x] : 0;
+    u32 tot;
+    u32 o = out + t.scan_excl(keep ? 1u : 0u, &tot);
+    if (keep) {
+      W.k[o] = k;
+      W.v[o] = v;
+    }
+    out += tot;
+  }
+  t.sync();
+  bool inU = sort_by_id(t, W, U, out, idbits);
+  GA S = inU ? U : W, D = inU ? W : U;
+  u32 m = 0;
+  for (u32 base = 0; base < out; base += (u32)T::kNT) {
+    u32 x = base + (u32)t.tid();
+    bool keep = x < out && (x == 0 || S.v[x - 1] != S.v[x]);
+    u64 k = x < out ? S.k[x] : 0;
+    u32 v = x < out ? S.v[x] : 0;
+    u32 tot;
+    u32 o = m + t.scan_excl(keep ? 1u : 0u, &tot);
+    if (keep) {
+      D.k[o] = k;
+      D.v[o] = v;
+    }
+    m += tot;
+  }
+  t.sync();
+  if (!inU) copy_arr(t, D, U, m);  // result always in U
+  return m;
+}
+
+// One speculative round: extract the `k` smallest of B_0, relax every out-edge
+// of them, collect the improved (dist, v) pairs in the global list U.
+template <class T, class P, class A0>
+PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
+                        const u32* wt, u64* dist, int idbits, u32 k, const SpecCfg& sc, SsspCounters* c,
+                        RoundMemo* memo, u32* ulen) {
+  using G = typename P::G;
+  const Lvl a0 = lvl_load(st, 0);
+  if (a0.nB == 0) return false;
+  A0 B = as_arr<A0>(lbuf(g, 0, a0.bsel));
+  const u32 take = k < a0.nB ? k : a0.nB;
+  KV thr = take == a0.nB ? kv_inf() : select_kth(t, B, a0.nB, take);
+  u32 n0, n1, n2;
+  A0 X = as_arr<A0>(lbuf(g, 0, 2));
+  partition3(t, B, a0.nB, thr, kv_inf(), X, as_arr<A0>(lbuf(g, 0, a0.bsel ^ 1)), X, &n0, &n1, &n2);
+  // out-degree prefix sums of the extracted vertices
+  u32 E = 0;
+  for (u32 base = 0; base < take; base += (u32)T::kNT) {
+    u32 j = base + (u32)t.tid();
+    u64 e0 = 0, e1 = 0;
+    if (j < take) {
+      u32 v = X.v[j];
+      e0 = off[v];
+      e1 = off[v + 1];
+      t.sh->ex0[j] = e0;
+    }
+    u32 tot;
+    u32 p = E + t.scan_excl((u32)(e1 - e0), &tot);
+    if (j < take) t.sh->exd[j] = p;
+    E += tot;
+  }
+  if (t.tid() == 0) t.sh->exd[take] = E;
+  t.sync();
+  G U{(decltype(G::k))sc.uk, (decltype(G::v))sc.uv};
+  u32 nu = 0;
+  for (u32 eb = 0; eb < E; eb += (u32)T::kNT) {
+    u32 e = eb + (u32)t.tid();
+    bool imp = false;
+    u64 cand = 0;
+    u32 v = 0;
+    if (e < E) {
+      u32 lo = 0, hi = take;  // largest j with exd[j] <= e
+      while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (t.sh->exd[mid] <= e)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      u64 ei = t.sh->ex0[lo] + (e - t.sh->exd[lo]);
+      v = tg[ei];
+      cand = X.k[lo] + (u64)wt[ei];
+      imp = cand < t.atomic_min(dist + v, cand);
+    }
+    u32 tot;
+    u32 p = t.scan_excl(imp ? 1u : 0u, &tot);
+    if (imp) {
+      U.k[nu + p] = cand;
+      U.v[nu + p] = v;
+    }
+    nu += tot;
+  }
+  t.sync();
+  G Wt{(decltype(G::k))sc.tk, (decltype(G::v))sc.tv};
+  nu = intake_list(t, U, nu, Wt, dist, idbits);
+  if (t.tid() == 0) {
+    st->L[0].bsel = a0.bsel ^ 1;
+    st->L[0].nB = n1;
+    st->elems += 3ull * a0.nB + 3ull * nu;
+    if (st->ell < 0 && n1 > 0) st->ell = 0;
+  }
+  t.sync();
+  c->relax += E;
+  c->updates += nu;
+  c->extracted += take;
+  memo->avgdeg = (float)E / (float)take;
+  *ulen = nu;
+  return true;
+}
+
 // parDijkstra: rounds until the heap is empty.  The extraction and the bulk
 // update of a round share one Resolve(0) and the schedule: between them S_0 is
 // empty and B_0 keeps at least d elements, so Algorithm 1's preconditions hold.
+// Speculative rounds bulk-update their list U in pieces of at most d, each
+// piece an operation followed by Resolve(0) and the schedule.
 template <class T, class P>
 PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
-                         const u32* wt, u64* dist, u32 n, u32 src, int sched, SsspCounters* cnt) {
+                         const u32* wt, u64* dist, u32 n, u32 src, int sched, const SpecCfg& sc, SsspCounters* cnt) {
+  using G = typename P::G;
   const int idbits = bits_for(n);
   if (t.tid() == 0) {
     Arr S = lbuf(g, 0, 3);
@@ -959,28 +1264,74 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     st->ell = 0;
   }
   t.sync();
-  u64 rounds = 0, relax = 0, upd = 1;
+  SsspCounters c{0, 0, 1, 0};
+  RoundMemo memo{0.0f};
+  u32 upos = 0, ulen = 0;
   for (;;) {
     // Resolve(0) and the schedule after the previous operation (the source's
-    // insertion, or the last round's bulk update), then make sure B_0 holds
-    // the minimum if the heap is not empty.
+    // insertion, a round's bulk update or a piece of it), then make sure B_0
+    // holds the minimum if the heap is not empty.
     drive<T, P>(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
     if (st->err) break;
+    if (upos < ulen) {  // next piece of the round's bulk update
+      u32 len = ulen - upos < g.d ? ulen - upos : g.d;
+      G U{(decltype(G::k))sc.uk, (decltype(G::v))sc.uv};
+      if (g.qlds > 0) {
+        typename P::L S = as_arr<typename P::L>(lbuf(g, 0, 3));
+        for (u32 x = (u32)t.tid(); x < len; x += (u32)T::kNT) {
+          S.k[x] = U.k[upos + x];
+          S.v[x] = U.v[upos + x];
+        }
+      } else {
+        G S = as_arr<G>(lbuf(g, 0, 3));
+        for (u32 x = (u32)t.tid(); x < len; x += (u32)T::kNT) {
+          S.k[x] = U.k[upos + x];
+          S.v[x] = U.v[upos + x];
+        }
+      }
+      t.sync();
+      if (t.tid() == 0) {
+        st->L[0].nS = len;
+        st->L[0].ssel = 0;
+        if (st->ell < 0) st->ell = 0;
+      }
+      t.sync();
+      upos += len;
+      continue;
+    }
     // Every extraction consumes one insertion and every insertion comes from
     // one scanned edge (or the source), so rounds <= 1 + relax always holds.
-    if (rounds > relax + 1) {
+    if (c.rounds > c.relax + 1) {
       if (t.tid() == 0) st->err = E_INTERNAL;
       t.sync();
       break;
     }
-    bool more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &relax, &upd)
-                           : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &relax, &upd);
+    bool more;
+    if (sc.rule == 0 && !sc.trace_f) {
+      more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates)
+                        : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates);
+      c.extracted += more ? 1 : 0;
+    } else {
+      const Lvl a0 = lvl_load(st, 0);
+      Arr Bg = lbuf(g, 0, a0.bsel);
+      u32 k;
+      if (g.qlds > 0) {
+        typename P::L B = as_arr<typename P::L>(Bg);
+        if (sc.trace_f && a0.nB && c.rounds % sc.trace_every == 0) record_trace(t, g, st, sc, B, a0.nB, memo);
+        k = propose_k(t, g, st, sc, B, a0.nB, c.rounds, memo);
+        more = round_spec<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, k, sc, &c, &memo, &ulen);
+      } else {
+        G B = as_arr<G>(Bg);
+        if (sc.trace_f && a0.nB && c.rounds % sc.trace_every == 0) record_trace(t, g, st, sc, B, a0.nB, memo);
+        k = propose_k(t, g, st, sc, B, a0.nB, c.rounds, memo);
+        more = round_spec<T, P, G>(t, g, st, off, tg, wt, dist, idbits, k, sc, &c, &memo, &ulen);
+      }
+      upos = 0;
+    }
     if (!more) break;
-    ++rounds;
+    ++c.rounds;
   }
-  cnt->rounds = rounds;
-  cnt->relax = relax;
-  cnt->updates = upd;
+  *cnt = c;
 }
 
 // ---------------------------------------------------------------- pbh_* calls

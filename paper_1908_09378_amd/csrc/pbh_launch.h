@@ -8,7 +8,7 @@ namespace bkt {
 
 // Device statistics block written by the SSSP kernel.
 struct SsspDevStats {
-  u64 rounds, relax, updates, elems;
+  u64 rounds, relax, updates, elems, extracted;
   long long err;
   long long ell;
   u64 resolves[MAXL];
@@ -24,6 +24,7 @@ struct SsspParams {
   int sched;
   Geom g;  // lk/lv are set inside the kernel
   SsspDevStats* stats;
+  SpecCfg spec;
 };
 
 
@@ -36,6 +37,10 @@ hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s);
 hipError_t launch_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out, hipStream_t s);
 hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s);
 size_t sssp_static_lds(int team);
+hipError_t launch_sssp_multi(int team, const SsspParams* qs, u32 nq, u32* counter, size_t lds, int grid,
+                             hipStream_t s);
+hipError_t launch_fill_multi(const SsspParams* qs, u32 nq, u32 maxn, u32* counter, hipStream_t s);
+int multi_occupancy(int team, size_t lds);
 hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s);
 hipError_t launch_pbh_extract(const PbhParams& p, hipStream_t s);
 hipError_t launch_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad,

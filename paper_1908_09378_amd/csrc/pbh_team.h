@@ -34,6 +34,10 @@ struct TeamShared {
   u32 base[256];
   u32 wcnt[NW][256];
   u32 b32[4];
+  u64 ex0[256];  // first edge of each vertex extracted in a round
+  u32 exd[257];  // prefix sums of their out-degrees
+  float mlp_h[64];
+  float mlp_z[64];
 };
 
 // DPP lane moves (gfx9 encodings): row_shr:n = 0x110 + n within rows of 16

@@ -5,6 +5,7 @@
 // operation scripts through the exact schedule, capacity and growth logic.
 // It is not part of the library and the library never calls it; results from
 // here are checked against the oracle like any other implementation.
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -165,7 +166,8 @@ int hm_level_items(void* hp, int i, u64* bk, u32* bv, u64* sk, u32* sv) {
 // separate buffer, standing in for LDS.  stats: rounds, relaxations, updates,
 // heap element touches, levels, resolves[0..15].
 int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src, u64* dist, u32 d_opt,
-            int sched, u64 hcap, int qlds, u64* stats) {
+            int sched, u64 hcap, int qlds, u64* stats, int rule, u32 kfix, u32 kmax, const u32* kseq, u32 kseq_len,
+            const float* model) {
   u64 md = 0;
   for (u32 u = 0; u < n; ++u) md = off[u + 1] - off[u] > md ? off[u + 1] - off[u] : md;
   u32 d = d_opt ? d_opt : (u32)(md ? md : 1);
@@ -188,14 +190,30 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   HostTeam t{&ts};
   for (u32 v = 0; v < n; ++v) dist[v] = KINF;
   dist[src] = 0;
+  SpecCfg sc;
+  std::memset(&sc, 0, sizeof sc);
+  sc.rule = rule;
+  sc.kfix = kfix ? kfix : 1;
+  sc.kmax = kmax ? kmax : 2 * d;
+  if (sc.kmax > (u32)KMAX_ROUND) sc.kmax = KMAX_ROUND;
+  sc.kseq = kseq;
+  sc.kseq_len = kseq_len;
+  sc.model = model;
+  std::vector<u64> uk(2ull * sc.kmax * d);
+  std::vector<u32> uv(2ull * sc.kmax * d);
+  sc.uk = uk.data();
+  sc.uv = uv.data();
+  sc.tk = uk.data() + (u64)sc.kmax * d;
+  sc.tv = uv.data() + (u64)sc.kmax * d;
   SsspCounters c;
-  sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, &c);
+  sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
   stats[0] = c.rounds;
   stats[1] = c.relax;
   stats[2] = c.updates;
   stats[3] = st.elems;
   stats[4] = (u64)q;
   for (int i = 0; i < MAXL; ++i) stats[5 + i] = st.L[i].cnt;
+  stats[21] = c.extracted;
   return st.err;
 }
 

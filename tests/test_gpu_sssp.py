@@ -102,3 +102,77 @@ def test_invalid_inputs():
     badoff[2], badoff[3] = badoff[3], badoff[2]
     with pytest.raises(pkg.PBHError):
         pkg.sssp(dev64(badoff), tg, wt, g.n, g.m, 0, dist)
+
+
+def _batch_check(graphs_sources, **kw):
+    import torch
+    from gpu_util import DEV, graph_to_dev, host64
+    qs, refs, keep = [], [], []
+    for g, srcs in graphs_sources:
+        off, tg, wt = graph_to_dev(g)
+        keep.append((off, tg, wt))
+        for s in srcs:
+            dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+            qs.append((off, tg, wt, g.n, g.m, s, dist))
+            refs.append(oracle.dijkstra(g, s, want_order=True))
+    print(f"[batch] {len(qs)} queries {kw}", flush=True)
+    st = pkg.sssp_batch(qs, **kw)
+    for q, (ref, order, nrelax) in zip(qs, refs):
+        got = host64(q[6])
+        assert np.array_equal(got, ref), f"{int((got != ref).sum())} distances differ"
+    assert st["rounds"] == sum(r[1].shape[0] for r in refs)
+    assert st["relaxations"] == sum(r[2] for r in refs)
+    return st
+
+
+def test_batch_mixed_graphs():
+    gs = [(W.rgg(4096 + 1000 * i, seed=20 + i), [0, 7, 100 + i, 4095]) for i in range(6)]
+    gs.append((W.grid4(64, 64, 1, 100, seed=1), [0, 4095]))
+    gs.append((W.random_graph(300, 3000, 0, 5, seed=3), [0, 1, 2]))
+    gs.append((W.path_graph(50, seed=2), [0, 49]))
+    _batch_check(gs)
+
+
+@pytest.mark.parametrize("kw", [dict(team=256), dict(lds_levels=0xFFFFFFFF), dict(schedule=1),
+                                dict(heap_capacity=64)])
+def test_batch_options(kw):
+    gs = [(W.rgg(3000 + 500 * i, seed=40 + i), [0, 11]) for i in range(4)]
+    gs.append((W.ring_lattice(2048, 16, 1, 1000, seed=5), [0, 1000]))
+    _batch_check(gs, **kw)
+
+
+def test_batch_many_queries_more_than_resident():
+    g = W.grid4(16, 16, 1, 100, seed=9)
+    _batch_check([(g, list(range(0, 256, 1)))] * 1 + [(W.rgg(2048, seed=8), list(range(0, 2048, 2)))])
+
+
+@pytest.mark.parametrize("gname", ["grid", "ring", "rgg", "multi"])
+@pytest.mark.parametrize("rule", ["fixed3", "fixed64", "seq"])
+def test_speculative_rounds_exact(gname, rule):
+    import torch
+    from gpu_util import dev32
+    g = {"grid": lambda: W.grid4(64, 64, 1, 100, seed=1), "ring": lambda: W.ring_lattice(1 << 13, 16, 1, 1000, seed=2),
+         "rgg": lambda: W.rgg(1 << 13, seed=3), "multi": lambda: W.random_graph(2000, 20000, 0, 9, seed=4)}[gname]()
+    kw = {"fixed3": dict(k_rule=1, k_fixed=3), "fixed64": dict(k_rule=1, k_fixed=64, k_max=64),
+          "seq": dict(k_rule=3, k_seq=dev32(np.array([1, 17, 2, 250, 5, 1, 64], np.uint32)), k_max=256)}[rule]
+    print(f"[spec] {g.name} {rule}", flush=True)
+    ref, order, _ = oracle.dijkstra(g, 0, want_order=True)
+    got, st = run_sssp(pkg, g, 0, **kw)
+    assert np.array_equal(got, ref)
+    assert st["extracted"] >= order.shape[0]
+
+
+def test_batch_speculative_exact():
+    import torch
+    from gpu_util import DEV, graph_to_dev, host64
+    gs = [(W.rgg(3000 + 700 * i, seed=60 + i), [0, 5]) for i in range(5)]
+    qs, refs, keep = [], [], []
+    for g, srcs in gs:
+        off, tg, wt = graph_to_dev(g)
+        keep.append((off, tg, wt))
+        for s in srcs:
+            qs.append((off, tg, wt, g.n, g.m, s, torch.empty(g.n, dtype=torch.int64, device=DEV)))
+            refs.append(oracle.dijkstra(g, s))
+    pkg.sssp_batch(qs, k_rule=1, k_fixed=8)
+    for q, ref in zip(qs, refs):
+        assert np.array_equal(host64(q[6]), ref)

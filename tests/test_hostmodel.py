@@ -154,3 +154,36 @@ def test_sssp_small_capacity_reports_capacity():
     assert rc in (0, -2)
     if rc == 0:
         assert np.array_equal(dist, oracle.dijkstra(g, 0))
+
+
+# ---------------------------------------------------------------- speculative rounds
+@pytest.mark.parametrize("gi", range(18))
+@pytest.mark.parametrize("kcase", ["fixed4", "fixed64", "random", "adversarial"])
+def test_speculative_rounds_exact_for_any_k(gi, kcase):
+    """Rounds that extract k > 1 minima re-insert improved vertices, so the
+    distances equal the oracle's for every k-sequence."""
+    g = list(_graphs())[gi]
+    src = (gi * 5) % g.n
+    ref, order, _ = oracle.dijkstra(g, src, want_order=True)
+    rng = np.random.default_rng(gi)
+    if kcase == "fixed4":
+        rc, dist, st = hm_sssp(g, src, rule=1, kfix=4)
+    elif kcase == "fixed64":
+        rc, dist, st = hm_sssp(g, src, rule=1, kfix=64, kmax=64)
+    elif kcase == "random":
+        rc, dist, st = hm_sssp(g, src, rule=3, kseq=rng.integers(1, 40, size=97), kmax=256)
+    else:  # alternate huge pulls with single ones
+        rc, dist, st = hm_sssp(g, src, rule=3, kseq=[256, 1, 1, 256, 3], kmax=256)
+    assert rc == 0
+    assert np.array_equal(dist, ref)
+    assert st["extracted"] >= order.shape[0]       # every reached vertex is extracted at least once
+    if kcase == "fixed4":
+        assert st["rounds"] <= order.shape[0]
+
+
+def test_rule_fixed_one_equals_plain_counts():
+    g = W.grid4(20, 20, 1, 100, seed=3)
+    rc0, d0, s0 = hm_sssp(g, 0)
+    rc1, d1, s1 = hm_sssp(g, 0, rule=1, kfix=1)
+    assert rc0 == rc1 == 0 and np.array_equal(d0, d1)
+    assert s0["rounds"] == s1["rounds"] == s1["extracted"] and s0["relax"] == s1["relax"]

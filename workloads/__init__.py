@@ -17,6 +17,7 @@ CSR layout used everywhere: ``offsets`` uint64[n+1], ``targets`` uint32[m],
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -98,7 +99,16 @@ def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray, name
     src = np.asarray(src, dtype=np.uint64)
     dst = np.asarray(dst, dtype=np.uint64)
     w = np.asarray(w, dtype=np.uint32)
-    order = np.lexsort((w, dst, src))
+    if n <= (1 << 31):
+        key = src * np.uint64(n) + dst
+        order = np.argsort(key, kind="stable")
+        # equal (src, dst) pairs (multi-edges) are ordered by weight
+        ks = key[order]
+        dup = np.nonzero(ks[1:] == ks[:-1])[0]
+        if dup.size:
+            order = np.lexsort((w, dst, src))
+    else:
+        order = np.lexsort((w, dst, src))
     src, dst, w = src[order], dst[order], w[order]
     counts = np.bincount(src.astype(np.int64), minlength=n).astype(np.uint64)
     offsets = np.zeros(n + 1, dtype=np.uint64)
@@ -204,7 +214,8 @@ def rgg(n: int, mean_degree: float = 24.0, seed: int = 9) -> Graph:
     """Random geometric graph: n points uniform in the unit square, an undirected
     edge between points closer than r = sqrt(mean_degree / (pi n)), both
     directions, weight round(1000 * length) + 1.  Neighbours are found by
-    binning points into cells of side r."""
+    binning points into cells of side >= r and testing each pair of points in
+    the same or adjacent cells once."""
     s = stream_seed(seed, 8)
     xy = rand_unit(s, np.arange(2 * n, dtype=np.uint64)).reshape(n, 2)
     r = math.sqrt(mean_degree / (math.pi * n))
@@ -214,28 +225,32 @@ def rgg(n: int, mean_degree: float = 24.0, seed: int = 9) -> Graph:
     order = np.argsort(cid, kind="stable")
     cid_sorted = cid[order]
     starts = np.searchsorted(cid_sorted, np.arange(g * g + 1))
+    cs = cell[order]
     srcs, dsts = [], []
-    for dx in (-1, 0, 1):
-        for dy in (-1, 0, 1):
-            nx = cell[:, 0] + dx
-            ny = cell[:, 1] + dy
-            ok = (nx >= 0) & (nx < g) & (ny >= 0) & (ny < g)
-            pts = np.nonzero(ok)[0]
-            nc = nx[pts] * g + ny[pts]
-            lo = starts[nc]
-            hi = starts[nc + 1]
-            cnt = hi - lo
-            rep = np.repeat(pts, cnt)
-            idx = np.repeat(lo - np.cumsum(np.concatenate([[0], cnt[:-1]])), cnt) + np.arange(cnt.sum())
-            cand = order[idx]
+    # half stencil: same cell (pairs i < j) and 4 of the 8 neighbour cells
+    for dx, dy in ((0, 0), (0, 1), (1, -1), (1, 0), (1, 1)):
+        nx = cs[:, 0] + dx
+        ny = cs[:, 1] + dy
+        ok = (nx >= 0) & (nx < g) & (ny >= 0) & (ny < g)
+        pts = np.nonzero(ok)[0]
+        nc = nx[pts] * g + ny[pts]
+        lo = starts[nc]
+        cnt = starts[nc + 1] - lo
+        tot = int(cnt.sum())
+        rep = np.repeat(pts, cnt)
+        first = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
+        cand = first + np.arange(tot, dtype=np.int64)
+        if dx == 0 and dy == 0:
             keep = rep < cand
-            srcs.append(rep[keep])
-            dsts.append(cand[keep])
+            rep, cand = rep[keep], cand[keep]
+        a, b = order[rep], order[cand]
+        d2 = ((xy[a] - xy[b]) ** 2).sum(axis=1)
+        keep = d2 < r * r
+        srcs.append(a[keep])
+        dsts.append(b[keep])
     a = np.concatenate(srcs)
     b = np.concatenate(dsts)
     d = np.sqrt(((xy[a] - xy[b]) ** 2).sum(axis=1))
-    keep = d < r
-    a, b, d = a[keep], b[keep], d[keep]
     w = (np.rint(1000.0 * d) + 1).astype(np.uint32)
     return _undirected(n, a.astype(np.uint64), b.astype(np.uint64), w, f"rgg_{n}")
 
@@ -332,3 +347,35 @@ def random_script(n_ops: int, id_cap: int, max_batch: int, key_max: int, seed: i
             ctr += 1
             ops.append(("extract", k))
     return ops
+
+
+def _rgg_item(args):
+    gi, n, seed, k = args
+    g = rgg(n, 24.0, seed=seed * 1000 + gi)
+    s2 = stream_seed(seed * 1000 + gi, 41)
+    src = []
+    c = 0
+    while len(src) < min(k, n):
+        v = int(rand_int(s2, np.array([c], np.uint64), 0, n - 1)[0])
+        c += 1
+        if v not in src:
+            src.append(v)
+    return g, src
+
+
+def rgg_batch(n_graphs: int = 64, sources_per_graph: int = 4, lo_log2: int = 12, hi_log2: int = 18,
+              seed: int = 50, workers: int = 8):
+    """The multi-source workload: n_graphs random geometric graphs with
+    n_g = floor(2^(lo + (hi-lo) u)), u uniform in [0, 1) (uneven sizes),
+    mean degree 24, and `sources_per_graph` distinct sources each.
+    Returns a list of (graph, [sources])."""
+    s = stream_seed(seed, 40)
+    u = rand_unit(s, np.arange(n_graphs, dtype=np.uint64))
+    items = [(gi, int(np.floor(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u[gi]))), seed, sources_per_graph)
+             for gi in range(n_graphs)]
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    if workers == 1:
+        return [_rgg_item(it) for it in items]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_rgg_item, items, chunksize=1)
