@@ -134,13 +134,17 @@ typedef struct {
                              W2[64][64], b2[64], w3[64], b3, mu[8], sd[8], scale
                              (weights input-major, already rounded to bfloat16); the
                              model maps 8 per-round features to y, k = 2^(scale*y) */
-  /* Training traces (sssp_ex only): every trace_every-th round writes 8 features
-   * to trace_features[8*i], and the 32 smallest (key, id) of B_0 in key order to
-   * trace_keys[32*i] / trace_ids[32*i], i = (*trace_count)++ while i < trace_cap. */
+  /* Training traces: every trace_every-th round writes 8 features to
+   * trace_features[8*i], the 32 smallest (key, id) of B_0 in key order to
+   * trace_keys[32*i] / trace_ids[32*i] (UINT64_MAX keys pad short lists) and the
+   * query's index (0 for sssp_ex, the position in the queries array for
+   * sssp_batch) to trace_query[i] (may be NULL), where i = atomicAdd(trace_count,
+   * 1) while i < trace_cap.  All device arrays. */
   float *trace_features;
   uint64_t *trace_keys;
   uint32_t *trace_ids;
   uint32_t *trace_count;
+  uint32_t *trace_query;
   uint32_t trace_every;
   uint32_t trace_cap;
   uint32_t reserved[4];
@@ -199,6 +203,33 @@ typedef struct {
  */
 int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, sssp_stats *stats,
                void *stream);
+
+/*
+ * Training of the extraction-threshold model (not in the paper: an addition
+ * that chooses k per round).  All arrays are device arrays; calls synchronous.
+ *
+ * mlp_trace_labels: labels[r] = log2 of the longest prefix of trace record r
+ *   (its keys in order) whose keys equal dists[trace_query[r]][id], i.e. how
+ *   many minima the round could have pulled with no wasted relaxation.
+ *   dists is a device array of per-query distance arrays (final distances).
+ * mlp_feature_stats: writes the feature means and standard deviations of
+ *   X[n][8] into blob (the mu and sd fields).
+ * mlp_grad: gradient of the mean squared error of the model on (X[n][8],
+ *   Y[n]) with respect to the PBH_MLP_PARAMS master weights of blob (forward
+ *   with the weights rounded to bfloat16, FP32 accumulation; the rounding is
+ *   taken as identity in the backward pass); loss[0] = the error.  n <= 65536.
+ * mlp_train: `steps` Adam steps (lr, betas 0.9/0.999) over consecutive
+ *   mini-batches of `batch` samples (the caller shuffles X), updating blob in
+ *   place, then rounds the weights to bfloat16.  loss_trace (HOST, may be NULL)
+ *   receives the loss of every step.
+ * Errors: PBH_EINVAL (NULL or empty arguments), PBH_ENOMEM, PBH_EDEVICE.
+ */
+int mlp_trace_labels(const uint64_t *trace_keys, const uint32_t *trace_ids, const uint32_t *trace_query,
+                     uint32_t count, const uint64_t *const *dists, float *labels);
+int mlp_feature_stats(const float *X, uint32_t n, float *blob);
+int mlp_grad(const float *X, const float *Y, uint32_t n, const float *blob, float *grad, float *loss);
+int mlp_train(const float *X, const float *Y, uint32_t n, float *blob, uint32_t batch, uint32_t steps, float lr,
+              float *loss_trace);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char *pbh_last_error(void);

@@ -35,8 +35,8 @@ class SsspOpts(C.Structure):
                 ("k_rule", C.c_uint32), ("k_fixed", C.c_uint32), ("k_max", C.c_uint32), ("k_seq_len", C.c_uint32),
                 ("k_seq", C.c_void_p), ("k_model", C.c_void_p),
                 ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
-                ("trace_count", C.c_void_p), ("trace_every", C.c_uint32), ("trace_cap", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
+                ("trace_cap", C.c_uint32), ("reserved", C.c_uint32 * 4)]
 
 
 class SsspStats(C.Structure):
@@ -53,7 +53,8 @@ class SsspQuery(C.Structure):
 
 _lib = None
 EXPORTS = ["pbh_create", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_destroy",
-           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "pbh_last_error"]
+           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "mlp_trace_labels", "mlp_feature_stats",
+           "mlp_grad", "mlp_train", "pbh_last_error"]
 
 
 def lib():
@@ -73,6 +74,10 @@ def lib():
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
         L.sssp_ex.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.sssp_batch.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
+        L.mlp_trace_labels.argtypes = [vp, vp, vp, u32, vp, vp]
+        L.mlp_feature_stats.argtypes = [vp, u32, vp]
+        L.mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
+        L.mlp_train.argtypes = [vp, vp, u32, vp, u32, u32, C.c_float, C.POINTER(C.c_float)]
         L.pbh_last_error.restype = C.c_char_p
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = C.c_int
@@ -121,8 +126,9 @@ def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fi
             raise ValueError(f"k_model must hold {MLP_BLOB} float32 values")
         o.k_model = _ptr(k_model, 4)
     if trace is not None:
-        f, k, v, cnt, every = trace
+        f, k, v, cnt, q, every = trace
         o.trace_features, o.trace_keys, o.trace_ids, o.trace_count = _ptr(f, 4), _ptr(k, 8), _ptr(v, 4), _ptr(cnt, 4)
+        o.trace_query = _ptr(q, 4) if q is not None else None
         o.trace_every, o.trace_cap = every, f.numel() // 8
     return o
 
@@ -209,3 +215,29 @@ class Heap:
                                       pk.ctypes.data, pv.ctypes.data, rs.ctypes.data))
         k = q.value
         return dict(q=k, ell=ell.value, nB=nB[:k], nS=nS[:k], pk=pk[:k], pv=pv[:k], resolves=rs[:k])
+
+
+# ---------------------------------------------------------------- learned k
+def mlp_trace_labels(trace_keys, trace_ids, trace_query, count: int, dists, labels) -> None:
+    """labels[r] = log2(zero-waste pull size) of trace record r; dists: a
+    sequence of per-query distance tensors (device)."""
+    import torch
+    ptrs = torch.tensor([d.data_ptr() for d in dists], dtype=torch.int64, device=labels.device)
+    _check(lib().mlp_trace_labels(_ptr(trace_keys, 8), _ptr(trace_ids, 4), _ptr(trace_query, 4), count,
+                                  _ptr(ptrs, 8), _ptr(labels, 4)))
+
+
+def mlp_feature_stats(X, blob) -> None:
+    _check(lib().mlp_feature_stats(_ptr(X, 4), X.shape[0], _ptr(blob, 4)))
+
+
+def mlp_grad(X, Y, blob, grad, loss) -> None:
+    _check(lib().mlp_grad(_ptr(X, 4), _ptr(Y, 4), X.shape[0], _ptr(blob, 4), _ptr(grad, 4), _ptr(loss, 4)))
+
+
+def mlp_train(X, Y, blob, batch: int, steps: int, lr: float):
+    import numpy as np
+    lt = np.zeros(max(1, steps), np.float32)
+    _check(lib().mlp_train(_ptr(X, 4), _ptr(Y, 4), X.shape[0], _ptr(blob, 4), batch, steps, lr,
+                           lt.ctypes.data_as(C.POINTER(C.c_float))))
+    return lt[:steps]

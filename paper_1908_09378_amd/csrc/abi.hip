@@ -409,6 +409,8 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       p.spec.trace_k = (u64*)o.trace_keys;
       p.spec.trace_v = o.trace_ids;
       p.spec.trace_count = o.trace_count;
+      p.spec.trace_q = o.trace_query;
+      p.spec.qid = 0;
       p.spec.trace_every = o.trace_every;
       p.spec.trace_cap = o.trace_cap;
     }
@@ -582,7 +584,8 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
     p.g.q = qv;
     p.g.qlds = qlds;
   }
-  if (o.trace_features) return fail(PBH_EINVAL, "sssp_batch: traces are recorded by sssp_ex only");
+  if (o.trace_features && (!o.trace_keys || !o.trace_ids || !o.trace_count || o.trace_every == 0))
+    return fail(PBH_EINVAL, "sssp_batch: trace needs keys, ids, count and trace_every");
   std::vector<u64> lel(nq, 0);
   u64 total_lel = 0;
   for (u32 j = 0; j < nq; ++j) {
@@ -591,6 +594,16 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
     if (rc) return rc;
     if (spec_needs_list(o)) lel[j] = 2ull * kmax * desc[j].g.d;
     total_lel += lel[j];
+    if (o.trace_features) {
+      desc[j].spec.trace_f = o.trace_features;
+      desc[j].spec.trace_k = (u64*)o.trace_keys;
+      desc[j].spec.trace_v = o.trace_ids;
+      desc[j].spec.trace_count = o.trace_count;
+      desc[j].spec.trace_q = o.trace_query;
+      desc[j].spec.qid = order[j];
+      desc[j].spec.trace_every = o.trace_every;
+      desc[j].spec.trace_cap = o.trace_cap;
+    }
   }
   if (g_batch_list.elems < total_lel) {
     arena_free(&g_batch_list);

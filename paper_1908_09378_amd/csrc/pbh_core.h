@@ -764,9 +764,14 @@ enum { DRIVE_AFTER = 1, DRIVE_ENSURE = 2 };
 //     sched 1 = on demand (as the sequential bucket heap of Section 2.1 does):
 //               Resolve(i+1) only when the next Resolve(i) would otherwise
 //               violate its preconditions on level i+1.
-// * DRIVE_ENSURE -- then, if B_0 is empty while the heap is not (possible when
-//     deleted duplicates or dead copies thin out the levels below), resolve
-//     levels j, j-1, ..., 0 for j = 1, 2, ... until B_0 has an element.
+// * DRIVE_ENSURE -- then, while B_0 is empty and the heap is not (possible
+//     when dead copies thin out the levels below: Resolve(0) drops the dead
+//     ones among the elements it moves up), let j be the shallowest non-empty
+//     level below 0 and resolve levels j, j-1, ..., 0 (Resolve(j) first, so
+//     that S_j elements above p_j move down and B_j is filled).  A cascade
+//     puts a live element into B_0 or drops dead ones at level 0; the loop
+//     gives up with E_INTERNAL after (elements + 1) * (q + 1) cascades rather
+//     than spin.
 //
 // Every requested Resolve(x) first resolves the levels below x that lack
 // room for what Resolve(x) may push down: find the first j >= x whose next
@@ -778,7 +783,8 @@ PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur,
   int tgt = -1, chain = -1;  // pending chain: levels chain, chain-1, ..., tgt
   int stage = (what & DRIVE_AFTER) ? 0 : 2;
   int si = 0;                // schedule position
-  int ej = 1, ek = -1;       // refill position
+  int ek = -1;               // refill position
+  u64 cascades = 0, climit = 0;
   for (;;) {
     if (st->err) break;
     int lvl;
@@ -812,9 +818,20 @@ PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur,
       if (x < 0 && stage == 2) {
         if (!(what & DRIVE_ENSURE)) break;
         if (ek < 0) {
-          if (st->L[0].nB != 0 || ej > st->ell) break;
-          ek = ej;
-          ++ej;
+          const int ell = st->ell;
+          if (st->L[0].nB != 0 || ell < 1) break;
+          int j = 1;
+          u64 tot = 0;
+          for (int l = 0; l <= ell; ++l) tot += (u64)st->L[l].nB + st->L[l].nS;
+          while (j <= ell && st->L[j].nB + st->L[j].nS == 0) ++j;
+          if (cascades == 0) climit = (tot + 1) * (u64)(g.q + 1);
+          if (j > ell || ++cascades > climit) {
+            t.sync();
+            if (t.tid() == 0) st->err = E_INTERNAL;
+            t.sync();
+            break;
+          }
+          ek = j;
         }
         x = ek--;
       }
@@ -969,6 +986,8 @@ struct SpecCfg {
   u32* trace_v;
   u32 trace_every, trace_cap;
   u32* trace_count;
+  u32* trace_q;  // query index of each record
+  u32 qid;
 };
 
 struct SsspCounters {
@@ -1085,11 +1104,13 @@ PBH_INL void record_trace(const T& t, const Geom& g, SP st, const SpecCfg& sc, A
   float f[NFEAT];
   round_features(t, g, st, B, nB, memo, f);
   u32 slot = 0;
-  if (t.tid() == 0) slot = (*sc.trace_count)++;
+  if (t.tid() == 0) slot = t.atomic_add32(sc.trace_count, 1u);
   slot = t.sum(slot);
   if (slot >= sc.trace_cap) return;
-  if (t.tid() == 0)
+  if (t.tid() == 0) {
     for (int i = 0; i < NFEAT; ++i) sc.trace_f[(u64)slot * NFEAT + i] = f[i];
+    if (sc.trace_q) sc.trace_q[slot] = sc.qid;
+  }
   u64 lastk = 0;
   u32 lastv = 0;
   bool have = false;
@@ -1243,9 +1264,17 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
 // empty and B_0 keeps at least d elements, so Algorithm 1's preconditions hold.
 // Speculative rounds bulk-update their list U in pieces of at most d, each
 // piece an operation followed by Resolve(0) and the schedule.
-template <class T, class P>
+struct NoHook {
+  template <class SP>
+  PBH_INL void operator()(const Geom&, SP, const SsspCounters&) const {}
+};
+
+// `hook` sees the heap after every operation's Resolve schedule (the CPU
+// tests use it to check invariants; the kernels pass NoHook).
+template <class T, class P, class Hook = NoHook>
 PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
-                         const u32* wt, u64* dist, u32 n, u32 src, int sched, const SpecCfg& sc, SsspCounters* cnt) {
+                         const u32* wt, u64* dist, u32 n, u32 src, int sched, const SpecCfg& sc, SsspCounters* cnt,
+                         const Hook& hook = Hook()) {
   using G = typename P::G;
   const int idbits = bits_for(n);
   if (t.tid() == 0) {
@@ -1273,6 +1302,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     // holds the minimum if the heap is not empty.
     drive<T, P>(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
     if (st->err) break;
+    hook(g, st, c);
     if (upos < ulen) {  // next piece of the round's bulk update
       u32 len = ulen - upos < g.d ? ulen - upos : g.d;
       G U{(decltype(G::k))sc.uk, (decltype(G::v))sc.uv};
@@ -1328,7 +1358,15 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
       }
       upos = 0;
     }
-    if (!more) break;
+    if (!more) {
+      // B_0 is empty only once the heap is (the refill above guarantees it).
+      if (st->ell >= 0) {
+        t.sync();
+        if (t.tid() == 0) st->err = E_INTERNAL;
+        t.sync();
+      }
+      break;
+    }
     ++c.rounds;
   }
   *cnt = c;
@@ -1481,7 +1519,13 @@ PBH_INL void pbh_extract_body(const T& t, const Geom& g, typename P::SP st, cons
     if (st->err || outpos >= p.k) break;
     const Lvl a0 = lvl_load(st, 0);
     if (a0.nB == 0) {
-      if (t.tid() == 0) st->aux[4] = 1;
+      t.sync();
+      if (t.tid() == 0) {
+        if (st->ell >= 0)
+          st->err = E_INTERNAL;  // the refill leaves B_0 empty only when the heap is
+        else
+          st->aux[4] = 1;
+      }
       t.sync();
       break;
     }

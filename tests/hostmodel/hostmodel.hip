@@ -12,6 +12,7 @@
 #include "../../paper_1908_09378_amd/csrc/pbh_core.h"
 
 using namespace bkt;
+typedef long long i64;
 
 namespace {
 
@@ -162,12 +163,56 @@ int hm_level_items(void* hp, int i, u64* bk, u32* bv, u64* sk, u32* sv) {
   return 0;
 }
 
+// Invariant check run after every operation of the round loop: the smallest
+// live element of the heap (key == dist[id]) sits in B_0, and with the plain
+// rule every reached vertex is either extracted or live in the heap exactly
+// once.  Records the round of the first violation.
+struct LiveCheck {
+  const u64* dist;
+  u32 n;
+  bool plain;
+  int* first_bad;  // -1 if none
+  u64* info;       // what was violated: (1, key, id) misplaced minimum, (2, live, reached)
+  void operator()(const Geom& g, HeapState* st, const SsspCounters& c) const {
+    if (*first_bad >= 0) return;
+    std::vector<char> seen(n, 0);
+    u64 live = 0, mk = KINF, mk0 = KINF;
+    u32 mv = VINF, mv0 = VINF;
+    for (int i = 0; i < g.q; ++i) {
+      const Lvl& L = st->L[i];
+      for (int w = 0; w < 2; ++w) {
+        Arr A = lbuf(g, i, w ? 3 + L.ssel : L.bsel);
+        u32 na = w ? L.nS : L.nB;
+        for (u32 x = 0; x < na; ++x) {
+          if (dist[A.v[x]] != A.k[x]) continue;
+          if (!seen[A.v[x]]) seen[A.v[x]] = 1, ++live;
+          if (A.k[x] < mk || (A.k[x] == mk && A.v[x] < mv)) mk = A.k[x], mv = A.v[x];
+          if (i == 0 && w == 0 && (A.k[x] < mk0 || (A.k[x] == mk0 && A.v[x] < mv0))) mk0 = A.k[x], mv0 = A.v[x];
+        }
+      }
+    }
+    if (mk != KINF && (mk0 != mk || mv0 != mv)) {
+      *first_bad = (int)c.rounds;
+      info[0] = 1, info[1] = mk, info[2] = mv;
+      return;
+    }
+    if (plain) {
+      u64 reached = 0;
+      for (u32 v = 0; v < n; ++v) reached += dist[v] != KINF;
+      if (live + c.extracted != reached) {
+        *first_bad = (int)c.rounds;
+        info[0] = 2, info[1] = live, info[2] = reached;
+      }
+    }
+  }
+};
+
 // parDijkstra with the kernel's round loop.  qlds levels are placed in a
 // separate buffer, standing in for LDS.  stats: rounds, relaxations, updates,
 // heap element touches, levels, resolves[0..15].
 int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src, u64* dist, u32 d_opt,
             int sched, u64 hcap, int qlds, u64* stats, int rule, u32 kfix, u32 kmax, const u32* kseq, u32 kseq_len,
-            const float* model) {
+            const float* model, int check_live) {
   u64 md = 0;
   for (u32 u = 0; u < n; ++u) md = off[u + 1] - off[u] > md ? off[u + 1] - off[u] : md;
   u32 d = d_opt ? d_opt : (u32)(md ? md : 1);
@@ -206,7 +251,18 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   sc.tk = uk.data() + (u64)sc.kmax * d;
   sc.tv = uv.data() + (u64)sc.kmax * d;
   SsspCounters c;
-  sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
+  int first_bad = -1;
+  u64 info[3] = {0, 0, 0};
+  if (check_live) {
+    LiveCheck hk{dist, n, rule == 0, &first_bad, info};
+    sssp_rounds<HostTeam, HostPolicy, LiveCheck>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk);
+  } else {
+    sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
+  }
+  stats[22] = (u64)(i64)first_bad;
+  stats[23] = info[0];
+  stats[24] = info[1];
+  stats[25] = info[2];
   stats[0] = c.rounds;
   stats[1] = c.relax;
   stats[2] = c.updates;

@@ -1,0 +1,135 @@
+"""GPU tests of the learned extraction threshold: training kernels against the
+FP64 model oracle, trace labels against the oracle, exactness of learned
+rounds (for any weights, including garbage), and the trained model's gain over
+the plain rule."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1908_09378_amd as pkg
+import workloads as W
+from gpu_util import DEV, dev32, host32, host64, run_sssp
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _blob(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    b = np.zeros(pkg.MLP_BLOB, np.float32)
+    b[:pkg.MLP_PARAMS] = rng.normal(size=pkg.MLP_PARAMS) * scale
+    b[pkg.MLP_PARAMS:pkg.MLP_PARAMS + 8] = rng.normal(size=8)
+    b[pkg.MLP_PARAMS + 8:pkg.MLP_PARAMS + 16] = rng.uniform(0.5, 2, size=8)
+    b[-1] = 1.0
+    return b
+
+
+def test_gradient_matches_fp64_oracle():
+    rng = np.random.default_rng(3)
+    b = _blob(4)
+    X = rng.normal(size=(96, 8)).astype(np.float32)
+    Y = rng.normal(size=96).astype(np.float32)
+    g = torch.zeros(pkg.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    pkg.mlp_grad(torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV), torch.from_numpy(b).to(DEV), g, loss)
+    gg = g.cpu().numpy().astype(np.float64)
+    ref_loss = mlp.loss(mlp.rounded(b), X.astype(np.float64), Y.astype(np.float64))
+    assert abs(loss.item() - ref_loss) <= 1e-4 * max(1.0, ref_loss)
+    idx = np.arange(0, mlp.PARAMS, 5)
+    base = mlp.rounded(b)
+    for p in idx:
+        a, c = base.copy(), base.copy()
+        a[p] += 1e-6
+        c[p] -= 1e-6
+        fd = (mlp.loss(a, X, Y) - mlp.loss(c, X, Y)) / 2e-6
+        assert abs(gg[p] - fd) <= 1e-2 * abs(fd) + 1e-4, (p, gg[p], fd)
+
+
+def test_trace_labels_match_oracle():
+    gs = [W.grid8(40, 40, wmax=10000, seed=5), W.ring_lattice(3000, 16, 1, 1000, seed=6), W.grid4(30, 50, 1, 100, seed=7)]
+    from paper_1908_09378_amd import learn
+    X, Y, st = learn.collect(gs, every=3, cap=1 << 14)
+    n = X.shape[0]
+    assert n > 100
+    # reproduce labels with the oracle from the traces and final distances
+    cap = 1 << 14
+    tf = torch.zeros(cap * 8, dtype=torch.float32, device=DEV)
+    tk = torch.zeros(cap * 32, dtype=torch.int64, device=DEV)
+    tv = torch.zeros(cap * 32, dtype=torch.int32, device=DEV)
+    tq = torch.zeros(cap, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    qs, keep, dists = [], [], []
+    for g in gs:
+        off = torch.from_numpy(g.offsets.view(np.int64)).to(DEV)
+        tg = torch.from_numpy(g.targets.view(np.int32)).to(DEV)
+        wt = torch.from_numpy(g.weights.view(np.int32)).to(DEV)
+        dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+        keep.append((off, tg, wt))
+        dists.append(dist)
+        qs.append((off, tg, wt, g.n, g.m, 0, dist))
+    pkg.sssp_batch(qs, trace=(tf, tk, tv, cnt, tq, 3))
+    m = int(cnt.item())
+    lab = torch.empty(m, dtype=torch.float32, device=DEV)
+    pkg.mlp_trace_labels(tk, tv, tq, m, dists, lab)
+    K, V, Q = host64(tk).reshape(-1, 32), host32(tv).reshape(-1, 32), host32(tq)
+    D = [oracle.dijkstra(g, 0) for g in gs]
+    for r in range(m):
+        ref = mlp.zero_waste_label(K[r], V[r], D[Q[r]])
+        assert abs(lab[r].item() - ref) < 1e-6
+    # traced key prefixes are ascending (key order)
+    for r in range(m):
+        ks = [int(x) for x in K[r] if x != np.uint64(0xFFFFFFFFFFFFFFFF)]
+        assert ks == sorted(ks)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(8)
+    X = rng.normal(size=(8192, 8)).astype(np.float32)
+    Y = (np.tanh(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] > 0).astype(np.float32) * 3.0
+    from paper_1908_09378_amd import learn
+    blob, losses = learn.train(torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV), steps=400, batch=512)
+    assert losses[-20:].mean() < 0.5 * losses[:5].mean()
+    b = blob.cpu().numpy()
+    assert np.array_equal(b[:pkg.MLP_PARAMS], mlp.bf16_round(b[:pkg.MLP_PARAMS]))   # weights stored as bf16
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_learned_rule_exact_with_any_weights(seed):
+    g = W.grid8(96, 96, wmax=10000, seed=9)
+    b = torch.from_numpy(_blob(seed, scale=1.5)).to(DEV)
+    ref = oracle.dijkstra(g, 0)
+    got, st = run_sssp(pkg, g, 0, k_rule=2, k_model=b, k_max=64)
+    assert np.array_equal(got, ref)
+
+
+def test_learned_rule_falls_back_on_nan():
+    g = W.grid4(40, 40, 1, 100, seed=2)
+    b = _blob(1)
+    b[5] = np.nan
+    got, st = run_sssp(pkg, g, 0, k_rule=2, k_model=torch.from_numpy(b).to(DEV))
+    ref, order, _ = oracle.dijkstra(g, 0, want_order=True)
+    assert np.array_equal(got, ref)
+    assert st["rounds"] == order.shape[0]   # k = 1 every round
+
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1908_09378_amd", "models", "k_mlp.bin")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained model file")
+def test_trained_model_beats_plain():
+    """What the trained network gains over the plain rule on a held-out graph
+    of the evaluation family (8-neighbour grid, log-uniform weights)."""
+    from paper_1908_09378_amd import learn
+    blob = torch.from_numpy(learn.load_model(MODEL)).to(DEV)
+    g = W.grid8(384, 384, wmax=10000, seed=123)
+    ref = oracle.dijkstra(g, 0)
+    got0, st0 = run_sssp(pkg, g, 0)
+    got1, st1 = run_sssp(pkg, g, 0, k_rule=2, k_model=blob)
+    assert np.array_equal(got0, ref) and np.array_equal(got1, ref)
+    print(f"[learned] plain {st0['rounds']} rounds {st0['kernel_ms']:.1f} ms; learned {st1['rounds']} rounds "
+          f"{st1['extracted']} extracted {st1['kernel_ms']:.1f} ms", flush=True)
+    assert st1["rounds"] < 0.5 * st0["rounds"]
+    assert st1["kernel_ms"] < st0["kernel_ms"]

@@ -61,6 +61,20 @@ def test_grid8_loguniform():
     _check(W.grid8(128, 128, wmax=10000, seed=4), 0)
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(team=256), dict(lds_levels=0), dict(schedule=1),
+                                dict(k_rule=1, k_fixed=16), dict(k_rule=1, k_fixed=1)])
+def test_grid8_dead_copies_refill(kw):
+    """Many dead copies collect in B_1 and B_2 on this graph, so refilling an
+    empty B_0 takes repeated Resolve(0) calls."""
+    g = W.grid8(96, 96, wmax=10000, seed=9)
+    if "k_rule" not in kw:
+        _check(g, 0, **kw)
+        return
+    print(f"[sssp] {g.name} {kw}", flush=True)
+    got, _ = run_sssp(pkg, g, 0, **kw)
+    assert np.array_equal(got, oracle.dijkstra(g, 0))
+
+
 def test_unit_weights_many_ties():
     _check(W.grid4(100, 100, 1, 1, seed=5), 0)
     _check(W.ring_lattice(1 << 13, 16, 1, 1, seed=5), 0)

@@ -127,20 +127,30 @@ def _graphs():
     yield W.grid4(9, 9, 1, 1, seed=5)
     yield W.rgg(700, seed=6)
     yield W.paper_dag(150, 3000, seed=7)
+    # many dead copies pile up in B_1 and B_2: refilling B_0 takes repeated
+    # Resolve(0) calls, each dropping a window of dead elements
+    yield W.grid8(96, 96, wmax=10000, seed=9)
     for s in range(12):
         yield W.random_graph(1 + 7 * s, 5 * s * s, [0, 0, 1][s % 3], [0, 5, 50][s % 3], 40 + s)
 
 
-@pytest.mark.parametrize("gi", range(18))
+NGRAPHS = 19
+
+
+@pytest.mark.parametrize("gi", range(NGRAPHS))
 @pytest.mark.parametrize("variant", [(0, 0, 0), (1, 0, 2), (0, 1, 1), (0, 3, 0)])
 def test_sssp_logic_vs_oracle(gi, variant):
+    """Distances, rounds and relaxations equal the oracle's; after every
+    operation the smallest live element is in B_0 and each reached vertex is
+    extracted or live in the heap exactly once."""
     sched, dmul, qlds = variant
     g = list(_graphs())[gi]
     src = (gi * 7) % g.n
     ref, order, nrelax = oracle.dijkstra(g, src, want_order=True)
     d = 0 if dmul == 0 else max(1, g.max_degree()) * dmul
-    rc, dist, st = hm_sssp(g, src, d=d, sched=sched, qlds=qlds)
+    rc, dist, st = hm_sssp(g, src, d=d, sched=sched, qlds=qlds, check_live=True)
     assert rc == 0
+    assert st["first_bad"] == -1, st["violation"]
     assert np.array_equal(dist, ref)
     assert st["rounds"] == order.shape[0]          # plain rule: one round per settled vertex
     assert st["relax"] == nrelax
@@ -157,7 +167,7 @@ def test_sssp_small_capacity_reports_capacity():
 
 
 # ---------------------------------------------------------------- speculative rounds
-@pytest.mark.parametrize("gi", range(18))
+@pytest.mark.parametrize("gi", range(NGRAPHS))
 @pytest.mark.parametrize("kcase", ["fixed4", "fixed64", "random", "adversarial"])
 def test_speculative_rounds_exact_for_any_k(gi, kcase):
     """Rounds that extract k > 1 minima re-insert improved vertices, so the
@@ -173,7 +183,8 @@ def test_speculative_rounds_exact_for_any_k(gi, kcase):
     elif kcase == "random":
         rc, dist, st = hm_sssp(g, src, rule=3, kseq=rng.integers(1, 40, size=97), kmax=256)
     else:  # alternate huge pulls with single ones
-        rc, dist, st = hm_sssp(g, src, rule=3, kseq=[256, 1, 1, 256, 3], kmax=256)
+        rc, dist, st = hm_sssp(g, src, rule=3, kseq=[256, 1, 1, 256, 3], kmax=256, check_live=True)
+        assert st["first_bad"] == -1, st["violation"]
     assert rc == 0
     assert np.array_equal(dist, ref)
     assert st["extracted"] >= order.shape[0]       # every reached vertex is extracted at least once

@@ -379,3 +379,25 @@ def rgg_batch(n_graphs: int = 64, sources_per_graph: int = 4, lo_log2: int = 12,
     import multiprocessing as mp
     with mp.get_context("fork").Pool(workers) as pool:
         return pool.map(_rgg_item, items, chunksize=1)
+
+
+def training_graphs(count: int = 200, lo_log2: int = 14, hi_log2: int = 18, seed: int = 70):
+    """Graphs whose plain parDijkstra runs train the extraction-threshold model:
+    ring lattices (w ~ U[1,1000]), 4-neighbour grids (w ~ U[1,100]) and
+    8-neighbour grids (log-uniform w in [1, 10^4]) in turn, with n log-uniform
+    in [2^lo, 2^hi] (grids use the nearest square)."""
+    s = stream_seed(seed, 60)
+    u = rand_unit(s, np.arange(count, dtype=np.uint64))
+    out = []
+    for i in range(count):
+        n = int(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * u[i]))
+        fam = i % 3
+        if fam == 0:
+            out.append(ring_lattice(max(n, 64), 16, 1, 1000, seed=seed * 1000 + i))
+        else:
+            side = max(8, int(round(math.sqrt(n))))
+            if fam == 1:
+                out.append(grid4(side, side, 1, 100, seed=seed * 1000 + i))
+            else:
+                out.append(grid8(side, side, wmax=10000, seed=seed * 1000 + i))
+    return out
