@@ -1,6 +1,7 @@
 """Benchmark: parDijkstra (plain rule) on the parallel bucket heap, 1 MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ring|grid64|grid8|dag]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ring|grid64|grid8|dag|multi|heap]
+                    [--method plain|learned|both]
 
 One step = one complete sssp() over the resident graph (every round of the
 hot path: extract-min, relaxation, bulk update, Resolve schedule).  The
@@ -11,7 +12,9 @@ edges), integer weights uniform in [1, 1000], source 0.
 Prints one JSON line: GTEPS = m / seconds per step, the roofline of the
 round-loop kernel (algorithmic bytes per launch / its HIP-event duration vs
 8 TB/s) and the CPU oracle (single-thread binary-heap Dijkstra) timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  With --method both (the default) the
+line also carries the learned-threshold rule on the same graph ("learned"),
+whose distances are checked against the oracle like the plain run's.
 """
 import argparse
 import json
@@ -106,6 +109,108 @@ def run_multi(args):
     print(json.dumps(line), flush=True)
 
 
+def run_heap(args):
+    """The standalone heap: 2^24 ids with keys uniform in [0, 2^40) loaded in
+    16 pieces of d = 2^20 (untimed), then rounds of bulk_update with 2^20
+    decrease-keys (ids drawn with replacement from the live set, new key = old
+    - uniform[0, old/2]) and extract_min of 2^16.  Each call is synchronous
+    and timed on its own; the batches come from a host copy of the current
+    keys kept in lockstep.  Every extraction is checked exactly: ascending,
+    keys equal to the current keys, and the largest extracted pair below every
+    remaining one."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1908_09378_amd as pkg
+    import workloads as W
+
+    INF = np.uint64(0xFFFFFFFFFFFFFFFF)
+    n_ids, d, ext = 1 << 24, 1 << 20, 1 << 16
+    rounds = args.heap_rounds
+    dev = torch.device("cuda:0")
+
+    def to_dev(k, i):
+        return (torch.from_numpy(k.view(np.int64)).to(dev), torch.from_numpy(i.view(np.int32)).to(dev))
+
+    keys, ids = W.heap_init_pairs(n_ids, seed=3)
+    h = pkg.Heap(n_ids, d)
+    for c in range(0, n_ids, d):
+        h.bulk_update(*to_dev(keys[c:c + d], ids[c:c + d]))
+    torch.cuda.synchronize()
+    cur = np.full(n_ids, INF, dtype=np.uint64)
+    cur[ids] = keys
+    ko = torch.empty(ext, dtype=torch.int64, device=dev)
+    io = torch.empty(ext, dtype=torch.int32, device=dev)
+    t_upd = t_ext = 0.0
+    elems_upd = 0
+    ok = True
+    kept = []
+    for r in range(rounds):
+        live = np.flatnonzero(cur != INF).astype(np.uint32)
+        bk, bi = W.decrease_batch(live, lambda x: cur[x], d, 3, r)
+        if len(kept) < 4:
+            kept.append((bk, bi))
+        dk, di = to_dev(bk, bi)
+        torch.cuda.synchronize()
+        e0 = h.traffic()
+        t0 = time.perf_counter()
+        h.bulk_update(dk, di)
+        t_upd += time.perf_counter() - t0
+        elems_upd += h.traffic() - e0
+        np.minimum.at(cur, bi, bk)
+        t0 = time.perf_counter()
+        n = h.extract_min(ext, ko, io)
+        t_ext += time.perf_counter() - t0
+        hk = ko[:n].cpu().numpy().view(np.uint64)
+        hi = io[:n].cpu().numpy().view(np.uint32)
+        good = n == ext and bool(np.all(cur[hi] == hk)) and np.unique(hi).shape[0] == n
+        good = good and bool(np.all((hk[1:] > hk[:-1]) | ((hk[1:] == hk[:-1]) & (hi[1:] > hi[:-1]))))
+        cur[hi] = INF
+        mk = cur.min()
+        if good and mk != INF:
+            good = mk > hk[-1] or (mk == hk[-1] and int(np.flatnonzero(cur == mk).min()) > int(hi[-1]))
+        ok &= bool(good)
+        if r % 32 == 0:
+            print(f"[bench] heap round {r}: update {t_upd / (r + 1) * 1e3:.2f} ms, extract "
+                  f"{t_ext / (r + 1) * 1e3:.2f} ms, exact={ok}", file=sys.stderr, flush=True)
+    ok &= h.size() == int(np.count_nonzero(cur != INF))
+    upd_s = t_upd / rounds
+    # algorithmic bytes of one bulk_update: the level operations' elements
+    # (12 B each) plus the intake: read the pairs (12 B), the atomicMin on the
+    # current key (8 B) and the bitmap (4 bits per id, read and cleared)
+    abytes = 12.0 * elems_upd / rounds + 20.0 * d + n_ids / 4
+    achieved = abytes / upd_s / 1e9
+    line = {"metric": "parBucketHeap bulk_update keys/s on 1 MI355X", "value": d / upd_s, "unit": "keys/s",
+            "n_gpus": 1, "steps": rounds, "warmup": 0, "ms_per_step": (t_upd + t_ext) / rounds * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "standalone heap: 2^24 ids, keys U[0,2^40), d=2^20; rounds of 2^20 "
+                                   "decrease-keys (new = old - U[0, old/2]) + extract_min(2^16)",
+                       "rounds": rounds, "engine": "device-wide"},
+            "update_ms": upd_s * 1e3, "extract_ms": t_ext / rounds * 1e3,
+            "extract_keys_per_s": ext / (t_ext / rounds),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "bulk_update (all kernels, "
+                         "host-synchronous steps included)", "algorithmic_bytes": abytes},
+            "exact": ok}
+    if not args.no_cpu:
+        o = oracle.PQ(n_ids)
+        o.bulk_update(keys, ids)
+        t0 = time.perf_counter()
+        done = 0
+        for bk, bi in kept:
+            o.bulk_update(bk, bi)
+            o.extract_min(ext)
+            done += bk.shape[0]
+            if time.perf_counter() - t0 > args.cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": done / el, "unit": "keys/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{len(kept)} rounds (bulk_update 2^20 + extract_min 2^16) on the "
+                                          f"std::set oracle after the same 2^24 load ({el:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
 def algorithmic_bytes(st):
     """Bytes the method must move per launch: per settled vertex its two CSR
     offsets (16 B); per scanned edge its target and weight (8 B) and the 8-byte
@@ -120,7 +225,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ring")
+    ap.add_argument("--method", default="both", choices=["plain", "learned", "both"],
+                    help="plain parDijkstra (the timed value), the learned threshold, or both on the same graph")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--heap-rounds", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -130,6 +238,8 @@ def main():
 
     if args.workload == "multi":
         return run_multi(args)
+    if args.workload == "heap":
+        return run_heap(args)
 
     import numpy as np
     import torch
@@ -144,16 +254,42 @@ def main():
     dist = torch.empty(g.n, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
-    stats = []
-    for _ in range(args.warmup):
-        pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = (t1 - t0) / args.steps
+    import oracle
+    ref = oracle.dijkstra(g, 0)
+
+    def timed(steps, warmup, **kw):
+        stats = []
+        for _ in range(warmup):
+            pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            stats.append(pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist, **kw))
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        exact = bool(np.array_equal(dist.cpu().numpy().view(np.uint64), ref))
+        print(f"[bench] {kw.get('k_rule', 0) and 'learned' or 'plain'}: {sec * 1e3:.1f} ms/step, "
+              f"{stats[-1]['rounds']} rounds, exact={exact}", file=sys.stderr, flush=True)
+        return sec, stats, exact
+
+    learned = None
+    if args.method in ("both", "learned"):
+        from paper_1908_09378_amd import learn
+        blob = torch.from_numpy(learn.load_model()).to(dev)
+        lsec, lstats, lexact = timed(args.steps, args.warmup, k_rule=2, k_model=blob)
+        ls = lstats[-1]
+        learned = {"value": g.m / lsec / 1e9, "ms_per_step": lsec * 1e3, "rounds": ls["rounds"],
+                   "relaxations": ls["relaxations"], "extracted": ls["extracted"],
+                   "kernel_ms": sum(x["kernel_ms"] for x in lstats) / len(lstats), "exact": lexact,
+                   "model": "8-64-64-1 GELU MLP, bf16 weights (models/k_mlp.bin)"}
+    if args.method == "learned":
+        print(json.dumps({"metric": METRIC, "value": learned["value"], "unit": "GTEPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": learned["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                          "data": "synthetic", "config": {"workload": desc, "method": "learned threshold",
+                                                          "n": g.n, "m": g.m}, "learned": learned}), flush=True)
+        return
+    sec, stats, exact = timed(args.steps, args.warmup)
     gteps = g.m / sec / 1e9
 
     st = stats[-1]
@@ -182,11 +318,11 @@ def main():
         "rounds": st["rounds"],
         "relaxations": st["relaxations"],
         "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]),
+        "exact": exact,
     }
-    # correctness of the timed run, against the oracle
-    import oracle
-    ref = oracle.dijkstra(g, 0)
-    line["exact"] = bool(np.array_equal(dist.cpu().numpy().view(np.uint64), ref))
+    if learned is not None:
+        learned["speedup_vs_plain"] = learned["value"] / gteps
+        line["learned"] = learned
     if not args.no_cpu:
         per_run, runs = oracle.time_dijkstra(g, 0, args.cpu_budget)
         line["cpu_baseline"] = {"value": g.m / per_run / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",

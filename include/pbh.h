@@ -56,6 +56,29 @@ typedef struct pbh pbh_t; /* opaque; owned by the library */
 int pbh_create(pbh_t **out, uint32_t id_capacity, uint32_t d);
 
 /*
+ * pbh_create_ex: pbh_create with a choice of engine (same results, same
+ * errors; opts may be NULL = automatic).
+ *   engine 0 = automatic: the device-wide engine for d >= 16384, else the
+ *              one-workgroup engine;
+ *   engine 1 = one workgroup runs each operation and keeps the heap state on
+ *              the device (suits small d: a few microseconds per operation);
+ *   engine 2 = device-wide: every step of Resolve (merge with duplicate
+ *              deletion, Select, the splits) is a grid-wide kernel and the
+ *              host runs Resolve's control flow and the schedule, reading
+ *              back a few sizes per step (suits large d: HBM-bound).
+ *   schedule 0 = Theorem 1 (Resolve(i+1) after every fourth Resolve(i)),
+ *   schedule 1 = on demand (Resolve(i+1) only when level i+1 needs it).
+ * Errors: those of pbh_create, and PBH_EINVAL for engine > 2 or
+ * schedule > 1.
+ */
+typedef struct pbh_opts {
+  uint32_t engine;
+  uint32_t schedule;
+  uint32_t reserved[6]; /* must be zero */
+} pbh_opts;
+int pbh_create_ex(pbh_t **out, uint32_t id_capacity, uint32_t d, const pbh_opts *opts);
+
+/*
  * pbh_bulk_update: BulkUpdate(U) of Section 1.2 -- update(e) for each of the
  * count pairs (keys[i], ids[i]) (device arrays): the element with that id gets
  * key min(current, keys[i]); an absent id is inserted.  Within a batch the
@@ -80,6 +103,15 @@ int pbh_extract_min(pbh_t *h, uint64_t k, uint64_t *keys_out, uint32_t *ids_out,
 
 /* pbh_size: number of elements in the heap (host *size_out). */
 int pbh_size(pbh_t *h, uint64_t *size_out);
+
+/*
+ * pbh_traffic: heap elements (12 bytes each) read or written by the level
+ * operations of Algorithm 1 (Merge, DeleteDuplicates, Select, the splits and
+ * the copies into S_0) since the handle was created, counted as the engine
+ * performs them (host *elements_out).  Used for the algorithmic-byte count
+ * of a benchmark.
+ */
+int pbh_traffic(pbh_t *h, uint64_t *elements_out);
 
 /* pbh_destroy: frees the handle and its arena.  NULL is accepted. */
 int pbh_destroy(pbh_t *h);

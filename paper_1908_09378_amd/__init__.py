@@ -29,6 +29,13 @@ MLP_BLOB = MLP_PARAMS + 2 * 8 + 1
 K_PLAIN, K_FIXED, K_LEARNED, K_SEQ = 0, 1, 2, 3
 
 
+class PbhOpts(C.Structure):
+    _fields_ = [("engine", C.c_uint32), ("schedule", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+
+
+ENGINE_AUTO, ENGINE_TEAM, ENGINE_WIDE = 0, 1, 2
+
+
 class SsspOpts(C.Structure):
     _fields_ = [("d", C.c_uint32), ("team", C.c_uint32), ("schedule", C.c_uint32),
                 ("lds_levels", C.c_uint32), ("heap_capacity", C.c_uint64),
@@ -52,7 +59,7 @@ class SsspQuery(C.Structure):
 
 
 _lib = None
-EXPORTS = ["pbh_create", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_destroy",
+EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "pbh_last_error"]
 
@@ -66,9 +73,11 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
         L.pbh_create.argtypes = [C.POINTER(vp), u32, u32]
+        L.pbh_create_ex.argtypes = [C.POINTER(vp), u32, u32, C.POINTER(PbhOpts)]
         L.pbh_bulk_update.argtypes = [vp, vp, vp, u64]
         L.pbh_extract_min.argtypes = [vp, u64, vp, vp, C.POINTER(u64)]
         L.pbh_size.argtypes = [vp, C.POINTER(u64)]
+        L.pbh_traffic.argtypes = [vp, C.POINTER(u64)]
         L.pbh_destroy.argtypes = [vp]
         L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
@@ -163,9 +172,12 @@ def sssp_batch(queries, *, stream=None, **kw) -> dict:
 class Heap:
     """A parallel bucket heap over ids [0, id_capacity) with bulk size d."""
 
-    def __init__(self, id_capacity: int, d: int):
+    def __init__(self, id_capacity: int, d: int, engine: int = ENGINE_AUTO, schedule: int = 0):
+        """engine: ENGINE_AUTO, ENGINE_TEAM (one workgroup per operation) or
+        ENGINE_WIDE (device-wide steps); schedule 0 = Theorem 1, 1 = on demand."""
         h = C.c_void_p()
-        _check(lib().pbh_create(C.byref(h), id_capacity, d))
+        o = PbhOpts(engine, schedule)
+        _check(lib().pbh_create_ex(C.byref(h), id_capacity, d, C.byref(o)))
         self._h = h
         self.id_capacity = id_capacity
         self.d = d
@@ -199,6 +211,12 @@ class Heap:
     def size(self) -> int:
         n = C.c_uint64(0)
         _check(lib().pbh_size(self._h, C.byref(n)))
+        return n.value
+
+    def traffic(self) -> int:
+        """Heap elements read or written by the level operations so far."""
+        n = C.c_uint64(0)
+        _check(lib().pbh_traffic(self._h, C.byref(n)))
         return n.value
 
     def debug_levels(self) -> dict:

@@ -2,7 +2,8 @@
 //
 // Host side only: argument checks, the device arena, growth of the level
 // arena, stream handling and error reporting.  All heap and SSSP work runs in
-// the kernels of kernels.hip.
+// the kernels of kernels.hip (one workgroup per operation) and wide.hip (the
+// device-wide heap engine for large d).
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -16,6 +17,7 @@
 
 #include "../../include/pbh.h"
 #include "pbh_launch.h"
+#include "wide.h"
 
 using namespace bkt;
 
@@ -95,6 +97,7 @@ struct pbh {
   u32* uids = nullptr;
   u64 ulist_cap = 0;
   u64* flag = nullptr;
+  WideScratch* wide = nullptr;  // device-wide engine (state authoritative on the host)
 };
 
 namespace {
@@ -131,19 +134,53 @@ int pbh_grow(pbh* h) {
 }
 
 int pull_state(pbh* h) {
+  if (h->wide) return PBH_OK;  // the host copy is the state
   HIPCHK(hipMemcpy(&h->host, h->gst, sizeof(HeapState), hipMemcpyDeviceToHost));
   return PBH_OK;
 }
 
 int push_state(pbh* h) {
+  if (h->wide) return PBH_OK;
   HIPCHK(hipMemcpy(h->gst, &h->host, sizeof(HeapState), hipMemcpyHostToDevice));
   return PBH_OK;
 }
 
 int state_error(const HeapState& s) {
   if (s.err == E_CAPACITY) return fail(PBH_ECAPACITY, "a heap level overflowed its allocation");
+  if (s.err == E_DEVICE) return fail(PBH_EDEVICE, "a HIP call of the device-wide heap engine failed");
   if (s.err) return fail(PBH_EINTERNAL, "device-side heap check failed (code %d)", s.err);
   return PBH_OK;
+}
+
+int wide_grow_cb(void* ctx, Geom* g) {
+  pbh* h = (pbh*)ctx;
+  int rc = pbh_grow(h);
+  if (rc) return rc == PBH_ECAPACITY ? E_CAPACITY : E_DEVICE;
+  *g = pbh_geom(h);
+  return 0;
+}
+
+WideHeap wide_view(pbh* h) {
+  WideHeap w;
+  w.g = pbh_geom(h);
+  w.st = &h->host;
+  w.cur = h->cur;
+  w.bitmap = h->bitmap;
+  w.nwords = h->nwords;
+  w.sched = h->sched;
+  w.ukeys = h->ukeys;
+  w.uids = h->uids;
+  w.grow = wide_grow_cb;
+  w.ctx = h;
+  return w;
+}
+
+// A device-wide engine result -> PBH code; a failed step leaves the heap
+// unusable (its error is kept in the state).
+int wide_result(pbh* h, int rc) {
+  if (rc == 0) return PBH_OK;
+  if (!h->host.err) h->host.err = rc;
+  return state_error(h->host);
 }
 
 // k rule of sssp_opts -> SpecCfg (the list buffers are filled in by the caller).
@@ -173,11 +210,20 @@ extern "C" {
 
 const char* pbh_last_error(void) { return g_err; }
 
-int pbh_create(pbh_t** out, uint32_t id_capacity, uint32_t d) {
+int pbh_create(pbh_t** out, uint32_t id_capacity, uint32_t d) { return pbh_create_ex(out, id_capacity, d, nullptr); }
+
+int pbh_create_ex(pbh_t** out, uint32_t id_capacity, uint32_t d, const pbh_opts* opts) {
   if (!out) return fail(PBH_EINVAL, "pbh_create: out is NULL");
   *out = nullptr;
   if (id_capacity == 0 || d == 0) return fail(PBH_EINVAL, "pbh_create: id_capacity and d must be > 0");
+  pbh_opts o{};
+  if (opts) o = *opts;
+  if (o.engine > 2 || o.schedule > 1) return fail(PBH_EINVAL, "pbh_create_ex: engine must be 0..2, schedule 0..1");
+  for (uint32_t r : o.reserved)
+    if (r) return fail(PBH_EINVAL, "pbh_create_ex: reserved fields must be zero");
+  const bool wide = o.engine == 2 || (o.engine == 0 && d >= 16384);
   pbh* h = new pbh;
+  h->sched = (int)o.schedule;
   h->id_cap = id_capacity;
   h->d = d;
   // q = ceil(log4(n/d)) + 1 (Section 2.2): the deepest nominal bucket holds n.
@@ -201,6 +247,10 @@ int pbh_create(pbh_t** out, uint32_t id_capacity, uint32_t d) {
     state_init(&h->host, d, h->q);
     rc = push_state(h);
   }
+  if (!rc && wide) {
+    if (wide_create(&h->wide, d) || wide_reserve(h->wide, capB(d, h->q - 1)))
+      rc = fail(PBH_ENOMEM, "pbh_create: scratch of the device-wide engine: %s", hipGetErrorString(hipGetLastError()));
+  }
   if (rc) {
     pbh_destroy(h);
     return rc;
@@ -217,6 +267,7 @@ int pbh_destroy(pbh_t* h) {
   if (h->ukeys) (void)hipFree(h->ukeys);
   if (h->uids) (void)hipFree(h->uids);
   if (h->flag) (void)hipFree(h->flag);
+  if (h->wide) wide_destroy(h->wide);
   arena_free(&h->arena);
   delete h;
   return PBH_OK;
@@ -242,6 +293,10 @@ int pbh_bulk_update(pbh_t* h, const uint64_t* keys, const uint32_t* ids, uint64_
     HIPCHK(hipMalloc(&h->ukeys, need * sizeof(u64)));
     HIPCHK(hipMalloc(&h->uids, need * sizeof(u32)));
     h->ulist_cap = need;
+  }
+  if (h->wide) {
+    WideHeap w = wide_view(h);
+    return wide_result(h, wide_bulk_update(h->wide, &w, (const u64*)keys, ids, count));
   }
   h->host.aux[0] = h->host.aux[1] = h->host.aux[3] = 0;
   h->host.progress = 0;
@@ -277,6 +332,10 @@ int pbh_extract_min(pbh_t* h, uint64_t k, uint64_t* keys_out, uint32_t* ids_out,
   if (k == 0) return PBH_OK;
   if (!keys_out || !ids_out) return fail(PBH_EINVAL, "pbh_extract_min: NULL output arrays");
   if (h->host.err) return state_error(h->host);
+  if (h->wide) {
+    WideHeap w = wide_view(h);
+    return wide_result(h, wide_extract_min(h->wide, &w, k, (u64*)keys_out, ids_out, (u64*)count_out));
+  }
   h->host.progress = 0;
   h->host.aux[3] = h->host.aux[4] = 0;
   int rc = push_state(h);
@@ -299,6 +358,14 @@ int pbh_extract_min(pbh_t* h, uint64_t k, uint64_t* keys_out, uint32_t* ids_out,
     if ((rc = pbh_grow(h))) return rc;
   }
   *count_out = h->host.progress;
+  return PBH_OK;
+}
+
+int pbh_traffic(pbh_t* h, uint64_t* elements_out) {
+  if (!h || !elements_out) return fail(PBH_EINVAL, "pbh_traffic: NULL argument");
+  int rc = pull_state(h);
+  if (rc) return rc;
+  *elements_out = h->host.elems;
   return PBH_OK;
 }
 

@@ -778,8 +778,11 @@ enum { DRIVE_AFTER = 1, DRIVE_ENSURE = 2 };
 // level can take all of S_j and B_j, then resolve j, j-1, ..., x.  After
 // Resolve(j), level j has S_j empty and |B_j| <= 2d*4^j, which always leaves
 // room for level j-1.
-template <class T, class P>
-PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur, int sched, int what) {
+//
+// `res(i)` performs Resolve(i) on `st`: the team's own Resolve in the kernels,
+// or the device-wide engine driven from the host.
+template <class T, class SP, class R>
+PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R&& res) {
   int tgt = -1, chain = -1;  // pending chain: levels chain, chain-1, ..., tgt
   int stage = (what & DRIVE_AFTER) ? 0 : 2;
   int si = 0;                // schedule position
@@ -841,8 +844,13 @@ PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur,
       lvl = j;
       chain = j > x ? j - 1 : -1;
     }
-    resolve<T, P>(t, g, st, cur, lvl);
+    res(lvl);
   }
+}
+
+template <class T, class P>
+PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur, int sched, int what) {
+  drive_with(t, g, st, sched, what, [&](int lvl) { resolve<T, P>(t, g, st, cur, lvl); });
 }
 
 // ---------------------------------------------------------------- parDijkstra

@@ -1,0 +1,49 @@
+// Device-wide engine of the parallel bucket heap, for large bulk sizes d.
+//
+// With d in the hundreds of thousands, one Resolve moves tens of megabytes,
+// which a single workgroup cannot stream at HBM speed.  This engine runs every
+// step of Algorithm 1 (Merge with DeleteDuplicates, Select, the splits) as a
+// grid-wide kernel over the whole device, and the host runs Resolve's control
+// flow and the schedule (drive_with, shared with the one-workgroup kernels),
+// reading back the few sizes each step produces.  The heap state (sizes,
+// pivots, buffer selectors) lives on the host; the arrays live in the same
+// level arena as the one-workgroup engine's.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pbh_core.h"
+
+namespace bkt {
+
+struct WideScratch;
+
+// What the engine needs from a heap handle.  `grow` adds one level to the
+// arena (existing levels keep their offsets) and refreshes `g`.
+struct WideHeap {
+  Geom g;
+  HeapState* st;  // host-side state, authoritative for this engine
+  u64* cur;       // device: current key of every id (KINF = absent)
+  u32* bitmap;    // device: one bit per id, all zero between calls
+  u32 nwords;
+  int sched;
+  u64* ukeys;     // device: room for min(count, id_capacity) update pairs
+  u32* uids;
+  int (*grow)(void* ctx, Geom* g);
+  void* ctx;
+};
+
+// Error codes: 0, E_CAPACITY, E_INTERNAL, or E_DEVICE for a failed HIP call.
+constexpr int E_DEVICE = -4;
+
+int wide_create(WideScratch** out, u32 d);
+void wide_destroy(WideScratch* w);
+// Makes room for arrays of up to `elems` elements (called after growth).
+int wide_reserve(WideScratch* w, u64 elems);
+
+// BulkUpdate of `count` pairs (device arrays, already validated).
+int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* ids, u64 count);
+// Batched ExtractMin of up to k elements into device arrays okeys/oids,
+// ascending by (key, id); *count_out = number written.
+int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out);
+
+}  // namespace bkt

@@ -1,0 +1,1134 @@
+// Device-wide engine of the parallel bucket heap (see wide.h).
+//
+// Kernels (256 threads per workgroup, tiles of 2048 elements):
+//   k_mpart / k_merge<false> / k_scan / k_merge<true>
+//       Merge of two id-sorted arrays with DeleteDuplicates (Section 2.1):
+//       merge-path split points per tile, a counting pass, a scan of the tile
+//       counts, and a writing pass that stages the tile in LDS and stores it
+//       coalesced.  The writing pass also counts outputs <= a pivot (the count
+//       in Resolve's EMPTY step) and the key range (the start of Select).
+//   k_part<false> / k_scan3 / k_part<true>
+//       Stable three-way split by two (key, id) pivots.
+//   k_sel_*
+//       Select: radix selection on the 96-bit (key, id) value, 11 bits per
+//       pass from the first bit where the keys differ, until few candidates
+//       remain; those are gathered and sorted in one workgroup.
+//   k_intake / k_bits<false> / k_bits<true>
+//       BulkUpdate intake: atomicMin on the current keys, an id bitmap of the
+//       ids whose key dropped, and its compaction into U sorted by id.
+//   k_tsort / k_spart / k_smerge
+//       Sorting the extracted minima by (key, id): bitonic sort of tiles in
+//       LDS, then merge passes.
+//   k_absent
+//       Marks extracted ids absent.
+#include "wide.h"
+
+#include <algorithm>
+#include <cstring>
+
+#include "pbh_team.h"
+
+namespace bkt {
+namespace {
+
+constexpr int NT = 256;
+constexpr int WE = 8;
+constexpr u32 TILE = NT * WE;  // 2048
+constexpr int SEL_BITS = 11;
+constexpr int SEL_BINS = 1 << SEL_BITS;
+constexpr u32 CANDMAX = 4096;
+constexpr int GRID_STRIDE = 2048;  // workgroups of the grid-stride kernels
+
+// Results of the device steps, copied to the host after each step.
+struct Ctl {
+  u32 total;    // output size of a merge or the bitmap compaction
+  u32 num_le;   // merge outputs <= the counting pivot
+  u32 part[4];  // three-way split sizes
+  u64 kmin, kmax;
+  u64 newly;    // ids inserted (absent before) by the intake
+  // selection state
+  u64 spk;
+  u32 spv;
+  int snb;      // leading bits of (key, id) fixed so far
+  u32 srank;    // rank still sought among the elements with that prefix
+  u32 scnt;     // elements with that prefix
+  int sdone;    // few enough candidates: gather them
+  int sfail;    // the gather ran before the passes were done
+  int sbad;     // no bin held the rank (never expected)
+  u32 sncand;
+  u64 rk;       // the selected element
+  u32 rv;
+  u32 pad;
+  u32 shist[SEL_BINS];
+};
+constexpr size_t CTL_HEAD = offsetof(Ctl, shist);
+
+__device__ __forceinline__ u64 atomic_min64(u64* p, u64 v) {
+  return __hip_atomic_fetch_min((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 atomic_max64(u64* p, u64 v) {
+  return __hip_atomic_fetch_max((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32 atomic_add32(u32* p, u32 v) {
+  return __hip_atomic_fetch_add((u32 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 atomic_add64(u64* p, u64 v) {
+  return __hip_atomic_fetch_add((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive scan over the workgroup (NTH threads); *total = the sum.
+// sw: LDS scratch of NTH/64 words.
+template <int NTH>
+__device__ __forceinline__ u32 block_scan(u32 x, u32* total, u32* sw) {
+  u32 inc = wave_incl(x);
+  const int w = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 63) sw[w] = inc;
+  __syncthreads();
+  u32 pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NTH / 64; ++k) {
+    u32 s = sw[k];
+    pre += k < w ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + inc - x;
+}
+template <int NTH>
+__device__ __forceinline__ u32 block_sum(u32 x, u32* sw) {
+  u32 t;
+  block_scan<NTH>(x, &t, sw);
+  return t;
+}
+template <int NTH>
+__device__ __forceinline__ void block_minmax(u64& lo, u64& hi, u64* swl, u64* swh) {
+  wave_minmax64(lo, hi);
+  const int w = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) {
+    swl[w] = lo;
+    swh[w] = hi;
+  }
+  __syncthreads();
+  lo = swl[0];
+  hi = swh[0];
+#pragma unroll
+  for (int k = 1; k < NTH / 64; ++k) {
+    lo = swl[k] < lo ? swl[k] : lo;
+    hi = swh[k] > hi ? swh[k] : hi;
+  }
+  __syncthreads();
+}
+
+// How many of the first `diag` elements of merge(A, B) come from A; ties go
+// to A first.  ById compares ids, otherwise (key, id).
+template <bool BYKV, class KP, class VP>
+__device__ __forceinline__ u32 mpath(KP ak, VP av, u32 na, KP bk, VP bv, u32 nb, u32 diag) {
+  u32 lo = diag > nb ? diag - nb : 0u, hi = diag < na ? diag : na;
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1, jb = diag - 1 - mid;
+    bool afirst;
+    if constexpr (BYKV) {
+      u64 ka = ak[mid], kb = bk[jb];
+      afirst = ka < kb || (ka == kb && av[mid] <= bv[jb]);
+    } else {
+      afirst = av[mid] <= bv[jb];
+    }
+    if (afirst)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ merge by id
+
+struct MArgs {
+  const u64* ak;
+  const u32* av;
+  u32 na;
+  const u64* bk;
+  const u32* bv;
+  u32 nb;
+  u64* ck;
+  u32* cv;
+  const u64* cur;  // liveness for PREFER_LIVE and filterB (may be null)
+  int prefer;
+  int filterB;
+  u64 pk;          // outputs <= (pk, pv) are counted
+  u32 pv;
+};
+
+// The copy kept when A and B hold the same id (DeleteDuplicates).
+__device__ __forceinline__ bool pair_keep(const MArgs& a, u64 ka, u64 kb, u32 v, u64* k) {
+  if (a.prefer == PREFER_B) {
+    *k = kb;
+    return true;
+  }
+  if (a.prefer == PREFER_A || ka == kb) {
+    *k = ka;
+    return true;
+  }
+  if (a.cur) {
+    u64 c = a.cur[v];
+    *k = kb == c ? kb : ka;
+    return ka == c || kb == c;
+  }
+  *k = ka < kb ? ka : kb;
+  return true;
+}
+
+__global__ void k_mpart(const u32* av, u32 na, const u32* bv, u32 nb, u32 ntiles, u32* part) {
+  u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > ntiles) return;
+  u64 total = (u64)na + nb;
+  u64 dg = (u64)t * TILE;
+  u32 diag = (u32)(dg < total ? dg : total);
+  part[t] = mpath<false>((const u64*)nullptr, av, na, (const u64*)nullptr, bv, nb, diag);
+}
+
+// One tile of merge(A, B) by id with DeleteDuplicates.  Counting pass: tcnt[t]
+// = kept outputs.  Writing pass: the kept outputs go to C at toff[t].
+template <bool WRITE>
+__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Ctl* ctl) {
+  __shared__ u64 sk[WRITE ? TILE : 1];
+  __shared__ u32 sv[TILE];
+  __shared__ u32 sw[NT / 64];
+  __shared__ u64 swl[NT / 64], swh[NT / 64];
+  const u32 t = blockIdx.x, total = a.na + a.nb;
+  const u32 d0 = t * TILE, d1 = min(d0 + TILE, total);
+  const u32 i0 = part[t], i1 = part[t + 1];
+  const u32 j0 = d0 - i0, j1 = d1 - i1;
+  const u32 nA = i1 - i0, nT = d1 - d0, nB = nT - nA;
+  for (u32 x = threadIdx.x; x < nT; x += NT) {
+    if (x < nA) {
+      sv[x] = a.av[i0 + x];
+      if constexpr (WRITE) sk[x] = a.ak[i0 + x];
+    } else {
+      sv[x] = a.bv[j0 + x - nA];
+      if constexpr (WRITE) sk[x] = a.bk[j0 + x - nA];
+    }
+  }
+  // neighbours just outside the tile decide duplicates across its edges
+  const bool hasPrev = i0 > 0, hasNext = j1 < a.nb;
+  const u32 aprev = hasPrev ? a.av[i0 - 1] : 0u, bnext = hasNext ? a.bv[j1] : 0u;
+  __syncthreads();
+  const u32* sA = sv;
+  const u32* sB = sv + nA;
+  const u32 dd0 = min((u32)threadIdx.x * WE, nT), dd1 = min(dd0 + WE, nT);
+  u32 i = mpath<false>((const u64*)nullptr, sA, nA, (const u64*)nullptr, sB, nB, dd0), j = dd0 - i;
+  u64 ko[WE];
+  u32 vo[WE];
+  u32 keep = 0;
+#pragma unroll
+  for (int s = 0; s < WE; ++s) {
+    ko[s] = 0;
+    vo[s] = 0;
+    if (dd0 + s < dd1) {
+      const bool takeA = i < nA && (j >= nB || sA[i] <= sB[j]);
+      bool kp = true;
+      u64 k = 0;
+      u32 v;
+      if (takeA) {
+        v = sA[i];
+        const bool dup = j < nB ? sB[j] == v : (hasNext && bnext == v);
+        if constexpr (WRITE) k = sk[i];
+        if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
+          u64 ka, kb;
+          if constexpr (WRITE) {
+            ka = sk[i];
+            kb = j < nB ? sk[nA + j] : a.bk[j1];
+          } else {
+            ka = a.ak[i0 + i];
+            kb = j < nB ? a.bk[j0 + j] : a.bk[j1];
+          }
+          kp = pair_keep(a, ka, kb, v, &k);
+        }
+        ++i;
+      } else {
+        v = sB[j];
+        const bool prevdup = i > 0 ? sA[i - 1] == v : (hasPrev && aprev == v);
+        kp = !prevdup;
+        if constexpr (WRITE) {
+          k = sk[nA + j];
+        } else {
+          if (kp && a.filterB) k = a.bk[j0 + j];
+        }
+        if (kp && a.filterB && a.cur[v] != k) kp = false;
+        ++j;
+      }
+      ko[s] = k;
+      vo[s] = v;
+      keep |= (u32)kp << s;
+    }
+  }
+  const u32 c = (u32)__builtin_popcount(keep);
+  if constexpr (!WRITE) {
+    u32 tot = block_sum<NT>(c, sw);
+    if (threadIdx.x == 0) tcnt[t] = tot;
+  } else {
+    u32 tot;
+    u32 pos = block_scan<NT>(c, &tot, sw);  // also orders the LDS reads above before the writes below
+    u32 nle = 0;
+    u64 lo = KINF, hi = 0;
+#pragma unroll
+    for (int s = 0; s < WE; ++s)
+      if ((keep >> s) & 1u) {
+        sk[pos] = ko[s];
+        sv[pos] = vo[s];
+        ++pos;
+        nle += kv_le(KV{ko[s], vo[s]}, KV{a.pk, a.pv});
+        lo = ko[s] < lo ? ko[s] : lo;
+        hi = ko[s] > hi ? ko[s] : hi;
+      }
+    __syncthreads();
+    const u32 base = toff[t];
+    for (u32 x = threadIdx.x; x < tot; x += NT) {
+      a.ck[base + x] = sk[x];
+      a.cv[base + x] = sv[x];
+    }
+    nle = block_sum<NT>(nle, sw);
+    block_minmax<NT>(lo, hi, swl, swh);
+    if (threadIdx.x == 0) {
+      if (nle) atomic_add32(&ctl->num_le, nle);
+      if (tot) {
+        atomic_min64(&ctl->kmin, lo);
+        atomic_max64(&ctl->kmax, hi);
+      }
+    }
+  }
+}
+
+// Exclusive scan of n tile counts (one workgroup of 1024); *total = the sum.
+// blockIdx.x selects one of several count arrays spaced `stride` apart.
+__global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride, u32* off, u32* total) {
+  __shared__ u32 sw[16];
+  cnt += (u64)blockIdx.x * stride;
+  off += (u64)blockIdx.x * stride;
+  u32 carry = 0;
+  for (u32 b = 0; b < n; b += 1024) {
+    u32 x = b + threadIdx.x;
+    u32 v = x < n ? cnt[x] : 0u;
+    u32 tot;
+    u32 e = block_scan<1024>(v, &tot, sw);
+    if (x < n) off[x] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) total[blockIdx.x] = carry;
+}
+
+__global__ void k_ctl_reset(Ctl* c) {
+  if (threadIdx.x == 0) {
+    c->total = 0;
+    c->num_le = 0;
+    c->part[0] = c->part[1] = c->part[2] = c->part[3] = 0;
+    c->kmin = KINF;
+    c->kmax = 0;
+    c->newly = 0;
+  }
+}
+
+// ------------------------------------------------------------------ three-way split
+
+struct PArgs {
+  const u64* k;
+  const u32* v;
+  u32 n;
+  u64 p1k;
+  u32 p1v;
+  u64 p2k;
+  u32 p2v;
+  const u64* live;  // class-0 elements whose key is not live[id] are dropped
+  u64* ok[3];
+  u32* ov[3];
+};
+
+__device__ __forceinline__ u32 pclass(const PArgs& a, u64 k, u32 v) {
+  KV e{k, v};
+  u32 c = kv_le(e, KV{a.p1k, a.p1v}) ? 0u : (kv_le(e, KV{a.p2k, a.p2v}) ? 1u : 2u);
+  if (c == 0 && a.live && a.live[v] != k) c = 3;
+  return c;
+}
+
+// Tile t = elements [t*TILE, (t+1)*TILE), visited in WE rounds of NT
+// consecutive elements so that each round's outputs are written coalesced.
+template <bool WRITE>
+__global__ __launch_bounds__(NT) void k_part(PArgs a, u32* tc, const u32* toff, u32 stride) {
+  __shared__ u32 sw[NT / 64];
+  const u32 t = blockIdx.x;
+  const u64 base = (u64)t * TILE;
+  u32 c01 = 0, c2 = 0;
+  u32 run[3] = {0, 0, 0};
+  if constexpr (WRITE) {
+    run[0] = toff[t];
+    run[1] = toff[stride + t];
+    run[2] = toff[2 * stride + t];
+  }
+#pragma unroll
+  for (int r = 0; r < WE; ++r) {
+    const u64 x = base + (u64)r * NT + threadIdx.x;
+    u32 c = 3;
+    u64 k = 0;
+    u32 v = 0;
+    if (x < a.n) {
+      k = a.k[x];
+      v = a.v[x];
+      c = pclass(a, k, v);
+    }
+    if constexpr (!WRITE) {
+      c01 += c == 0 ? 1u : (c == 1 ? 1u << 16 : 0u);
+      c2 += c == 2;
+    } else {
+      u32 tot;
+      u32 e = block_scan<NT>(c < 3 ? 1u << (10 * c) : 0u, &tot, sw);
+      if (c < 3) {
+        u32 pos = run[c] + ((e >> (10 * c)) & 1023u);
+        a.ok[c][pos] = k;
+        a.ov[c][pos] = v;
+      }
+      run[0] += tot & 1023u;
+      run[1] += (tot >> 10) & 1023u;
+      run[2] += (tot >> 20) & 1023u;
+    }
+  }
+  if constexpr (!WRITE) {
+    c01 = block_sum<NT>(c01, sw);
+    c2 = block_sum<NT>(c2, sw);
+    if (threadIdx.x == 0) {
+      tc[t] = c01 & 0xFFFFu;
+      tc[stride + t] = c01 >> 16;
+      tc[2 * stride + t] = c2;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Select
+
+__device__ __forceinline__ bool sel_match(u64 k, u32 v, u64 pk, u32 pv, int nb) {
+  if (nb == 0) return true;
+  if (nb <= 64) return (k >> (64 - nb)) == (pk >> (64 - nb));
+  if (k != pk) return false;
+  const int r = nb - 64;
+  return (v >> (32 - r)) == (pv >> (32 - r));
+}
+// Bits [p, p + w) of the 96-bit value key * 2^32 + id.
+__device__ __forceinline__ u32 sel_digit(u64 k, u32 v, int p, int w) {
+  const u32 mask = (1u << w) - 1u;
+  if (p >= 32) return (u32)(k >> (p - 32)) & mask;
+  return (u32)(((k << 32) | v) >> p) & mask;
+}
+
+// Starts a selection of the element of rank r (1-based) among n, whose keys
+// lie in [ctl->kmin, ctl->kmax].
+__global__ __launch_bounds__(NT) void k_sel_init(Ctl* c, u32 r, u32 n) {
+  for (int b = threadIdx.x; b < SEL_BINS; b += NT) c->shist[b] = 0;
+  if (threadIdx.x == 0) {
+    const u64 mn = c->kmin, mx = c->kmax;
+    int nb;
+    u64 pk;
+    if (mn == mx) {
+      nb = 64;
+      pk = mn;
+    } else {
+      nb = __builtin_clzll(mn ^ mx);
+      pk = nb ? (mn >> (64 - nb)) << (64 - nb) : 0ull;
+    }
+    c->spk = pk;
+    c->spv = 0;
+    c->snb = nb;
+    c->srank = r;
+    c->scnt = n;
+    c->sdone = n <= CANDMAX;
+    c->sfail = 0;
+    c->sbad = 0;
+    c->sncand = 0;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_sel_hist(const u64* K, const u32* V, u32 n, Ctl* c) {
+  __shared__ u32 h[SEL_BINS];
+  if (c->sdone) return;
+  const u64 pk = c->spk;
+  const u32 pv = c->spv;
+  const int nb = c->snb;
+  const int w = 96 - nb < SEL_BITS ? 96 - nb : SEL_BITS;
+  const int p = 96 - nb - w;
+  for (int b = threadIdx.x; b < SEL_BINS; b += NT) h[b] = 0;
+  __syncthreads();
+  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
+    u64 k = K[x];
+    u32 v = V[x];
+    if (sel_match(k, v, pk, pv, nb)) atomicAdd(&h[sel_digit(k, v, p, w)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < SEL_BINS; b += NT)
+    if (h[b]) atomic_add32(&c->shist[b], h[b]);
+}
+
+__global__ __launch_bounds__(NT) void k_sel_pick(Ctl* c) {
+  __shared__ u32 sw[NT / 64];
+  if (c->sdone) return;
+  constexpr int PER = SEL_BINS / NT;
+  u32 loc[PER];
+  u32 sum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    loc[q] = c->shist[threadIdx.x * PER + q];
+    sum += loc[q];
+  }
+  u32 tot;
+  u32 before = block_scan<NT>(sum, &tot, sw);
+  const u32 rank = c->srank;
+  const int nb = c->snb;
+  const int w = 96 - nb < SEL_BITS ? 96 - nb : SEL_BITS;
+  const int p = 96 - nb - w;
+  if (before < rank && rank <= before + sum) {
+    u32 acc = before;
+    for (int q = 0; q < PER; ++q) {
+      if (acc + loc[q] >= rank) {
+        const u32 b = threadIdx.x * PER + q;
+        u64 pk = c->spk;
+        u32 pv = c->spv;
+        if (p >= 32) {
+          pk |= (u64)b << (p - 32);
+        } else {
+          u64 lo = ((pk & 0xFFFFFFFFull) << 32) | pv;
+          lo |= (u64)b << p;
+          pk = (pk & 0xFFFFFFFF00000000ull) | (lo >> 32);
+          pv = (u32)lo;
+        }
+        c->spk = pk;
+        c->spv = pv;
+        c->snb = nb + w;
+        c->srank = rank - acc;
+        c->scnt = loc[q];
+        c->sdone = loc[q] <= CANDMAX || nb + w == 96;
+        break;
+      }
+      acc += loc[q];
+    }
+  }
+  if (threadIdx.x == 0 && (rank == 0 || rank > tot)) {
+    c->sbad = 1;
+    c->sdone = 1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) c->shist[threadIdx.x * PER + q] = 0;
+}
+
+__global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, u32 n, Ctl* c, u64* ck, u32* cv) {
+  const int done = c->sdone;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->sfail = !done;
+  if (!done) return;
+  const u64 pk = c->spk;
+  const u32 pv = c->spv;
+  const int nb = c->snb;
+  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
+    u64 k = K[x];
+    u32 v = V[x];
+    if (sel_match(k, v, pk, pv, nb)) {
+      u32 o = atomic_add32(&c->sncand, 1u);
+      if (o < CANDMAX) {
+        ck[o] = k;
+        cv[o] = v;
+      }
+    }
+  }
+}
+
+// Bitonic sort of N (key, id) pairs in LDS by (key, id), NTH threads.
+template <u32 N, int NTH>
+__device__ void bitonic_lds(u64* k, u32* v) {
+  for (u32 size = 2; size <= N; size <<= 1)
+    for (u32 stride = size >> 1; stride > 0; stride >>= 1) {
+      for (u32 q = threadIdx.x; q < N / 2; q += NTH) {
+        const u32 lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        u64 ka = k[lo], kb = k[hi];
+        u32 va = v[lo], vb = v[hi];
+        const bool gt = ka > kb || (ka == kb && va > vb);
+        if (gt == up) {
+          k[lo] = kb;
+          k[hi] = ka;
+          v[lo] = vb;
+          v[hi] = va;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv) {
+  __shared__ u64 sk[CANDMAX];
+  __shared__ u32 sv[CANDMAX];
+  if (!c->sdone || c->sbad) return;
+  const u32 n = c->sncand < CANDMAX ? c->sncand : CANDMAX;
+  for (u32 x = threadIdx.x; x < CANDMAX; x += 1024) {
+    sk[x] = x < n ? ck[x] : KINF;
+    sv[x] = x < n ? cv[x] : VINF;
+  }
+  __syncthreads();
+  bitonic_lds<CANDMAX, 1024>(sk, sv);
+  if (threadIdx.x == 0) {
+    const u32 r = c->srank;
+    if (r == 0 || r > n || c->sncand != c->scnt) {
+      c->sbad = 1;
+    } else {
+      c->rk = sk[r - 1];
+      c->rv = sv[r - 1];
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Ctl* c) {
+  __shared__ u64 swl[NT / 64], swh[NT / 64];
+  u64 lo = KINF, hi = 0;
+  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
+    u64 k = K[x];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  block_minmax<NT>(lo, hi, swl, swh);
+  if (threadIdx.x == 0 && lo <= hi) {
+    atomic_min64(&c->kmin, lo);
+    atomic_max64(&c->kmax, hi);
+  }
+}
+
+// ------------------------------------------------------------------ intake
+
+__global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, u64 count, u64* cur, u32* bitmap,
+                                               Ctl* c) {
+  __shared__ u32 sw[NT / 64];
+  u32 newly = 0;
+  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < count; x += (u64)gridDim.x * NT) {
+    const u32 id = ids[x];
+    const u64 k = keys[x];
+    const u64 old = atomic_min64(cur + id, k);
+    if (k < old) {
+      __hip_atomic_fetch_or((u32 PBH_GLB*)(bitmap + (id >> 5)), 1u << (id & 31), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+      newly += old == KINF;
+    }
+  }
+  newly = block_sum<NT>(newly, sw);
+  if (threadIdx.x == 0 && newly) atomic_add64(&c->newly, newly);
+}
+
+// Bitmap compaction: set bits in increasing id order -> (cur[id], id); the
+// words are cleared.  Tile t = words [t*TILE, (t+1)*TILE) in WE rounds.
+template <bool WRITE>
+__global__ __launch_bounds__(NT) void k_bits(u32* bitmap, u32 nwords, u32* tc, const u32* toff, const u64* cur,
+                                             u64* uk, u32* uv) {
+  __shared__ u32 sw[NT / 64];
+  const u32 t = blockIdx.x;
+  u32 run = WRITE ? toff[t] : 0u, cnt = 0;
+#pragma unroll
+  for (int r = 0; r < WE; ++r) {
+    const u64 w = (u64)t * TILE + (u64)r * NT + threadIdx.x;
+    u32 bits = w < nwords ? bitmap[w] : 0u;
+    u32 pc = (u32)__builtin_popcount(bits);
+    if constexpr (!WRITE) {
+      cnt += pc;
+    } else {
+      u32 tot;
+      u32 o = run + block_scan<NT>(pc, &tot, sw);
+      if (bits) bitmap[w] = 0u;
+      while (bits) {
+        const u32 b = (u32)__builtin_ctz(bits);
+        bits &= bits - 1;
+        const u32 id = (u32)w * 32u + b;
+        uv[o] = id;
+        uk[o] = cur[id];
+        ++o;
+      }
+      run += tot;
+    }
+  }
+  if constexpr (!WRITE) {
+    cnt = block_sum<NT>(cnt, sw);
+    if (threadIdx.x == 0) tc[t] = cnt;
+  }
+}
+
+__global__ void k_absent(const u32* ids, u64 n, u64* cur) {
+  for (u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (u64)gridDim.x * blockDim.x)
+    cur[ids[x]] = KINF;
+}
+
+// ------------------------------------------------------------------ sort by (key, id)
+
+__global__ __launch_bounds__(NT) void k_tsort(const u64* sk_, const u32* sv_, u32 n, u64* dk, u32* dv) {
+  __shared__ u64 sk[TILE];
+  __shared__ u32 sv[TILE];
+  const u64 base = (u64)blockIdx.x * TILE;
+  for (u32 x = threadIdx.x; x < TILE; x += NT) {
+    const u64 g = base + x;
+    sk[x] = g < n ? sk_[g] : KINF;
+    sv[x] = g < n ? sv_[g] : VINF;
+  }
+  __syncthreads();
+  bitonic_lds<TILE, NT>(sk, sv);
+  for (u32 x = threadIdx.x; x < TILE; x += NT) {
+    const u64 g = base + x;
+    if (g < n) {
+      dk[g] = sk[x];
+      dv[g] = sv[x];
+    }
+  }
+}
+
+// Merge pass over sorted runs of length L (a multiple of TILE): runs 2p and
+// 2p+1 are merged into [2pL, 2pL + 2L).  part[t] = A-elements before output
+// tile t within its pair.
+__device__ __forceinline__ void run_pair(u32 n, u32 L, u64 s, u32* base, u32* na, u32* nb) {
+  const u64 b = (s / (2ull * L)) * 2ull * L;
+  const u64 mid = b + L < n ? b + L : n, end = b + 2ull * L < n ? b + 2ull * L : n;
+  *base = (u32)b;
+  *na = (u32)(mid - b);
+  *nb = (u32)(end - mid);
+}
+
+__global__ void k_spart(const u64* K, const u32* V, u32 n, u32 L, u32 ntiles, u32* part) {
+  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  u32 b, na, nb;
+  run_pair(n, L, (u64)t * TILE, &b, &na, &nb);
+  part[t] = mpath<true>(K + b, V + b, na, K + b + na, V + b + na, nb, t * TILE - b);
+}
+
+__global__ __launch_bounds__(NT) void k_smerge(const u64* K, const u32* V, u32 n, u32 L, const u32* part, u64* DK,
+                                               u32* DV) {
+  __shared__ u64 sk[TILE];
+  __shared__ u32 sv[TILE];
+  const u32 t = blockIdx.x;
+  const u64 s = (u64)t * TILE;
+  u32 b, na, nb;
+  run_pair(n, L, s, &b, &na, &nb);
+  const u32 d0 = (u32)(s - b);
+  const u32 d1 = min(d0 + TILE, na + nb);
+  const u32 i0 = part[t];
+  const u32 i1 = d1 == na + nb ? na : part[t + 1];
+  const u32 j0 = d0 - i0, j1 = d1 - i1;
+  const u32 nA = i1 - i0, nT = d1 - d0, nB = j1 - j0;
+  for (u32 x = threadIdx.x; x < nT; x += NT) {
+    const u32 g = x < nA ? b + i0 + x : b + na + j0 + (x - nA);
+    sk[x] = K[g];
+    sv[x] = V[g];
+  }
+  __syncthreads();
+  const u32 dd0 = min((u32)threadIdx.x * WE, nT), dd1 = min(dd0 + WE, nT);
+  u32 i = mpath<true>(sk, sv, nA, sk + nA, sv + nA, nB, dd0), j = dd0 - i;
+  u64 ko[WE];
+  u32 vo[WE];
+#pragma unroll
+  for (int q = 0; q < WE; ++q) {
+    ko[q] = 0;
+    vo[q] = 0;
+    if (dd0 + q < dd1) {
+      bool takeA = i < nA;
+      if (takeA && j < nB) {
+        const u64 ka = sk[i], kb = sk[nA + j];
+        takeA = ka < kb || (ka == kb && sv[i] <= sv[nA + j]);
+      }
+      if (takeA) {
+        ko[q] = sk[i];
+        vo[q] = sv[i];
+        ++i;
+      } else {
+        ko[q] = sk[nA + j];
+        vo[q] = sv[nA + j];
+        ++j;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < WE; ++q)
+    if (dd0 + q < dd1) {
+      sk[dd0 + q] = ko[q];
+      sv[dd0 + q] = vo[q];
+    }
+  __syncthreads();
+  for (u32 x = threadIdx.x; x < nT; x += NT) {
+    DK[s + x] = sk[x];
+    DV[s + x] = sv[x];
+  }
+}
+
+u32 cdiv(u64 a, u64 b) { return (u32)((a + b - 1) / b); }
+u32 grid_for(u64 n) {
+  u64 g = (n + NT - 1) / NT;
+  return (u32)(g < 1 ? 1 : (g > GRID_STRIDE ? GRID_STRIDE : g));
+}
+
+}  // namespace
+
+struct WideScratch {
+  u32 d = 0;
+  Ctl* ctl = nullptr;   // device
+  Ctl* hctl = nullptr;  // pinned host copy of the header
+  u32* part = nullptr;  // tile split points (maxtiles + 1)
+  u32* tc = nullptr;    // tile counts, 3 arrays of maxtiles
+  u32* toff = nullptr;  // tile offsets, 3 arrays of maxtiles
+  u64* cand_k = nullptr;
+  u32* cand_v = nullptr;
+  u64* tmp_k = nullptr;  // sort scratch (4d elements)
+  u32* tmp_v = nullptr;
+  u32 maxtiles = 0;
+  hipStream_t s = 0;
+};
+
+namespace {
+
+#define WCHK(x)                               \
+  do {                                        \
+    if ((x) != hipSuccess) return E_DEVICE;   \
+  } while (0)
+
+int fetch(WideScratch* w) {
+  WCHK(hipMemcpyAsync(w->hctl, w->ctl, CTL_HEAD, hipMemcpyDeviceToHost, w->s));
+  WCHK(hipStreamSynchronize(w->s));
+  return 0;
+}
+
+int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : E_DEVICE; }
+
+// C = DeleteDuplicates(Merge(A, B)) by id; *num_le = outputs <= piv.
+int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, int prefer, bool filterB, KV piv,
+           u32* m, u32* num_le) {
+  const u64 total = (u64)na + nb;
+  if (total == 0) {
+    *m = 0;
+    *num_le = 0;
+    return 0;
+  }
+  const u32 nt = cdiv(total, TILE);
+  if (nt > w->maxtiles) return E_INTERNAL;
+  MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
+  hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
+  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->ctl);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
+  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->ctl);
+  if (int rc = launch_ok()) return rc;
+  if (int rc = fetch(w)) return rc;
+  *m = w->hctl->total;
+  *num_le = w->hctl->num_le;
+  return 0;
+}
+
+// Element of rank r (1-based) among A[0, n); the key range must be in ctl
+// (from the merge that wrote A) unless have_range is false.
+int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
+  if (!have_range) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
+    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n)), dim3(NT), 0, w->s, A.k, n, w->ctl);
+  }
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(NT), 0, w->s, w->ctl, r, n);
+  const u32 g = grid_for(n);
+  // Each pass fixes 11 more of the 96 bits, so 9 passes always finish.
+  for (int round = 0; round < 3; ++round) {
+    for (int p = 0; p < 3; ++p) {
+      hipLaunchKernelGGL(k_sel_hist, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl);
+      hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(NT), 0, w->s, w->ctl);
+    }
+    hipLaunchKernelGGL(k_sel_collect, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v);
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1024), 0, w->s, w->ctl, w->cand_k, w->cand_v);
+    if (int rc = launch_ok()) return rc;
+    if (int rc = fetch(w)) return rc;
+    if (w->hctl->sbad) return E_INTERNAL;
+    if (!w->hctl->sfail) {
+      *out = KV{w->hctl->rk, w->hctl->rv};
+      return 0;
+    }
+  }
+  return E_INTERNAL;
+}
+
+int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, const u64* live, u32* n0,
+                u32* n1, u32* n2) {
+  if (n == 0) {
+    *n0 = *n1 = *n2 = 0;
+    return 0;
+  }
+  const u32 nt = cdiv(n, TILE);
+  if (nt > w->maxtiles) return E_INTERNAL;
+  PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}};
+  hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
+  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->ctl->part);
+  hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
+  if (int rc = launch_ok()) return rc;
+  if (int rc = fetch(w)) return rc;
+  *n0 = w->hctl->part[0];
+  *n1 = w->hctl->part[1];
+  *n2 = w->hctl->part[2];
+  return 0;
+}
+
+// Sorts X[0, n) by (key, id) into D (n <= 4d; X is overwritten).
+int wsort(WideScratch* w, Arr X, u32 n, u64* dk, u32* dv) {
+  if (n == 0) return 0;
+  const u32 nt = cdiv(n, TILE);
+  if (nt > w->maxtiles) return E_INTERNAL;
+  int passes = 0;
+  for (u64 L = TILE; L < n; L *= 2) ++passes;
+  // ping-pong so that the last pass lands in D
+  Arr bufs[2] = {X, Arr{w->tmp_k, w->tmp_v}};
+  Arr dst = passes == 0 ? Arr{dk, dv} : bufs[(passes & 1) ? 1 : 0];
+  hipLaunchKernelGGL(k_tsort, dim3(nt), dim3(NT), 0, w->s, X.k, X.v, n, dst.k, dst.v);
+  Arr src = dst;
+  u64 L = TILE;
+  for (int p = 0; p < passes; ++p, L *= 2) {
+    Arr to = p == passes - 1 ? Arr{dk, dv} : (src.k == bufs[0].k ? bufs[1] : bufs[0]);
+    hipLaunchKernelGGL(k_spart, dim3(cdiv(nt, 256)), dim3(256), 0, w->s, src.k, src.v, n, (u32)L, nt, w->part);
+    hipLaunchKernelGGL(k_smerge, dim3(nt), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, w->part, to.k, to.v);
+    src = to;
+  }
+  return launch_ok();
+}
+
+// Resolve(i) of Algorithm 1 with the device-wide steps; the control flow is
+// the one-workgroup engine's (resolve_t), step for step.
+int wresolve(WideScratch* w, const Geom& g, HeapState* st, const u64* cur, int i) {
+  Lvl a = st->L[i];
+  const bool nx = i + 1 < g.q;
+  Lvl b = nx ? st->L[i + 1] : Lvl{0, 0, 0, 0, KINF, VINF, 0};
+  int ell = st->ell;
+  KV pi{a.pk, a.pv}, pn{b.pk, b.pv};
+  const u32 cB = (u32)nomB(g.d, i);
+  u64 touched = 0;
+  int rc = 0;
+  if (a.nS > 0 || a.nB > cB) {
+    Arr S = lbuf(g, i, 3 + a.ssel), B = lbuf(g, i, a.bsel), M = lbuf(g, i, a.bsel ^ 1);
+    if ((u64)a.nS + a.nB > capB(g.d, i)) return E_INTERNAL;
+    u32 m, num;
+    // S_0 holds the latest updates, so at level 0 its copy of an id is the live one.
+    if ((rc = wmerge(w, S, a.nS, B, a.nB, M, cur, i == 0 ? PREFER_A : PREFER_LIVE, false, pi, &m, &num))) return rc;
+    touched += 2ull * (a.nS + a.nB) + m;
+    a.bsel ^= 1;
+    a.nS = 0;
+    a.ssel = 0;
+    if (num > cB) {
+      if ((rc = wselect(w, M, m, cB, true, &pi))) return rc;
+      num = cB;
+      touched += m;
+    }
+    if (num < m) {
+      if (!nx) return E_CAPACITY;
+      Arr Lo = lbuf(g, i, a.bsel ^ 1), Hi = lbuf(g, i, 2);
+      u32 n0, n1, n2;
+      if ((rc = wpartition3(w, M, m, pi, kv_inf(), Lo, Hi, Hi, nullptr, &n0, &n1, &n2))) return rc;
+      touched += 3ull * m;
+      a.bsel ^= 1;
+      a.nB = n0;
+      if ((u64)b.nS + n1 > capS(g.d, i + 1)) return E_INTERNAL;
+      Arr Sn = lbuf(g, i + 1, 3 + b.ssel), Sn2 = lbuf(g, i + 1, 3 + (b.ssel ^ 1));
+      u32 ms, dummy;
+      if ((rc = wmerge(w, Sn, b.nS, Hi, n1, Sn2, cur, PREFER_LIVE, false, kv_inf(), &ms, &dummy))) return rc;
+      touched += 2ull * (b.nS + n1) + ms;
+      b.ssel ^= 1;
+      b.nS = ms;
+      if (ell < i + 1) ell = i + 1;
+    } else {
+      a.nB = m;
+    }
+  }
+  if (a.nB < cB && i < ell && nx) {
+    Arr Bn = lbuf(g, i + 1, b.bsel), Sn = lbuf(g, i + 1, 3 + b.ssel), M2 = lbuf(g, i + 1, b.bsel ^ 1);
+    if ((u64)b.nB + b.nS > capB(g.d, i + 1)) return E_INTERNAL;
+    u32 m2, dummy;
+    if ((rc = wmerge(w, Bn, b.nB, Sn, b.nS, M2, cur, PREFER_LIVE, false, kv_inf(), &m2, &dummy))) return rc;
+    touched += 2ull * (b.nB + b.nS) + m2;
+    b.nS = 0;
+    b.ssel = 0;
+    b.bsel ^= 1;
+    b.nB = m2;
+    if (m2 > 0) {
+      const u32 r = cB - a.nB;
+      KV pnew = kv_inf();
+      if (r < m2) {
+        if ((rc = wselect(w, M2, m2, r, true, &pnew))) return rc;
+        touched += m2;
+      }
+      if (kv_less(pn, pnew)) pnew = pn;
+      Arr Up = lbuf(g, i, 2), Bk = lbuf(g, i + 1, b.bsel ^ 1), Sk = lbuf(g, i + 1, 3);
+      u32 nu, nb1, ns1;
+      // Elements moving up into B_0 are checked for liveness here, all at once.
+      if ((rc = wpartition3(w, M2, m2, pnew, pn, Up, Bk, Sk, i == 0 ? cur : nullptr, &nu, &nb1, &ns1))) return rc;
+      touched += 3ull * m2;
+      b.bsel ^= 1;
+      b.nB = nb1;
+      b.nS = ns1;
+      b.ssel = 0;
+      Arr Bi = lbuf(g, i, a.bsel), Bi2 = lbuf(g, i, a.bsel ^ 1);
+      u32 mb;
+      if ((rc = wmerge(w, Bi, a.nB, Up, nu, Bi2, cur, i == 0 ? PREFER_B : PREFER_LIVE, false, kv_inf(), &mb,
+                       &dummy)))
+        return rc;
+      touched += 2ull * (a.nB + nu) + mb;
+      a.bsel ^= 1;
+      a.nB = mb;
+      pi = pnew;
+    }
+  }
+  a.cnt++;
+  a.pk = pi.k;
+  a.pv = pi.v;
+  st->L[i] = a;
+  if (nx) st->L[i + 1] = b;
+  st->elems += touched;
+  fix_ell(st, g.q);
+  return 0;
+}
+
+void wdrive(WideScratch* w, WideHeap* h, int what) {
+  HostTeam t{nullptr};
+  drive_with(t, h->g, h->st, h->sched, what, [&](int lvl) {
+    int rc = wresolve(w, h->g, h->st, h->cur, lvl);
+    if (rc) h->st->err = rc;
+  });
+}
+
+int grow_if_needed(WideScratch* w, WideHeap* h) {
+  while (need_grow(h->g, h->st)) {
+    if (int rc = h->grow(h->ctx, &h->g)) return rc;
+    if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int wide_reserve(WideScratch* w, u64 elems) {
+  const u64 need = (elems + TILE - 1) / TILE + 2;
+  if (need <= w->maxtiles) return 0;
+  if (w->part) (void)hipFree(w->part);
+  if (w->tc) (void)hipFree(w->tc);
+  if (w->toff) (void)hipFree(w->toff);
+  w->part = w->tc = w->toff = nullptr;
+  w->maxtiles = 0;
+  WCHK(hipMalloc(&w->part, (need + 1) * sizeof(u32)));
+  WCHK(hipMalloc(&w->tc, 3 * need * sizeof(u32)));
+  WCHK(hipMalloc(&w->toff, 3 * need * sizeof(u32)));
+  w->maxtiles = (u32)need;
+  return 0;
+}
+
+int wide_create(WideScratch** out, u32 d) {
+  WideScratch* w = new WideScratch;
+  w->d = d;
+  *out = w;
+  WCHK(hipMalloc(&w->ctl, sizeof(Ctl)));
+  WCHK(hipHostMalloc(&w->hctl, sizeof(Ctl), hipHostMallocDefault));
+  WCHK(hipMalloc(&w->cand_k, CANDMAX * sizeof(u64)));
+  WCHK(hipMalloc(&w->cand_v, CANDMAX * sizeof(u32)));
+  WCHK(hipMalloc(&w->tmp_k, 4ull * d * sizeof(u64)));
+  WCHK(hipMalloc(&w->tmp_v, 4ull * d * sizeof(u32)));
+  WCHK(hipMemset(w->ctl, 0, sizeof(Ctl)));
+  return wide_reserve(w, 4ull * d);
+}
+
+void wide_destroy(WideScratch* w) {
+  if (!w) return;
+  (void)hipDeviceSynchronize();
+  if (w->ctl) (void)hipFree(w->ctl);
+  if (w->hctl) (void)hipHostFree(w->hctl);
+  if (w->part) (void)hipFree(w->part);
+  if (w->tc) (void)hipFree(w->tc);
+  if (w->toff) (void)hipFree(w->toff);
+  if (w->cand_k) (void)hipFree(w->cand_k);
+  if (w->cand_v) (void)hipFree(w->cand_v);
+  if (w->tmp_k) (void)hipFree(w->tmp_k);
+  if (w->tmp_v) (void)hipFree(w->tmp_v);
+  delete w;
+}
+
+// BulkUpdate (Section 2.2): cur[id] = min(cur[id], key) for every pair, the
+// ids whose key dropped form U sorted by id; pieces of at most d go into S_0,
+// each followed by Resolve(0) and the schedule.
+int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* ids, u64 count) {
+  HeapState* st = h->st;
+  if (count == 0) return 0;
+  if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
+  hipLaunchKernelGGL(k_intake, dim3(grid_for(count)), dim3(NT), 0, w->s, keys, ids, count, h->cur, h->bitmap,
+                     w->ctl);
+  const u32 nt = cdiv(h->nwords, TILE);
+  if (nt > w->maxtiles) return E_INTERNAL;
+  hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, w->tc, (const u32*)nullptr,
+                     (const u64*)h->cur, h->ukeys, h->uids);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
+  hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, (u32*)nullptr, w->toff,
+                     (const u64*)h->cur, h->ukeys, h->uids);
+  if (int rc = launch_ok()) return rc;
+  if (int rc = fetch(w)) return rc;
+  const u64 nu = w->hctl->total;
+  st->live += w->hctl->newly;
+  for (u64 c0 = 0; c0 < nu;) {
+    if (int rc = grow_if_needed(w, h)) return rc;
+    const u32 len = (u32)((nu - c0) < h->g.d ? (nu - c0) : h->g.d);
+    Arr S = lbuf(h->g, 0, 3);
+    WCHK(hipMemcpyAsync(S.k, h->ukeys + c0, len * sizeof(u64), hipMemcpyDeviceToDevice, w->s));
+    WCHK(hipMemcpyAsync(S.v, h->uids + c0, len * sizeof(u32), hipMemcpyDeviceToDevice, w->s));
+    st->L[0].nS = len;
+    st->L[0].ssel = 0;
+    if (st->ell < 0) st->ell = 0;
+    st->elems += 2ull * len;
+    wdrive(w, h, DRIVE_AFTER);
+    if (st->err) return st->err;
+    c0 += len;
+  }
+  return 0;
+}
+
+// Batched ExtractMin: repeatedly the smallest min(k_left, |B_0|) elements of
+// B_0 (B_0 <= p_0 < everything else and holds only live elements) are split
+// off, sorted by (key, id), written out and marked absent; then Resolve(0)
+// and the schedule.
+int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out) {
+  HeapState* st = h->st;
+  *count_out = 0;
+  u64 out = 0;
+  bool pending = false;
+  if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
+  for (;;) {
+    if (!pending && out >= k) break;
+    if (int rc = grow_if_needed(w, h)) return rc;
+    wdrive(w, h, (pending ? DRIVE_AFTER : 0) | (out < k ? DRIVE_ENSURE : 0));
+    pending = false;
+    if (st->err) return st->err;
+    if (out >= k) break;
+    const Lvl a0 = st->L[0];
+    if (a0.nB == 0) {
+      if (st->ell >= 0) return E_INTERNAL;  // the refill leaves B_0 empty only when the heap is
+      break;
+    }
+    const u32 take = (u32)((k - out) < a0.nB ? (k - out) : a0.nB);
+    Arr B = lbuf(h->g, 0, a0.bsel), X = lbuf(h->g, 0, 2);
+    KV thr = kv_inf();
+    if (take < a0.nB)
+      if (int rc = wselect(w, B, a0.nB, take, false, &thr)) return rc;
+    u32 n0, n1, n2;
+    if (int rc = wpartition3(w, B, a0.nB, thr, kv_inf(), X, lbuf(h->g, 0, a0.bsel ^ 1), X, nullptr, &n0, &n1, &n2))
+      return rc;
+    if (n0 != take) return E_INTERNAL;
+    if (int rc = wsort(w, X, take, okeys + out, oids + out)) return rc;
+    hipLaunchKernelGGL(k_absent, dim3(grid_for(take)), dim3(NT), 0, w->s, (const u32*)(oids + out), (u64)take,
+                       h->cur);
+    if (int rc = launch_ok()) return rc;
+    st->L[0].bsel ^= 1;
+    st->L[0].nB = n1;
+    st->live -= take;
+    st->elems += 6ull * a0.nB;
+    out += take;
+    pending = true;
+  }
+  WCHK(hipStreamSynchronize(w->s));
+  *count_out = out;
+  return 0;
+}
+
+}  // namespace bkt

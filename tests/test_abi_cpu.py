@@ -41,6 +41,9 @@ def test_null_arguments_are_rejected():
     h = C.c_void_p()
     assert L.pbh_create(C.byref(h), 0, 2) == pkg.PBH_EINVAL
     assert L.pbh_create(C.byref(h), 10, 0) == pkg.PBH_EINVAL
+    for bad in (pkg.PbhOpts(3, 0), pkg.PbhOpts(0, 2), pkg.PbhOpts(0, 0, (C.c_uint32 * 6)(1, 0, 0, 0, 0, 0))):
+        assert L.pbh_create_ex(C.byref(h), 10, 2, C.byref(bad)) == pkg.PBH_EINVAL
+    assert b"pbh_create_ex" in L.pbh_last_error()
 
 
 def test_sssp_rejects_bad_sizes_before_device_work():

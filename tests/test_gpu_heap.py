@@ -13,8 +13,8 @@ pytestmark = pytest.mark.gpu
 INF = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 
-def _script(cap, d, ops):
-    h = pkg.Heap(cap, d)
+def _script(cap, d, ops, engine=pkg.ENGINE_AUTO, schedule=0):
+    h = pkg.Heap(cap, d, engine, schedule)
     o = oracle.PQ(cap)
     kmax = max([op[1] for op in ops if op[0] == "extract"] + [1])
     ko = torch.empty(kmax, dtype=torch.int64, device=DEV)
@@ -53,6 +53,38 @@ def test_worked_example():
     _script(ex["id_capacity"], 2, ops)
 
 
+@pytest.mark.parametrize("seed", range(10))
+def test_random_scripts_wide_engine(seed):
+    """The device-wide engine on the same scripts (tiny d: single-tile steps)."""
+    d = [1, 3, 8, 32, 100][seed % 5]
+    cap = [7, 100, 2000][seed % 3]
+    print(f"[heap] wide script seed={seed} d={d} cap={cap}", flush=True)
+    _script(cap, d, W.random_script(50, cap, [d, 4 * d][seed % 2], [5, 10 ** 12][seed % 2], 900 + seed),
+            engine=pkg.ENGINE_WIDE, schedule=seed % 2)
+
+
+def _check_levels(h, d):
+    L = h.debug_levels()
+    assert L["nS"][0] == 0
+    for i in range(L["q"]):
+        assert L["nB"][i] <= 4 * d * 4 ** i and L["nS"][i] <= 2 * d * 4 ** i
+    ps = [(int(L["pk"][i]), int(L["pv"][i])) for i in range(max(L["ell"], 0))]
+    assert ps == sorted(ps)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_wide_engine_multi_tile(seed):
+    """Sizes that span many 2048-element tiles: merges across tile edges,
+    radix Select passes over more than 4096 candidates, and several merge
+    passes when sorting the extracted minima."""
+    cap, d = 60000, [4096, 5000][seed % 2]
+    keymax = [1 << 40, 3000, 1 << 63][seed % 3]
+    print(f"[heap] wide multi-tile seed={seed} d={d} keymax={keymax}", flush=True)
+    h = _script(cap, d, W.random_script(24, cap, 3 * d, keymax, 40 + seed), engine=pkg.ENGINE_WIDE,
+                schedule=seed % 2)
+    _check_levels(h, d)
+
+
 def test_invariants_after_ops():
     h = _script(500, 4, W.random_script(40, 500, 30, 1000, 77))
     L = h.debug_levels()
@@ -61,13 +93,9 @@ def test_invariants_after_ops():
         assert L["nB"][i] <= 4 * 4 * 4 ** i and L["nS"][i] <= 2 * 4 * 4 ** i
 
 
-def test_decrease_key_workload_reduced():
-    """The standalone-heap workload at reduced scale: 2^18 ids loaded in pieces
-    of d = 2^14, then rounds of 2^14 decrease-keys on live ids (new = old -
-    uniform[0, old/2]) and extracts of 2^10."""
-    n_ids, d, rounds, ext = 1 << 18, 1 << 14, 16, 1 << 10
-    keys, ids = W.heap_init_pairs(n_ids, seed=3)
-    h = pkg.Heap(n_ids, d)
+def _decrease_key_workload(n_ids, d, rounds, ext, engine, seed=3):
+    keys, ids = W.heap_init_pairs(n_ids, seed=seed)
+    h = pkg.Heap(n_ids, d, engine)
     o = oracle.PQArrays(n_ids)
     for c in range(0, n_ids, d):
         h.bulk_update(dev64(keys[c:c + d]), dev32(ids[c:c + d]))
@@ -76,7 +104,7 @@ def test_decrease_key_workload_reduced():
     io = torch.empty(ext, dtype=torch.int32, device=DEV)
     for r in range(rounds):
         live = np.nonzero(o.cur != INF)[0].astype(np.uint32)
-        bk, bi = W.decrease_batch(live, lambda x: o.cur[x], d, 3, r)
+        bk, bi = W.decrease_batch(live, lambda x: o.cur[x], d, seed, r)
         h.bulk_update(dev64(bk), dev32(bi))
         o.bulk_update(bk, bi)
         n = h.extract_min(ext, ko, io)
@@ -84,6 +112,25 @@ def test_decrease_key_workload_reduced():
         assert n == ext
         assert np.array_equal(host64(ko[:n]), ek) and np.array_equal(host32(io[:n]), ei)
     assert h.size() == o.size()
+    _check_levels(h, d)
+    return h
+
+
+@pytest.mark.parametrize("engine", [pkg.ENGINE_TEAM, pkg.ENGINE_WIDE])
+def test_decrease_key_workload_reduced(engine):
+    """The standalone-heap workload at reduced scale: 2^18 ids loaded in pieces
+    of d = 2^14, then rounds of 2^14 decrease-keys on live ids (new = old -
+    uniform[0, old/2]) and extracts of 2^10."""
+    print(f"[heap] reduced workload engine={engine}", flush=True)
+    _decrease_key_workload(1 << 18, 1 << 14, 16, 1 << 10, engine)
+
+
+def test_decrease_key_workload_full_size():
+    """The standalone-heap workload at its full sizes (2^24 ids with keys in
+    [0, 2^40), d = 2^20, rounds of 2^20 decrease-keys and extracts of 2^16),
+    8 rounds, every extracted pair checked against the oracle."""
+    print("[heap] full-size workload, 8 rounds", flush=True)
+    _decrease_key_workload(1 << 24, 1 << 20, 8, 1 << 16, pkg.ENGINE_AUTO, seed=5)
 
 
 def test_invalid_updates_change_nothing():

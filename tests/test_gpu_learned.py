@@ -126,7 +126,7 @@ def test_trained_model_beats_plain():
     blob = torch.from_numpy(learn.load_model(MODEL)).to(DEV)
     g = W.grid8(384, 384, wmax=10000, seed=123)
     ref = oracle.dijkstra(g, 0)
-    got0, st0 = run_sssp(pkg, g, 0)
+    got0, st0 = run_sssp(pkg, g, 0, k_rule=0)
     got1, st1 = run_sssp(pkg, g, 0, k_rule=2, k_model=blob)
     assert np.array_equal(got0, ref) and np.array_equal(got1, ref)
     print(f"[learned] plain {st0['rounds']} rounds {st0['kernel_ms']:.1f} ms; learned {st1['rounds']} rounds "
