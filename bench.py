@@ -1,10 +1,11 @@
-"""Benchmark: parDijkstra (plain rule) on the parallel bucket heap, 1 MI355X.
+"""Benchmark: parDijkstra on the parallel bucket heap, 1 MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ring|grid64|grid8|dag|multi|heap]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ring|grid64|grid8|dag|multi|heap|copy]
                     [--method plain|learned|both]
 
 One step = one complete sssp() over the resident graph (every round of the
-hot path: extract-min, relaxation, bulk update, Resolve schedule).  The
+hot path: the extraction threshold, extract-min, relaxation, bulk update,
+Resolve schedule).  The
 default workload is the large high-diameter ring lattice: n = 2^20 vertices,
 each linked to its 16 nearest neighbours on each side (m = 33,554,432 directed
 edges), integer weights uniform in [1, 1000], source 0.
@@ -13,8 +14,9 @@ Prints one JSON line: GTEPS = m / seconds per step, the roofline of the
 round-loop kernel (algorithmic bytes per launch / its HIP-event duration vs
 8 TB/s) and the CPU oracle (single-thread binary-heap Dijkstra) timed on a
 bounded sample of the same workload.  With --method both (the default) the
-line also carries the learned-threshold rule on the same graph ("learned"),
-whose distances are checked against the oracle like the plain run's.
+value is the learned-threshold rule's and the line also carries plain
+parDijkstra on the same graph ("plain") and the speedup; both runs' distances
+are checked against the oracle.
 """
 import argparse
 import json
@@ -63,38 +65,50 @@ def run_multi(args):
         for s in srcs:
             qs.append((off, tg, wt, g.n, g.m, s, torch.empty(g.n, dtype=torch.int64, device=dev)))
     sum_m = sum(q[4] for q in qs)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        pkg.sssp_batch(qs)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(pkg.sssp_batch(qs))
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
-    st = stats[-1]
-    kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
-    abytes = algorithmic_bytes(st)
-    achieved = abytes / (kern_ms * 1e-3) / 1e9
+    refs = [oracle.dijkstra(g, s) for g, srcs in batch for s in srcs]
+
+    def timed(**kw):
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            pkg.sssp_batch(qs, **kw)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            stats.append(pkg.sssp_batch(qs, **kw))
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        exact = all(np.array_equal(q[6].cpu().numpy().view(np.uint64), r) for q, r in zip(qs, refs))
+        st = stats[-1]
+        kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
+        abytes = algorithmic_bytes(st)
+        achieved = abytes / (kern_ms * 1e-3) / 1e9
+        print(f"[bench] batch {kw.get('k_rule', 0)}: {sec * 1e3:.1f} ms/step exact={exact}", file=sys.stderr,
+              flush=True)
+        return {"value": sum_m / sec / 1e9, "ms_per_step": sec * 1e3, "rounds": st["rounds"],
+                "relaxations": st["relaxations"], "extracted": st["extracted"], "team": st["team"],
+                "exact": exact,
+                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp_multi",
+                             "kernel_ms": kern_ms, "algorithmic_bytes": abytes}}
+
+    from paper_1908_09378_amd import learn
+    blob = torch.from_numpy(learn.load_model()).to(dev)
+    lr = timed(k_rule=2, k_model=blob)
+    pr = timed()
     line = {
-        "metric": METRIC, "value": sum_m / sec / 1e9, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": lr["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": lr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "256 queries: 64 random geometric graphs (n = floor(2^(12+6u)), mean degree 24, "
                                "w = round(1000 len)+1), 4 sources each, one launch",
-                   "method": "batched plain parDijkstra, one parBucketHeap per query", "queries": len(qs),
-                   "sum_n": sum(g.n for g, _ in batch), "sum_m_over_queries": sum_m, "team": st["team"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp_multi",
-                     "kernel_ms": kern_ms, "algorithmic_bytes": abytes},
-        "rounds": st["rounds"], "relaxations": st["relaxations"],
+                   "method": "batched parDijkstra with the learned threshold, one parBucketHeap per query",
+                   "queries": len(qs), "sum_n": sum(g.n for g, _ in batch), "sum_m_over_queries": sum_m,
+                   "team": lr["team"]},
+        "roofline": lr["roofline"], "rounds": lr["rounds"], "relaxations": lr["relaxations"],
+        "extracted": lr["extracted"], "exact": lr["exact"] and pr["exact"],
+        "plain": pr, "speedup_vs_plain": lr["value"] / pr["value"],
     }
-    ok = True
-    for (g, srcs), j in zip(batch, range(0, len(qs), 4)):
-        for k, s in enumerate(srcs):
-            ok &= bool(np.array_equal(qs[j + k][6].cpu().numpy().view(np.uint64), oracle.dijkstra(g, s)))
-    line["exact"] = ok
     if not args.no_cpu:
         t0 = time.perf_counter()
         runs = 0
@@ -211,12 +225,32 @@ def run_heap(args):
     print(json.dumps(line), flush=True)
 
 
+def run_copy(args):
+    """Calibration for the HBM counters: a plain device-to-device copy of
+    2 GiB (torch's copy kernel), repeated `steps` times.  FETCH_SIZE and
+    WRITE_SIZE of this kernel, divided by 2 GiB, give the factor by which the
+    counters over- or under-count HBM bytes."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.int64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "device copy GB/s", "value": 2 * 8 * n / sec / 1e9, "unit": "GB/s",
+                      "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n, "steps": args.steps}),
+          flush=True)
+
+
 def algorithmic_bytes(st):
-    """Bytes the method must move per launch: per settled vertex its two CSR
+    """Bytes the method must move per launch: per extracted vertex its two CSR
     offsets (16 B); per scanned edge its target and weight (8 B) and the 8-byte
     atomicMin on dist; per heap element read or written by the level operations
     (Merge, DeleteDuplicates, Select, splits) 12 B (u64 key + u32 id)."""
-    return 16 * st["rounds"] + 16 * st["relaxations"] + 12 * st["heap_elems"]
+    return 16 * st["extracted"] + 16 * st["relaxations"] + 12 * st["heap_elems"]
 
 
 def main():
@@ -240,6 +274,8 @@ def main():
         return run_multi(args)
     if args.workload == "heap":
         return run_heap(args)
+    if args.workload == "copy":
+        return run_copy(args)
 
     import numpy as np
     import torch
@@ -272,57 +308,55 @@ def main():
               f"{stats[-1]['rounds']} rounds, exact={exact}", file=sys.stderr, flush=True)
         return sec, stats, exact
 
-    learned = None
+    def record(sec, stats, exact, method):
+        st = stats[-1]
+        kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
+        abytes = algorithmic_bytes(st)
+        achieved = abytes / (kern_ms * 1e-3) / 1e9
+        return {"value": g.m / sec / 1e9, "ms_per_step": sec * 1e3, "method": method, "rounds": st["rounds"],
+                "relaxations": st["relaxations"], "extracted": st["extracted"], "updates": st["updates"],
+                "d": st["d"], "team": st["team"], "levels": st["levels"], "lds_levels": st["lds_levels"],
+                "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
+                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp",
+                             "kernel_ms": kern_ms, "algorithmic_bytes": abytes}}
+
+    runs = {}
     if args.method in ("both", "learned"):
         from paper_1908_09378_amd import learn
         blob = torch.from_numpy(learn.load_model()).to(dev)
-        lsec, lstats, lexact = timed(args.steps, args.warmup, k_rule=2, k_model=blob)
-        ls = lstats[-1]
-        learned = {"value": g.m / lsec / 1e9, "ms_per_step": lsec * 1e3, "rounds": ls["rounds"],
-                   "relaxations": ls["relaxations"], "extracted": ls["extracted"],
-                   "kernel_ms": sum(x["kernel_ms"] for x in lstats) / len(lstats), "exact": lexact,
-                   "model": "8-64-64-1 GELU MLP, bf16 weights (models/k_mlp.bin)"}
-    if args.method == "learned":
-        print(json.dumps({"metric": METRIC, "value": learned["value"], "unit": "GTEPS", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": learned["ms_per_step"],
-                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
-                          "data": "synthetic", "config": {"workload": desc, "method": "learned threshold",
-                                                          "n": g.n, "m": g.m}, "learned": learned}), flush=True)
-        return
-    sec, stats, exact = timed(args.steps, args.warmup)
-    gteps = g.m / sec / 1e9
-
-    st = stats[-1]
-    kern_ms = sum(s["kernel_ms"] for s in stats) / len(stats)
-    abytes = algorithmic_bytes(st)
-    achieved = abytes / (kern_ms * 1e-3) / 1e9
+        runs["learned"] = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob),
+                                 "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) "
+                                 "picks how many minima each round extracts; improved vertices are re-inserted")
+    if args.method in ("both", "plain"):
+        runs["plain"] = record(*timed(args.steps, args.warmup), "plain parDijkstra (k = 1)")
+    main_run = runs["learned" if "learned" in runs else "plain"]
     line = {
         "metric": METRIC,
-        "value": gteps,
+        "value": main_run["value"],
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": desc, "method": "plain parDijkstra (k=1) on parBucketHeap",
-                   "n": g.n, "m": g.m, "d": st["d"], "team": st["team"], "levels": st["levels"],
-                   "lds_levels": st["lds_levels"], "parallelism": "1 workgroup per query"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sssp", "kernel_ms": kern_ms, "algorithmic_bytes": abytes},
-        "rounds": st["rounds"],
-        "relaxations": st["relaxations"],
-        "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]),
-        "exact": exact,
+        "config": {"workload": desc, "method": main_run["method"], "n": g.n, "m": g.m, "d": main_run["d"],
+                   "team": main_run["team"], "levels": main_run["levels"], "lds_levels": main_run["lds_levels"],
+                   "parallelism": "1 workgroup per query"},
+        "roofline": main_run["roofline"],
+        "rounds": main_run["rounds"],
+        "relaxations": main_run["relaxations"],
+        "extracted": main_run["extracted"],
+        "us_per_round": main_run["us_per_round"],
+        "exact": all(r["exact"] for r in runs.values()),
     }
-    if learned is not None:
-        learned["speedup_vs_plain"] = learned["value"] / gteps
-        line["learned"] = learned
+    if "learned" in runs and "plain" in runs:
+        line["plain"] = {k: v for k, v in runs["plain"].items() if k != "method"}
+        line["speedup_vs_plain"] = runs["learned"]["value"] / runs["plain"]["value"]
     if not args.no_cpu:
         per_run, runs = oracle.time_dijkstra(g, 0, args.cpu_budget)
         line["cpu_baseline"] = {"value": g.m / per_run / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
