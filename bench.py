@@ -94,7 +94,11 @@ def run_multi(args):
 
     from paper_1908_09378_amd import learn
     blob = torch.from_numpy(learn.load_model()).to(dev)
-    lr = timed(k_rule=2, k_model=blob)
+    t0 = time.perf_counter()
+    tuned = pkg.sssp_batch_autotune(qs, k_rule=2, k_model=blob)
+    tuned["tune_s"] = time.perf_counter() - t0
+    print(f"[bench] batch autotune: {tuned}", file=sys.stderr, flush=True)
+    lr = timed(k_rule=2, k_model=blob, d_scale=tuned["d_scale"], k_max=tuned["k_max"])
     pr = timed()
     line = {
         "metric": METRIC, "value": lr["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -102,7 +106,9 @@ def run_multi(args):
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "256 queries: 64 random geometric graphs (n = floor(2^(12+6u)), mean degree 24, "
                                "w = round(1000 len)+1), 4 sources each, one launch",
-                   "method": "batched parDijkstra with the learned threshold, one parBucketHeap per query",
+                   "method": "batched parDijkstra with the learned threshold, one parBucketHeap per query; "
+                             "d (as a multiple of each query's max out-degree) and k_max autotuned",
+                   "autotune": tuned,
                    "queries": len(qs), "sum_n": sum(g.n for g, _ in batch), "sum_m_over_queries": sum_m,
                    "team": lr["team"]},
         "roofline": lr["roofline"], "rounds": lr["rounds"], "relaxations": lr["relaxations"],
@@ -321,15 +327,32 @@ def main():
                              "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp",
                              "kernel_ms": kern_ms, "algorithmic_bytes": abytes}}
 
+    def tune(**kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = pkg.sssp_autotune(off, tg, wt, g.n, g.m, 0, dist, **kw)
+        torch.cuda.synchronize()
+        t["tune_s"] = time.perf_counter() - t0
+        print(f"[bench] autotune {kw.get('k_rule', 0)}: {t}", file=sys.stderr, flush=True)
+        return t
+
     runs = {}
     if args.method in ("both", "learned"):
         from paper_1908_09378_amd import learn
         blob = torch.from_numpy(learn.load_model()).to(dev)
-        runs["learned"] = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob),
-                                 "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) "
-                                 "picks how many minima each round extracts; improved vertices are re-inserted")
+        t = tune(k_rule=2, k_model=blob)
+        r = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"]),
+                   "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) picks how many "
+                   "minima each round extracts, improved vertices are re-inserted; d and k_max autotuned")
+        r["autotune"] = t
+        runs["learned"] = r
     if args.method in ("both", "plain"):
-        runs["plain"] = record(*timed(args.steps, args.warmup), "plain parDijkstra (k = 1)")
+        runs["plain"] = record(*timed(args.steps, args.warmup), "plain parDijkstra (k = 1, d = max out-degree)")
+    if args.method == "both":
+        t = tune()
+        r = record(*timed(args.steps, args.warmup, d=t["d"]), "plain parDijkstra (k = 1), d autotuned")
+        r["autotune"] = t
+        runs["plain_tuned"] = r
     main_run = runs["learned" if "learned" in runs else "plain"]
     line = {
         "metric": METRIC,
@@ -354,9 +377,14 @@ def main():
         "us_per_round": main_run["us_per_round"],
         "exact": all(r["exact"] for r in runs.values()),
     }
+    if "autotune" in main_run:
+        line["config"]["autotune"] = main_run["autotune"]
     if "learned" in runs and "plain" in runs:
         line["plain"] = {k: v for k, v in runs["plain"].items() if k != "method"}
         line["speedup_vs_plain"] = runs["learned"]["value"] / runs["plain"]["value"]
+    if "plain_tuned" in runs:
+        line["plain_tuned"] = runs["plain_tuned"]
+        line["speedup_vs_plain_tuned"] = runs["learned"]["value"] / runs["plain_tuned"]["value"]
     if not args.no_cpu:
         per_run, runs = oracle.time_dijkstra(g, 0, args.cpu_budget)
         line["cpu_baseline"] = {"value": g.m / per_run / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",

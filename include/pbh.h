@@ -179,7 +179,12 @@ typedef struct {
   uint32_t *trace_query;
   uint32_t trace_every;
   uint32_t trace_cap;
-  uint32_t reserved[4];
+  /* Trial limits (the autotuner's; distances are then incomplete): a round
+   * does not start once the smallest key in the heap exceeds stop_key
+   * (0 = no limit), nor after max_rounds rounds (0 = no limit). */
+  uint64_t stop_key;
+  uint32_t max_rounds;
+  uint32_t d_scale;       /* with d == 0: d = maximum out-degree * max(1, d_scale) */
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
@@ -198,6 +203,8 @@ typedef struct {
   uint32_t team;          /* workgroup size used */
   uint32_t lds_levels;    /* levels resident in LDS */
   double kernel_ms;       /* device time of the round-loop kernel (HIP events) */
+  uint64_t last_key;      /* smallest key left in the heap when the rounds stopped
+                             (UINT64_MAX if the heap ran empty; largest over a batch) */
 } sssp_stats;
 
 /*
@@ -235,6 +242,28 @@ typedef struct {
  */
 int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, sssp_stats *stats,
                void *stream);
+
+/*
+ * sssp_autotune: picks opts->d and opts->k_max for this query by timing trial
+ * runs on the query itself.  A plain trial of a few rounds finds a distance
+ * frontier D (the smallest key left after them); then each candidate
+ * (d = max out-degree * 1, 2, 4, ... up to 2048, and k_max 64 or 256 when
+ * k_rule != 0) runs until every vertex closer than D is settled, which is the
+ * same work for every candidate, and the fastest is written back into *opts
+ * (the other fields are kept and used for the trials).  dist_out is used as
+ * scratch.  Errors: those of sssp_ex.
+ */
+int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
+                  uint64_t m, uint32_t source, uint64_t *dist_out, sssp_opts *opts, void *stream);
+
+/*
+ * sssp_batch_autotune: picks opts->d_scale (with opts->d = 0) and opts->k_max
+ * for a batch by timing each candidate as one sssp_batch launch over a sample
+ * of the queries (up to 16 around the median size, run to completion); the
+ * fastest is written back into *opts.  Those queries' dist_out arrays are
+ * used as scratch.  Errors: those of sssp_batch.
+ */
+int sssp_batch_autotune(const sssp_query *queries, uint32_t nq, sssp_opts *opts, void *stream);
 
 /*
  * Training of the extraction-threshold model (not in the paper: an addition

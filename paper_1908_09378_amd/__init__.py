@@ -43,14 +43,15 @@ class SsspOpts(C.Structure):
                 ("k_seq", C.c_void_p), ("k_model", C.c_void_p),
                 ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
-                ("trace_cap", C.c_uint32), ("reserved", C.c_uint32 * 4)]
+                ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
+                ("d_scale", C.c_uint32)]
 
 
 class SsspStats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("relaxations", C.c_uint64), ("updates", C.c_uint64),
                 ("heap_elems", C.c_uint64), ("extracted", C.c_uint64), ("resolves", C.c_uint64 * 16),
                 ("levels", C.c_uint32), ("d", C.c_uint32), ("team", C.c_uint32), ("lds_levels", C.c_uint32),
-                ("kernel_ms", C.c_double)]
+                ("kernel_ms", C.c_double), ("last_key", C.c_uint64)]
 
 
 class SsspQuery(C.Structure):
@@ -60,7 +61,7 @@ class SsspQuery(C.Structure):
 
 _lib = None
 EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_destroy",
-           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "mlp_trace_labels", "mlp_feature_stats",
+           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "pbh_last_error"]
 
 
@@ -83,6 +84,8 @@ def lib():
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
         L.sssp_ex.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.sssp_batch.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
+        L.sssp_autotune.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), vp]
+        L.sssp_batch_autotune.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), vp]
         L.mlp_trace_labels.argtypes = [vp, vp, vp, u32, vp, vp]
         L.mlp_feature_stats.argtypes = [vp, u32, vp]
         L.mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
@@ -114,7 +117,7 @@ def _ptr(t, elem_bytes):
 def _stats_dict(s):
     return dict(rounds=s.rounds, relaxations=s.relaxations, updates=s.updates, heap_elems=s.heap_elems,
                 extracted=s.extracted, resolves=list(s.resolves), levels=s.levels, d=s.d, team=s.team,
-                lds_levels=s.lds_levels, kernel_ms=s.kernel_ms)
+                lds_levels=s.lds_levels, kernel_ms=s.kernel_ms, last_key=s.last_key)
 
 
 def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> None:
@@ -124,10 +127,11 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
-          k_model=None, trace=None):
+          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0):
     o = SsspOpts()
     o.d, o.team, o.schedule, o.lds_levels, o.heap_capacity = d, team, schedule, lds_levels, heap_capacity
     o.k_rule, o.k_fixed, o.k_max = k_rule, k_fixed, k_max
+    o.stop_key, o.max_rounds, o.d_scale = stop_key, max_rounds, d_scale
     if k_seq is not None:
         o.k_seq, o.k_seq_len = _ptr(k_seq, 4), k_seq.numel()
     if k_model is not None:
@@ -155,13 +159,43 @@ def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *,
     return _stats_dict(s)
 
 
-def sssp_batch(queries, *, stream=None, **kw) -> dict:
-    """Many independent parDijkstra queries in one launch.  queries: sequence
-    of (offsets, targets, weights, n, m, source, dist_out)."""
+def _tuned(o) -> dict:
+    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max)
+
+
+def sssp_autotune(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:
+    """Picks d and k_max for this query by timed trials on it (sssp_autotune
+    in include/pbh.h); returns {d, d_scale, k_max} to pass to sssp_ex along
+    with the other options.  dist_out is scratch."""
+    o = _opts(**kw)
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sssp_autotune(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source,
+                               _ptr(dist_out, 8), C.byref(o), sp))
+    return _tuned(o)
+
+
+def _queries(queries):
     arr = (SsspQuery * max(1, len(queries)))()
     for i, (off, tg, wt, n, m, src, dist) in enumerate(queries):
         arr[i] = SsspQuery(_ptr(off, 8), _ptr(tg, 4) if m else None, _ptr(wt, 4) if m else None, m, n, src,
                            _ptr(dist, 8))
+    return arr
+
+
+def sssp_batch_autotune(queries, *, stream=None, **kw) -> dict:
+    """Picks d_scale and k_max for a batch (sssp_batch_autotune in
+    include/pbh.h); returns {d, d_scale, k_max} for sssp_batch."""
+    arr = _queries(queries)
+    o = _opts(**kw)
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sssp_batch_autotune(arr, len(queries), C.byref(o), sp))
+    return _tuned(o)
+
+
+def sssp_batch(queries, *, stream=None, **kw) -> dict:
+    """Many independent parDijkstra queries in one launch.  queries: sequence
+    of (offsets, targets, weights, n, m, source, dist_out)."""
+    arr = _queries(queries)
     o = _opts(**kw)
     s = SsspStats()
     sp = None if stream is None else C.c_void_p(stream.cuda_stream)

@@ -198,6 +198,8 @@ int spec_from_opts(const sssp_opts& o, u32 d, SpecCfg* sc, u32* kmax_out) {
   sc->kseq = o.k_seq;
   sc->kseq_len = o.k_seq_len;
   sc->model = o.k_model;
+  sc->stop_key = o.stop_key;
+  sc->max_rounds = o.max_rounds;
   *kmax_out = kmax;
   return PBH_OK;
 }
@@ -418,7 +420,7 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
   HIPCHK(hipMemcpyAsync(&cc, g_csr, sizeof cc, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (cc.bad) return fail(PBH_EINVAL, "sssp: malformed CSR (offsets or targets)");
-  u32 d = o.d ? o.d : (u32)(cc.maxdeg ? cc.maxdeg : 1);
+  u32 d = o.d ? o.d : (u32)(cc.maxdeg ? cc.maxdeg : 1) * (o.d_scale > 1 ? o.d_scale : 1u);
   if (cc.maxdeg > d) return fail(PBH_EINVAL, "sssp: opts.d %u below the maximum out-degree %llu", d,
                                  (unsigned long long)cc.maxdeg);
   int team = (int)o.team;
@@ -521,6 +523,7 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       stats->updates = ds.updates;
       stats->heap_elems = ds.elems;
       stats->extracted = ds.extracted;
+      stats->last_key = ds.last_key;
       for (int i = 0; i < 16 && i < MAXL; ++i) stats->resolves[i] = ds.resolves[i];
       stats->levels = (u32)q;
       stats->d = d;
@@ -598,7 +601,7 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
   std::vector<u32> qd(nq);
   for (u32 i = 0; i < nq; ++i) {
     u64 md = cc[qg[i]].maxdeg;
-    qd[i] = o.d ? o.d : (u32)(md ? md : 1);
+    qd[i] = o.d ? o.d : (u32)(md ? md : 1) * (o.d_scale > 1 ? o.d_scale : 1u);
     dmax = std::max(dmax, qd[i]);
   }
   int team = (int)o.team;
@@ -746,6 +749,7 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
       stats->updates += ds[j].updates;
       stats->heap_elems += ds[j].elems;
       stats->extracted += ds[j].extracted;
+      stats->last_key = j == 0 ? ds[j].last_key : std::max(stats->last_key, (uint64_t)ds[j].last_key);
       for (int i = 0; i < 16 && i < MAXL; ++i) stats->resolves[i] += ds[j].resolves[i];
     }
     stats->levels = 0;
@@ -781,6 +785,97 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
 int sssp(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
          uint32_t source, uint64_t* dist_out) {
   return sssp_ex(offsets, targets, weights, n, m, source, dist_out, nullptr, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Frontier trials on one query: a plain run of a few rounds gives the
+// distance frontier D; every candidate (d = maxdeg * mult, k_max) then runs
+// until all vertices closer than D are settled -- the same work for each --
+// and the fastest wins.  Returns the winning multiple and k_max.
+int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
+               uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream, u32* mult_out,
+               u32* kmax_out, u32* maxdeg_out) {
+  sssp_opts base = user;
+  base.stop_key = 0;
+  base.max_rounds = 0;
+  base.trace_features = nullptr;
+  base.d = 0;
+  base.d_scale = 0;
+  sssp_opts t0 = base;
+  t0.k_rule = 0;
+  t0.max_rounds = std::min<u32>(65536u, std::max<u32>(256u, n / 32));
+  sssp_stats s0;
+  int rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t0, &s0, stream);
+  if (rc) return rc;
+  const u32 maxdeg = s0.d;
+  const u64 D = s0.last_key;  // UINT64_MAX: the whole run fits in the trial; candidates run to the end
+  const bool spec = user.k_rule != 0;
+  const u32 kms[2] = {64, 256};
+  double best = 1e300;
+  u32 bm = 1, bk = user.k_max;
+  for (u32 mult = 1; (u64)maxdeg * mult <= 2048 || mult == 1; mult *= 2) {
+    for (int ki = 0; ki < (spec ? 2 : 1); ++ki) {
+      sssp_opts t = base;
+      t.d = maxdeg * mult;
+      if (spec) t.k_max = kms[ki];
+      t.stop_key = D == KINF ? 0 : D;
+      sssp_stats st;
+      rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
+      if (rc == PBH_EINVAL) return rc;  // e.g. the LDS does not fit: a caller error, not a candidate's
+      if (rc) continue;
+      if (st.kernel_ms < best) {
+        best = st.kernel_ms;
+        bm = mult;
+        bk = spec ? kms[ki] : user.k_max;
+      }
+    }
+  }
+  if (best == 1e300) return fail(PBH_EINTERNAL, "sssp_autotune: every candidate failed");
+  *mult_out = bm;
+  *kmax_out = bk;
+  *maxdeg_out = maxdeg;
+  return PBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n,
+                  uint64_t m, uint32_t source, uint64_t* dist_out, sssp_opts* opts, void* stream) {
+  if (!opts) return fail(PBH_EINVAL, "sssp_autotune: opts is NULL");
+  u32 mult = 1, kmax = 0, maxdeg = 1;
+  int rc = tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg);
+  if (rc) return rc;
+  opts->d = maxdeg * mult;
+  opts->d_scale = 0;
+  opts->k_max = kmax;
+  return PBH_OK;
+}
+
+int sssp_batch_autotune(const sssp_query* queries, uint32_t nq, sssp_opts* opts, void* stream) {
+  if (!opts) return fail(PBH_EINVAL, "sssp_batch_autotune: opts is NULL");
+  if (nq == 0) return PBH_OK;
+  if (!queries) return fail(PBH_EINVAL, "sssp_batch_autotune: queries is NULL");
+  // The largest query is the batch's critical path: tune on it and apply
+  // the same multiple of each query's maximum out-degree to all.
+  u32 big = 0;
+  for (u32 i = 1; i < nq; ++i)
+    if (queries[i].m > queries[big].m) big = i;
+  const sssp_query& q = queries[big];
+  if (!q.offsets || !q.dist_out || (q.m > 0 && (!q.targets || !q.weights)) || q.n == 0 || q.source >= q.n)
+    return fail(PBH_EINVAL, "sssp_batch_autotune: query %u is malformed", big);
+  u32 mult = 1, kmax = 0, maxdeg = 1;
+  int rc = tune_query(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, *opts, stream, &mult, &kmax,
+                      &maxdeg);
+  if (rc) return rc;
+  opts->d = 0;
+  opts->d_scale = mult;
+  opts->k_max = kmax;
+  return PBH_OK;
 }
 
 }  // extern "C"

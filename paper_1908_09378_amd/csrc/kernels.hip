@@ -68,6 +68,7 @@ __device__ void sssp_query(DevTeam<NT>& t, HeapState PBH_LDS* st, unsigned char*
     o->relax = c.relax;
     o->updates = c.updates;
     o->extracted = c.extracted;
+    o->last_key = c.last_key;
     o->elems = st->elems;
     o->err = st->err;
     o->ell = st->ell;

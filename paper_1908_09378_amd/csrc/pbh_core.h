@@ -996,11 +996,34 @@ struct SpecCfg {
   u32* trace_count;
   u32* trace_q;  // query index of each record
   u32 qid;
+  // trial limits: no round starts once the heap's smallest key exceeds
+  // stop_key (0 = none) or after max_rounds rounds (0 = none)
+  u64 stop_key;
+  u32 max_rounds;
 };
 
 struct SsspCounters {
   u64 rounds, relax, updates, extracted;
+  u64 last_key;  // smallest key left in the heap when the rounds stopped (KINF: ran empty)
+  u32 stopped;   // a trial limit ended the rounds
 };
+
+// Smallest key of B_0 (the heap's minimum once B_0 has been refilled).
+template <class T, class P>
+PBH_INL u64 b0_min_key(const T& t, const Geom& g, typename P::SP st) {
+  const Lvl a0 = lvl_load(st, 0);
+  Arr Bg = lbuf(g, 0, a0.bsel);
+  u64 lo = KINF, hi = 0;
+  if (g.qlds > 0) {
+    typename P::L B = as_arr<typename P::L>(Bg);
+    for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) lo = B.k[x] < lo ? B.k[x] : lo;
+  } else {
+    typename P::G B = as_arr<typename P::G>(Bg);
+    for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) lo = B.k[x] < lo ? B.k[x] : lo;
+  }
+  t.minmax64(lo, hi);
+  return lo;
+}
 
 struct RoundMemo {  // team-uniform facts about the previous round
   float avgdeg;
@@ -1301,7 +1324,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     st->ell = 0;
   }
   t.sync();
-  SsspCounters c{0, 0, 1, 0};
+  SsspCounters c{0, 0, 1, 0, KINF, 0};
   RoundMemo memo{0.0f};
   u32 upos = 0, ulen = 0;
   for (;;) {
@@ -1336,6 +1359,14 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
       t.sync();
       upos += len;
       continue;
+    }
+    if (sc.max_rounds || sc.stop_key) {
+      const u64 mn = b0_min_key<T, P>(t, g, st);
+      if ((sc.max_rounds && c.rounds >= sc.max_rounds) || (sc.stop_key && mn != KINF && mn > sc.stop_key)) {
+        c.last_key = mn;
+        c.stopped = 1;
+        break;
+      }
     }
     // Every extraction consumes one insertion and every insertion comes from
     // one scanned edge (or the source), so rounds <= 1 + relax always holds.

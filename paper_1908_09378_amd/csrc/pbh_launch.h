@@ -8,7 +8,7 @@ namespace bkt {
 
 // Device statistics block written by the SSSP kernel.
 struct SsspDevStats {
-  u64 rounds, relax, updates, elems, extracted;
+  u64 rounds, relax, updates, elems, extracted, last_key;
   long long err;
   long long ell;
   u64 resolves[MAXL];

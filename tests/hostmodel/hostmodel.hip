@@ -212,7 +212,7 @@ struct LiveCheck {
 // heap element touches, levels, resolves[0..15].
 int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src, u64* dist, u32 d_opt,
             int sched, u64 hcap, int qlds, u64* stats, int rule, u32 kfix, u32 kmax, const u32* kseq, u32 kseq_len,
-            const float* model, int check_live) {
+            const float* model, int check_live, u64 stop_key, u32 max_rounds) {
   u64 md = 0;
   for (u32 u = 0; u < n; ++u) md = off[u + 1] - off[u] > md ? off[u + 1] - off[u] : md;
   u32 d = d_opt ? d_opt : (u32)(md ? md : 1);
@@ -244,6 +244,8 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   sc.kseq = kseq;
   sc.kseq_len = kseq_len;
   sc.model = model;
+  sc.stop_key = stop_key;
+  sc.max_rounds = max_rounds;
   std::vector<u64> uk(2ull * sc.kmax * d);
   std::vector<u32> uv(2ull * sc.kmax * d);
   sc.uk = uk.data();
@@ -259,6 +261,8 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   } else {
     sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
   }
+  stats[26] = c.last_key;
+  stats[27] = c.stopped;
   stats[22] = (u64)(i64)first_bad;
   stats[23] = info[0];
   stats[24] = info[1];

@@ -190,3 +190,54 @@ def test_batch_speculative_exact():
     pkg.sssp_batch(qs, k_rule=1, k_fixed=8)
     for q, ref in zip(qs, refs):
         assert np.array_equal(host64(q[6]), ref)
+
+
+def test_trial_limits_on_gpu():
+    """max_rounds / stop_key: the autotuner's equal-work trials."""
+    g = W.grid8(80, 80, wmax=10000, seed=12)
+    ref = oracle.dijkstra(g, 0)
+    print("[sssp] trial limits", flush=True)
+    got, st = run_sssp(pkg, g, 0, max_rounds=700)
+    assert st["rounds"] == 700 and st["last_key"] == int(np.sort(ref)[700])
+    D = st["last_key"]
+    for kw in (dict(), dict(k_rule=1, k_fixed=9), dict(k_rule=1, k_fixed=40, d=64)):
+        got, st = run_sssp(pkg, g, 0, stop_key=D, **kw)
+        settled = ref <= D
+        assert np.array_equal(got[settled], ref[settled]) and st["last_key"] > D
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_autotune_then_exact(rule):
+    from gpu_util import graph_to_dev, DEV, host64
+    import torch
+    g = W.ring_lattice(1 << 14, 16, 1, 1000, seed=5)
+    off, tg, wt = graph_to_dev(g)
+    dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+    kw = dict(k_rule=1, k_fixed=8) if rule else {}
+    print(f"[sssp] autotune rule={rule}", flush=True)
+    t = pkg.sssp_autotune(off, tg, wt, g.n, g.m, 0, dist, **kw)
+    assert t["d"] % g.max_degree() == 0 and t["d"] >= g.max_degree()
+    if rule:
+        assert t["k_max"] in (64, 256)
+    kw.update(t)
+    pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist, **kw)
+    assert np.array_equal(host64(dist), oracle.dijkstra(g, 0))
+
+
+def test_batch_autotune_then_exact():
+    import torch
+    from gpu_util import DEV, graph_to_dev, host64
+    gs = [(W.rgg(1500 + 900 * i, seed=80 + i), [0, 3]) for i in range(4)]
+    qs, refs, keep = [], [], []
+    for g, srcs in gs:
+        off, tg, wt = graph_to_dev(g)
+        keep.append((off, tg, wt))
+        for s in srcs:
+            qs.append((off, tg, wt, g.n, g.m, s, torch.empty(g.n, dtype=torch.int64, device=DEV)))
+            refs.append(oracle.dijkstra(g, s))
+    print("[sssp] batch autotune", flush=True)
+    t = pkg.sssp_batch_autotune(qs, k_rule=1, k_fixed=6)
+    assert t["d"] == 0 and t["d_scale"] >= 1
+    pkg.sssp_batch(qs, k_rule=1, k_fixed=6, **t)
+    for q, r in zip(qs, refs):
+        assert np.array_equal(host64(q[6]), r)

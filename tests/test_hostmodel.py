@@ -198,3 +198,24 @@ def test_rule_fixed_one_equals_plain_counts():
     rc1, d1, s1 = hm_sssp(g, 0, rule=1, kfix=1)
     assert rc0 == rc1 == 0 and np.array_equal(d0, d1)
     assert s0["rounds"] == s1["rounds"] == s1["extracted"] and s0["relax"] == s1["relax"]
+
+
+@pytest.mark.parametrize("rule", [0, 2])
+def test_trial_limits_settle_everything_below_the_frontier(rule):
+    """max_rounds stops after that many rounds and reports the smallest key
+    left; stop_key = that key then settles every vertex at or below it, for
+    any k rule (the autotuner's equal-work trials)."""
+    g = W.grid8(60, 60, wmax=10000, seed=12)
+    ref = oracle.dijkstra(g, 0)
+    rc, dist, st = hm_sssp(g, 0, max_rounds=500)
+    assert rc == 0 and st["stopped"] and st["rounds"] == 500
+    D = st["last_key"]
+    assert D == int(np.sort(ref)[500])              # plain rounds settle vertices in (dist, id) order
+    kw = dict(rule=1, kfix=12) if rule else {}
+    rc, dist, st = hm_sssp(g, 0, stop_key=D, **kw)
+    assert rc == 0 and st["stopped"] and st["last_key"] > D
+    settled = ref <= D
+    assert np.array_equal(dist[settled], ref[settled])
+    rc, dist, st = hm_sssp(g, 0, stop_key=1 << 62)
+    assert rc == 0 and not st["stopped"] and st["last_key"] == 2 ** 64 - 1
+    assert np.array_equal(dist, ref)
