@@ -10,9 +10,9 @@
 //   k_part<false> / k_scan3 / k_part<true>
 //       Stable three-way split by two (key, id) pivots.
 //   k_sel_*
-//       Select: radix selection on the 96-bit (key, id) value, 11 bits per
-//       pass from the first bit where the keys differ, until few candidates
-//       remain; those are gathered and sorted in one workgroup.
+//       Select: radix selection on the 96-bit (key, id) value, 8 bits per
+//       pass from the first bit where the keys differ, until at most 256
+//       candidates remain; those are gathered and ranked in one workgroup.
 //   k_intake / k_bits<false> / k_bits<true>
 //       BulkUpdate intake: atomicMin on the current keys, an id bitmap of the
 //       ids whose key dropped, and its compaction into U sorted by id.
@@ -34,10 +34,11 @@ namespace {
 constexpr int NT = 256;
 constexpr int WE = 8;
 constexpr u32 TILE = NT * WE;  // 2048
-constexpr int SEL_BITS = 11;
-constexpr int SEL_BINS = 1 << SEL_BITS;
-constexpr u32 CANDMAX = 4096;
-constexpr int GRID_STRIDE = 2048;  // workgroups of the grid-stride kernels
+constexpr int SEL_BITS = 8;
+constexpr int SEL_BINS = 1 << SEL_BITS;  // one bin per thread of the pick kernel
+constexpr u32 CANDMAX = NT;              // candidates ranked by one workgroup
+constexpr int GRID_STRIDE = 2048;        // workgroups of the grid-stride kernels
+constexpr int GRID_HIST = 512;           // workgroups of a Select pass (each flushes <= 256 atomics)
 
 // Results of the device steps, copied to the host after each step.
 struct Ctl {
@@ -188,13 +189,47 @@ __global__ void k_mpart(const u32* av, u32 na, const u32* bv, u32 nb, u32 ntiles
   part[t] = mpath<false>((const u64*)nullptr, av, na, (const u64*)nullptr, bv, nb, diag);
 }
 
-// One tile of merge(A, B) by id with DeleteDuplicates.  Counting pass: tcnt[t]
-// = kept outputs.  Writing pass: the kept outputs go to C at toff[t].
+// First index in v[0, n) whose id is >= x (lower) or > x (upper).
+__device__ __forceinline__ u32 lower_id(const u32* v, u32 n, u32 x) {
+  u32 lo = 0, hi = n;
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1;
+    if (v[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ u32 upper_id(const u32* v, u32 n, u32 x) {
+  u32 lo = 0, hi = n;
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1;
+    if (v[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One tile of merge(A, B) by id with DeleteDuplicates: the outputs at merge
+// positions [t*TILE, (t+1)*TILE), whose inputs are A[i0, i1) and B[j0, j1).
+// Every element finds its position in the tile by a binary search of its id
+// in the other input's window (ties: A first), independently of the others.
+// The copy of an id present in both inputs is decided at A's slot (pair_keep)
+// and B's slot is dropped; a partner just outside the window is A[i0-1] or
+// B[j1].  Counting pass: tcnt[t] = kept outputs.  Writing pass: the tile is
+// laid out in merge order in LDS, compacted, and stored coalesced at C +
+// toff[t]; with `stats` it also counts outputs <= (pk, pv) and the key range.
 template <bool WRITE>
-__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Ctl* ctl) {
+__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Ctl* ctl,
+                                              int stats) {
   __shared__ u64 sk[WRITE ? TILE : 1];
   __shared__ u32 sv[TILE];
+  __shared__ unsigned char skeep[WRITE ? TILE : 1];
   __shared__ u32 sw[NT / 64];
+  __shared__ u32 swr[WE][NT / 64];
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   const u32 t = blockIdx.x, total = a.na + a.nb;
   const u32 d0 = t * TILE, d1 = min(d0 + TILE, total);
@@ -210,77 +245,110 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
       if constexpr (WRITE) sk[x] = a.bk[j0 + x - nA];
     }
   }
-  // neighbours just outside the tile decide duplicates across its edges
   const bool hasPrev = i0 > 0, hasNext = j1 < a.nb;
   const u32 aprev = hasPrev ? a.av[i0 - 1] : 0u, bnext = hasNext ? a.bv[j1] : 0u;
   __syncthreads();
   const u32* sA = sv;
   const u32* sB = sv + nA;
-  const u32 dd0 = min((u32)threadIdx.x * WE, nT), dd1 = min(dd0 + WE, nT);
-  u32 i = mpath<false>((const u64*)nullptr, sA, nA, (const u64*)nullptr, sB, nB, dd0), j = dd0 - i;
+  u32 pos[WE];
   u64 ko[WE];
   u32 vo[WE];
   u32 keep = 0;
 #pragma unroll
-  for (int s = 0; s < WE; ++s) {
-    ko[s] = 0;
-    vo[s] = 0;
-    if (dd0 + s < dd1) {
-      const bool takeA = i < nA && (j >= nB || sA[i] <= sB[j]);
-      bool kp = true;
-      u64 k = 0;
-      u32 v;
-      if (takeA) {
-        v = sA[i];
-        const bool dup = j < nB ? sB[j] == v : (hasNext && bnext == v);
-        if constexpr (WRITE) k = sk[i];
-        if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
-          u64 ka, kb;
-          if constexpr (WRITE) {
-            ka = sk[i];
-            kb = j < nB ? sk[nA + j] : a.bk[j1];
-          } else {
-            ka = a.ak[i0 + i];
-            kb = j < nB ? a.bk[j0 + j] : a.bk[j1];
-          }
-          kp = pair_keep(a, ka, kb, v, &k);
-        }
-        ++i;
-      } else {
-        v = sB[j];
-        const bool prevdup = i > 0 ? sA[i - 1] == v : (hasPrev && aprev == v);
-        kp = !prevdup;
+  for (int q = 0; q < WE; ++q) {
+    const u32 x = threadIdx.x + (u32)q * NT;
+    pos[q] = 0;
+    ko[q] = 0;
+    vo[q] = 0;
+    if (x >= nT) continue;
+    const u32 v = sv[x];
+    bool kp = true;
+    u64 k = 0;
+    if constexpr (WRITE) k = sk[x];
+    if (x < nA) {
+      const u32 lb = lower_id(sB, nB, v);
+      pos[q] = x + lb;
+      const bool dup = lb < nB ? sB[lb] == v : (hasNext && bnext == v);
+      if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
+        u64 ka, kb;
         if constexpr (WRITE) {
-          k = sk[nA + j];
+          ka = k;
+          kb = lb < nB ? sk[nA + lb] : a.bk[j1];
         } else {
-          if (kp && a.filterB) k = a.bk[j0 + j];
+          ka = a.ak[i0 + x];
+          kb = lb < nB ? a.bk[j0 + lb] : a.bk[j1];
         }
-        if (kp && a.filterB && a.cur[v] != k) kp = false;
-        ++j;
+        kp = pair_keep(a, ka, kb, v, &k);
       }
-      ko[s] = k;
-      vo[s] = v;
-      keep |= (u32)kp << s;
+    } else {
+      const u32 j = x - nA;
+      const u32 ub = upper_id(sA, nA, v);
+      pos[q] = j + ub;
+      kp = !(ub > 0 ? sA[ub - 1] == v : (hasPrev && aprev == v));
+      if (kp && a.filterB) {
+        if constexpr (!WRITE) k = a.bk[j0 + j];
+        kp = a.cur[v] == k;
+      }
     }
+    ko[q] = k;
+    vo[q] = v;
+    keep |= (u32)kp << q;
   }
-  const u32 c = (u32)__builtin_popcount(keep);
   if constexpr (!WRITE) {
-    u32 tot = block_sum<NT>(c, sw);
+    const u32 tot = block_sum<NT>((u32)__builtin_popcount(keep), sw);
     if (threadIdx.x == 0) tcnt[t] = tot;
   } else {
-    u32 tot;
-    u32 pos = block_scan<NT>(c, &tot, sw);  // also orders the LDS reads above before the writes below
+    __syncthreads();  // every read of the input windows is done
+#pragma unroll
+    for (int q = 0; q < WE; ++q)
+      if (threadIdx.x + (u32)q * NT < nT) {
+        sk[pos[q]] = ko[q];
+        sv[pos[q]] = vo[q];
+        skeep[pos[q]] = (unsigned char)((keep >> q) & 1u);
+      }
+    __syncthreads();
+    // compaction in merge order: round q covers positions [q*NT, (q+1)*NT)
+    const int w = (int)(threadIdx.x >> 6);
+    u32 kbits = 0;
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      const bool kp = x < nT && skeep[x];
+      kbits |= (u32)kp << q;
+      const u64 m = __ballot(kp);
+      if ((threadIdx.x & 63) == 0) swr[q][w] = (u32)__builtin_popcountll(m);
+      ko[q] = kp ? sk[x] : 0;
+      vo[q] = kp ? sv[x] : 0;
+    }
+    __syncthreads();
+    // output slot = kept outputs of earlier rounds + of earlier waves in this
+    // round + of lower lanes in this wave
+    u32 acc = 0;
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      u32 base = acc;
+#pragma unroll
+      for (int ww = 0; ww < NT / 64; ++ww) {
+        if (ww < w) base += swr[q][ww];
+        acc += swr[q][ww];
+      }
+      const u64 m = __ballot((kbits >> q) & 1u);
+      pos[q] = base + (u32)__builtin_popcountll(m & ((1ull << (threadIdx.x & 63)) - 1ull));
+    }
+    const u32 tot = acc;
+    __syncthreads();
     u32 nle = 0;
     u64 lo = KINF, hi = 0;
 #pragma unroll
-    for (int s = 0; s < WE; ++s)
-      if ((keep >> s) & 1u) {
-        sk[pos] = ko[s];
-        sv[pos] = vo[s];
-        ++pos;
-        nle += kv_le(KV{ko[s], vo[s]}, KV{a.pk, a.pv});
-        lo = ko[s] < lo ? ko[s] : lo;
-        hi = ko[s] > hi ? ko[s] : hi;
+    for (int q = 0; q < WE; ++q)
+      if ((kbits >> q) & 1u) {
+        sk[pos[q]] = ko[q];
+        sv[pos[q]] = vo[q];
+        if (stats) {
+          nle += kv_le(KV{ko[q], vo[q]}, KV{a.pk, a.pv});
+          lo = ko[q] < lo ? ko[q] : lo;
+          hi = ko[q] > hi ? ko[q] : hi;
+        }
       }
     __syncthreads();
     const u32 base = toff[t];
@@ -288,13 +356,15 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
       a.ck[base + x] = sk[x];
       a.cv[base + x] = sv[x];
     }
-    nle = block_sum<NT>(nle, sw);
-    block_minmax<NT>(lo, hi, swl, swh);
-    if (threadIdx.x == 0) {
-      if (nle) atomic_add32(&ctl->num_le, nle);
-      if (tot) {
-        atomic_min64(&ctl->kmin, lo);
-        atomic_max64(&ctl->kmax, hi);
+    if (stats) {
+      nle = block_sum<NT>(nle, sw);
+      block_minmax<NT>(lo, hi, swl, swh);
+      if (threadIdx.x == 0) {
+        if (nle) atomic_add32(&ctl->num_le, nle);
+        if (tot) {
+          atomic_min64(&ctl->kmin, lo);
+          atomic_max64(&ctl->kmax, hi);
+        }
       }
     }
   }
@@ -466,56 +536,44 @@ __global__ __launch_bounds__(NT) void k_sel_hist(const u64* K, const u32* V, u32
     if (h[b]) atomic_add32(&c->shist[b], h[b]);
 }
 
+// One pass's pick: bin b (one per thread) holds the sought rank; its digit
+// joins the prefix.  Clears the histogram for the next pass.
 __global__ __launch_bounds__(NT) void k_sel_pick(Ctl* c) {
+  static_assert(SEL_BINS == NT, "one bin per thread");
   __shared__ u32 sw[NT / 64];
   if (c->sdone) return;
-  constexpr int PER = SEL_BINS / NT;
-  u32 loc[PER];
-  u32 sum = 0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    loc[q] = c->shist[threadIdx.x * PER + q];
-    sum += loc[q];
-  }
+  const u32 b = threadIdx.x;
+  const u32 h = c->shist[b];
   u32 tot;
-  u32 before = block_scan<NT>(sum, &tot, sw);
+  const u32 before = block_scan<NT>(h, &tot, sw);
   const u32 rank = c->srank;
   const int nb = c->snb;
   const int w = 96 - nb < SEL_BITS ? 96 - nb : SEL_BITS;
   const int p = 96 - nb - w;
-  if (before < rank && rank <= before + sum) {
-    u32 acc = before;
-    for (int q = 0; q < PER; ++q) {
-      if (acc + loc[q] >= rank) {
-        const u32 b = threadIdx.x * PER + q;
-        u64 pk = c->spk;
-        u32 pv = c->spv;
-        if (p >= 32) {
-          pk |= (u64)b << (p - 32);
-        } else {
-          u64 lo = ((pk & 0xFFFFFFFFull) << 32) | pv;
-          lo |= (u64)b << p;
-          pk = (pk & 0xFFFFFFFF00000000ull) | (lo >> 32);
-          pv = (u32)lo;
-        }
-        c->spk = pk;
-        c->spv = pv;
-        c->snb = nb + w;
-        c->srank = rank - acc;
-        c->scnt = loc[q];
-        c->sdone = loc[q] <= CANDMAX || nb + w == 96;
-        break;
-      }
-      acc += loc[q];
+  if (h && before < rank && rank <= before + h) {
+    u64 pk = c->spk;
+    u32 pv = c->spv;
+    if (p >= 32) {
+      pk |= (u64)b << (p - 32);
+    } else {
+      u64 lo = ((pk & 0xFFFFFFFFull) << 32) | pv;
+      lo |= (u64)b << p;
+      pk = (pk & 0xFFFFFFFF00000000ull) | (lo >> 32);
+      pv = (u32)lo;
     }
+    c->spk = pk;
+    c->spv = pv;
+    c->snb = nb + w;
+    c->srank = rank - before;
+    c->scnt = h;
+    c->sdone = h <= CANDMAX || nb + w == 96;
   }
   if (threadIdx.x == 0 && (rank == 0 || rank > tot)) {
     c->sbad = 1;
     c->sdone = 1;
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) c->shist[threadIdx.x * PER + q] = 0;
+  c->shist[b] = 0;
 }
 
 __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, u32 n, Ctl* c, u64* ck, u32* cv) {
@@ -560,24 +618,28 @@ __device__ void bitonic_lds(u64* k, u32* v) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv) {
+// The remaining candidates (<= 256, distinct (key, id)) are ranked by
+// counting: the one with exactly rank-1 smaller candidates is the answer.
+__global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv) {
   __shared__ u64 sk[CANDMAX];
   __shared__ u32 sv[CANDMAX];
   if (!c->sdone || c->sbad) return;
   const u32 n = c->sncand < CANDMAX ? c->sncand : CANDMAX;
-  for (u32 x = threadIdx.x; x < CANDMAX; x += 1024) {
-    sk[x] = x < n ? ck[x] : KINF;
-    sv[x] = x < n ? cv[x] : VINF;
+  const u32 r = c->srank;
+  if (threadIdx.x < n) {
+    sk[threadIdx.x] = ck[threadIdx.x];
+    sv[threadIdx.x] = cv[threadIdx.x];
   }
   __syncthreads();
-  bitonic_lds<CANDMAX, 1024>(sk, sv);
-  if (threadIdx.x == 0) {
-    const u32 r = c->srank;
-    if (r == 0 || r > n || c->sncand != c->scnt) {
-      c->sbad = 1;
-    } else {
-      c->rk = sk[r - 1];
-      c->rv = sv[r - 1];
+  if (threadIdx.x == 0 && (r == 0 || r > n || c->sncand != c->scnt)) c->sbad = 1;
+  if (threadIdx.x < n) {
+    const u64 k = sk[threadIdx.x];
+    const u32 v = sv[threadIdx.x];
+    u32 below = 0;
+    for (u32 y = 0; y < n; ++y) below += sk[y] < k || (sk[y] == k && sv[y] < v);
+    if (below + 1 == r) {
+      c->rk = k;
+      c->rv = v;
     }
   }
 }
@@ -798,7 +860,7 @@ int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : E_DEVICE; }
 
 // C = DeleteDuplicates(Merge(A, B)) by id; *num_le = outputs <= piv.
 int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, int prefer, bool filterB, KV piv,
-           u32* m, u32* num_le) {
+           u32* m, u32* num_le, bool stats = true) {
   const u64 total = (u64)na + nb;
   if (total == 0) {
     *m = 0;
@@ -810,9 +872,11 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
   hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
-  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->ctl);
+  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->ctl,
+                     0);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
-  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->ctl);
+  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->ctl,
+                     stats ? 1 : 0);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->hctl->total;
@@ -828,15 +892,16 @@ int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
     hipLaunchKernelGGL(k_minmax, dim3(grid_for(n)), dim3(NT), 0, w->s, A.k, n, w->ctl);
   }
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(NT), 0, w->s, w->ctl, r, n);
-  const u32 g = grid_for(n);
-  // Each pass fixes 11 more of the 96 bits, so 9 passes always finish.
-  for (int round = 0; round < 3; ++round) {
-    for (int p = 0; p < 3; ++p) {
-      hipLaunchKernelGGL(k_sel_hist, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl);
+  const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
+  // Each pass fixes 8 more of the 96 bits, so 12 passes always finish;
+  // typically two do.  Passes after the last needed one return at once.
+  for (int round = 0; round < 4; ++round) {
+    for (int p = 0; p < (round == 0 ? 2 : 4); ++p) {
+      hipLaunchKernelGGL(k_sel_hist, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl);
       hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(NT), 0, w->s, w->ctl);
     }
     hipLaunchKernelGGL(k_sel_collect, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v);
-    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1024), 0, w->s, w->ctl, w->cand_k, w->cand_v);
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v);
     if (int rc = launch_ok()) return rc;
     if (int rc = fetch(w)) return rc;
     if (w->hctl->sbad) return E_INTERNAL;
@@ -927,7 +992,7 @@ int wresolve(WideScratch* w, const Geom& g, HeapState* st, const u64* cur, int i
       if ((u64)b.nS + n1 > capS(g.d, i + 1)) return E_INTERNAL;
       Arr Sn = lbuf(g, i + 1, 3 + b.ssel), Sn2 = lbuf(g, i + 1, 3 + (b.ssel ^ 1));
       u32 ms, dummy;
-      if ((rc = wmerge(w, Sn, b.nS, Hi, n1, Sn2, cur, PREFER_LIVE, false, kv_inf(), &ms, &dummy))) return rc;
+      if ((rc = wmerge(w, Sn, b.nS, Hi, n1, Sn2, cur, PREFER_LIVE, false, kv_inf(), &ms, &dummy, false))) return rc;
       touched += 2ull * (b.nS + n1) + ms;
       b.ssel ^= 1;
       b.nS = ms;
@@ -966,7 +1031,7 @@ int wresolve(WideScratch* w, const Geom& g, HeapState* st, const u64* cur, int i
       Arr Bi = lbuf(g, i, a.bsel), Bi2 = lbuf(g, i, a.bsel ^ 1);
       u32 mb;
       if ((rc = wmerge(w, Bi, a.nB, Up, nu, Bi2, cur, i == 0 ? PREFER_B : PREFER_LIVE, false, kv_inf(), &mb,
-                       &dummy)))
+                       &dummy, false)))
         return rc;
       touched += 2ull * (a.nB + nu) + mb;
       a.bsel ^= 1;
