@@ -236,13 +236,29 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
   const u32 i0 = part[t], i1 = part[t + 1];
   const u32 j0 = d0 - i0, j1 = d1 - i1;
   const u32 nA = i1 - i0, nT = d1 - d0, nB = nT - nA;
-  for (u32 x = threadIdx.x; x < nT; x += NT) {
-    if (x < nA) {
-      sv[x] = a.av[i0 + x];
-      if constexpr (WRITE) sk[x] = a.ak[i0 + x];
-    } else {
-      sv[x] = a.bv[j0 + x - nA];
-      if constexpr (WRITE) sk[x] = a.bk[j0 + x - nA];
+  {
+    // all of the thread's loads are issued before any is waited for
+    u64 lk[WE];
+    u32 lv[WE];
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      const bool fromA = x < nA;
+      const u32 g = fromA ? i0 + x : j0 + (x - nA);
+      lv[q] = 0;
+      lk[q] = 0;
+      if (x < nT) {
+        lv[q] = fromA ? a.av[g] : a.bv[g];
+        if constexpr (WRITE) lk[q] = fromA ? a.ak[g] : a.bk[g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      if (x < nT) {
+        sv[x] = lv[q];
+        if constexpr (WRITE) sk[x] = lk[q];
+      }
     }
   }
   const bool hasPrev = i0 > 0, hasNext = j1 < a.nb;
@@ -435,17 +451,20 @@ __global__ __launch_bounds__(NT) void k_part(PArgs a, u32* tc, const u32* toff, 
     run[1] = toff[stride + t];
     run[2] = toff[2 * stride + t];
   }
+  u64 kk[WE];
+  u32 vv[WE];
 #pragma unroll
   for (int r = 0; r < WE; ++r) {
     const u64 x = base + (u64)r * NT + threadIdx.x;
-    u32 c = 3;
-    u64 k = 0;
-    u32 v = 0;
-    if (x < a.n) {
-      k = a.k[x];
-      v = a.v[x];
-      c = pclass(a, k, v);
-    }
+    kk[r] = x < a.n ? a.k[x] : 0;
+    vv[r] = x < a.n ? a.v[x] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < WE; ++r) {
+    const u64 x = base + (u64)r * NT + threadIdx.x;
+    const u64 k = kk[r];
+    const u32 v = vv[r];
+    const u32 c = x < a.n ? pclass(a, k, v) : 3u;
     if constexpr (!WRITE) {
       c01 += c == 0 ? 1u : (c == 1 ? 1u << 16 : 0u);
       c2 += c == 2;
@@ -526,10 +545,19 @@ __global__ __launch_bounds__(NT) void k_sel_hist(const u64* K, const u32* V, u32
   const int p = 96 - nb - w;
   for (int b = threadIdx.x; b < SEL_BINS; b += NT) h[b] = 0;
   __syncthreads();
-  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
-    u64 k = K[x];
-    u32 v = V[x];
-    if (sel_match(k, v, pk, pv, nb)) atomicAdd(&h[sel_digit(k, v, p, w)], 1u);
+  const u64 step = (u64)gridDim.x * NT;
+  for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
+    u64 k[4];
+    u32 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 x = x0 + q * step;
+      k[q] = x < n ? K[x] : KINF;
+      v[q] = x < n ? V[x] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (x0 + q * step < n && sel_match(k[q], v[q], pk, pv, nb)) atomicAdd(&h[sel_digit(k[q], v[q], p, w)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < SEL_BINS; b += NT)
@@ -583,16 +611,25 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
   const u64 pk = c->spk;
   const u32 pv = c->spv;
   const int nb = c->snb;
-  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
-    u64 k = K[x];
-    u32 v = V[x];
-    if (sel_match(k, v, pk, pv, nb)) {
-      u32 o = atomic_add32(&c->sncand, 1u);
-      if (o < CANDMAX) {
-        ck[o] = k;
-        cv[o] = v;
-      }
+  const u64 step = (u64)gridDim.x * NT;
+  for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
+    u64 k[4];
+    u32 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 x = x0 + q * step;
+      k[q] = x < n ? K[x] : KINF;
+      v[q] = x < n ? V[x] : 0u;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (x0 + q * step < n && sel_match(k[q], v[q], pk, pv, nb)) {
+        u32 o = atomic_add32(&c->sncand, 1u);
+        if (o < CANDMAX) {
+          ck[o] = k[q];
+          cv[o] = v[q];
+        }
+      }
   }
 }
 
@@ -647,10 +684,17 @@ __global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const 
 __global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Ctl* c) {
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   u64 lo = KINF, hi = 0;
-  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < n; x += (u64)gridDim.x * NT) {
-    u64 k = K[x];
-    lo = k < lo ? k : lo;
-    hi = k > hi ? k : hi;
+  const u64 step = (u64)gridDim.x * NT;
+  for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
+    u64 k[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) k[q] = x0 + q * step < n ? K[x0 + q * step] : KINF;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (x0 + q * step < n) {
+        lo = k[q] < lo ? k[q] : lo;
+        hi = k[q] > hi ? k[q] : hi;
+      }
   }
   block_minmax<NT>(lo, hi, swl, swh);
   if (threadIdx.x == 0 && lo <= hi) {
@@ -665,15 +709,25 @@ __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, 
                                                Ctl* c) {
   __shared__ u32 sw[NT / 64];
   u32 newly = 0;
-  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < count; x += (u64)gridDim.x * NT) {
-    const u32 id = ids[x];
-    const u64 k = keys[x];
-    const u64 old = atomic_min64(cur + id, k);
-    if (k < old) {
-      __hip_atomic_fetch_or((u32 PBH_GLB*)(bitmap + (id >> 5)), 1u << (id & 31), __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-      newly += old == KINF;
+  const u64 step = (u64)gridDim.x * NT;
+  for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < count; x0 += 4 * step) {
+    u32 id[4];
+    u64 k[4], old[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u64 x = x0 + q * step;
+      id[q] = x < count ? ids[x] : 0u;
+      k[q] = x < count ? keys[x] : KINF;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) old[q] = x0 + q * step < count ? atomic_min64(cur + id[q], k[q]) : KINF;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (k[q] < old[q]) {
+        __hip_atomic_fetch_or((u32 PBH_GLB*)(bitmap + (id[q] >> 5)), 1u << (id[q] & 31), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        newly += old[q] == KINF;
+      }
   }
   newly = block_sum<NT>(newly, sw);
   if (threadIdx.x == 0 && newly) atomic_add64(&c->newly, newly);
@@ -726,10 +780,20 @@ __global__ __launch_bounds__(NT) void k_tsort(const u64* sk_, const u32* sv_, u3
   __shared__ u64 sk[TILE];
   __shared__ u32 sv[TILE];
   const u64 base = (u64)blockIdx.x * TILE;
-  for (u32 x = threadIdx.x; x < TILE; x += NT) {
-    const u64 g = base + x;
-    sk[x] = g < n ? sk_[g] : KINF;
-    sv[x] = g < n ? sv_[g] : VINF;
+  {
+    u64 lk[WE];
+    u32 lv[WE];
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u64 g = base + threadIdx.x + (u64)q * NT;
+      lk[q] = g < n ? sk_[g] : KINF;
+      lv[q] = g < n ? sv_[g] : VINF;
+    }
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      sk[threadIdx.x + q * NT] = lk[q];
+      sv[threadIdx.x + q * NT] = lv[q];
+    }
   }
   __syncthreads();
   bitonic_lds<TILE, NT>(sk, sv);
@@ -775,10 +839,24 @@ __global__ __launch_bounds__(NT) void k_smerge(const u64* K, const u32* V, u32 n
   const u32 i1 = d1 == na + nb ? na : part[t + 1];
   const u32 j0 = d0 - i0, j1 = d1 - i1;
   const u32 nA = i1 - i0, nT = d1 - d0, nB = j1 - j0;
-  for (u32 x = threadIdx.x; x < nT; x += NT) {
-    const u32 g = x < nA ? b + i0 + x : b + na + j0 + (x - nA);
-    sk[x] = K[g];
-    sv[x] = V[g];
+  {
+    u64 lk[WE];
+    u32 lv[WE];
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      const u32 g = x < nA ? b + i0 + x : b + na + j0 + (x - nA);
+      lk[q] = x < nT ? K[g] : 0;
+      lv[q] = x < nT ? V[g] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      if (x < nT) {
+        sk[x] = lk[q];
+        sv[x] = lv[q];
+      }
+    }
   }
   __syncthreads();
   const u32 dd0 = min((u32)threadIdx.x * WE, nT), dd1 = min(dd0 + WE, nT);
