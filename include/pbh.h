@@ -113,6 +113,15 @@ int pbh_size(pbh_t *h, uint64_t *size_out);
  */
 int pbh_traffic(pbh_t *h, uint64_t *elements_out);
 
+/*
+ * pbh_merge_profile: for the device-wide engine, totals over the writing
+ * passes of its merges (Merge + DeleteDuplicates, its largest kernel) since
+ * the handle was created: launches, algorithmic bytes (12 per input element
+ * read + 12 per output element written) and summed HIP-event time in ms (host
+ * outputs).  Zeros for the one-workgroup engine.
+ */
+int pbh_merge_profile(pbh_t *h, uint64_t *launches, uint64_t *bytes, double *ms);
+
 /* pbh_destroy: frees the handle and its arena.  NULL is accepted. */
 int pbh_destroy(pbh_t *h);
 
@@ -247,21 +256,22 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
  * sssp_autotune: picks opts->d and opts->k_max for this query by timing trial
  * runs on the query itself.  A plain trial of a few rounds finds a distance
  * frontier D (the smallest key left after them); then each candidate
- * (d = max out-degree * 1, 2, 4, ... up to 2048, and k_max 64 or 256 when
+ * (d = max out-degree * 1, 2, 4, ... up to 2048; team 64 or 256 threads for
+ * d in [64, 2048] unless opts->team fixes it; k_max 64 or 256 when
  * k_rule != 0) runs until every vertex closer than D is settled, which is the
  * same work for every candidate, and the fastest is written back into *opts
- * (the other fields are kept and used for the trials).  dist_out is used as
- * scratch.  Errors: those of sssp_ex.
+ * (d, team, k_max; the other fields are kept and used for the trials).
+ * dist_out is used as scratch.  Errors: those of sssp_ex.
  */
 int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
                   uint64_t m, uint32_t source, uint64_t *dist_out, sssp_opts *opts, void *stream);
 
 /*
- * sssp_batch_autotune: picks opts->d_scale (with opts->d = 0) and opts->k_max
- * for a batch by timing each candidate as one sssp_batch launch over a sample
- * of the queries (up to 16 around the median size, run to completion); the
- * fastest is written back into *opts.  Those queries' dist_out arrays are
- * used as scratch.  Errors: those of sssp_batch.
+ * sssp_batch_autotune: picks opts->d_scale (with opts->d = 0), opts->team and
+ * opts->k_max for a batch: the largest query (the critical path of the
+ * persistent launch) is tuned as by sssp_autotune and its multiple of the
+ * maximum out-degree applies to every query.  That query's dist_out is used
+ * as scratch.  Errors: those of sssp_ex.
  */
 int sssp_batch_autotune(const sssp_query *queries, uint32_t nq, sssp_opts *opts, void *stream);
 

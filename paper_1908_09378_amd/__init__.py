@@ -60,7 +60,7 @@ class SsspQuery(C.Structure):
 
 
 _lib = None
-EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_destroy",
+EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "pbh_last_error"]
 
@@ -79,6 +79,7 @@ def lib():
         L.pbh_extract_min.argtypes = [vp, u64, vp, vp, C.POINTER(u64)]
         L.pbh_size.argtypes = [vp, C.POINTER(u64)]
         L.pbh_traffic.argtypes = [vp, C.POINTER(u64)]
+        L.pbh_merge_profile.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(C.c_double)]
         L.pbh_destroy.argtypes = [vp]
         L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
@@ -160,7 +161,7 @@ def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *,
 
 
 def _tuned(o) -> dict:
-    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max)
+    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max, team=o.team)
 
 
 def sssp_autotune(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:
@@ -246,6 +247,13 @@ class Heap:
         n = C.c_uint64(0)
         _check(lib().pbh_size(self._h, C.byref(n)))
         return n.value
+
+    def merge_profile(self) -> dict:
+        """Device-wide engine: launches, algorithmic bytes and HIP-event ms of
+        the merge writing passes so far."""
+        a, b, t = C.c_uint64(0), C.c_uint64(0), C.c_double(0)
+        _check(lib().pbh_merge_profile(self._h, C.byref(a), C.byref(b), C.byref(t)))
+        return dict(launches=a.value, bytes=b.value, ms=t.value)
 
     def traffic(self) -> int:
         """Heap elements read or written by the level operations so far."""

@@ -363,6 +363,17 @@ int pbh_extract_min(pbh_t* h, uint64_t k, uint64_t* keys_out, uint32_t* ids_out,
   return PBH_OK;
 }
 
+int pbh_merge_profile(pbh_t* h, uint64_t* launches, uint64_t* bytes, double* ms) {
+  if (!h || !launches || !bytes || !ms) return fail(PBH_EINVAL, "pbh_merge_profile: NULL argument");
+  u64 l = 0, b = 0;
+  double t = 0.0;
+  if (h->wide) wide_merge_profile(h->wide, &l, &b, &t);
+  *launches = l;
+  *bytes = b;
+  *ms = t;
+  return PBH_OK;
+}
+
 int pbh_traffic(pbh_t* h, uint64_t* elements_out) {
   if (!h || !elements_out) return fail(PBH_EINVAL, "pbh_traffic: NULL argument");
   int rc = pull_state(h);
@@ -797,7 +808,7 @@ namespace {
 // and the fastest wins.  Returns the winning multiple and k_max.
 int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
                uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream, u32* mult_out,
-               u32* kmax_out, u32* maxdeg_out) {
+               u32* kmax_out, u32* maxdeg_out, u32* team_out) {
   sssp_opts base = user;
   base.stop_key = 0;
   base.max_rounds = 0;
@@ -815,28 +826,47 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
   const bool spec = user.k_rule != 0;
   const u32 kms[2] = {64, 256};
   double best = 1e300;
-  u32 bm = 1, bk = user.k_max;
+  u32 bm = 1, bk = user.k_max, bt = user.team;
   for (u32 mult = 1; (u64)maxdeg * mult <= 2048 || mult == 1; mult *= 2) {
-    for (int ki = 0; ki < (spec ? 2 : 1); ++ki) {
-      sssp_opts t = base;
-      t.d = maxdeg * mult;
-      if (spec) t.k_max = kms[ki];
-      t.stop_key = D == KINF ? 0 : D;
-      sssp_stats st;
-      rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
-      if (rc == PBH_EINVAL) return rc;  // e.g. the LDS does not fit: a caller error, not a candidate's
-      if (rc) continue;
-      if (st.kernel_ms < best) {
-        best = st.kernel_ms;
-        bm = mult;
-        bk = spec ? kms[ki] : user.k_max;
-      }
+    const u32 d = maxdeg * mult;
+    // team sizes worth trying at this d (a caller's fixed team is kept)
+    u32 teams[2] = {0, 0};
+    int nt = 1;
+    if (user.team) {
+      teams[0] = user.team;
+    } else if (d < 64) {
+      teams[0] = 64;
+    } else if (d <= 2048) {
+      teams[0] = 64;
+      teams[1] = 256;
+      nt = 2;
+    } else {
+      teams[0] = 1024;
     }
+    for (int ti = 0; ti < nt; ++ti)
+      for (int ki = 0; ki < (spec ? 2 : 1); ++ki) {
+        sssp_opts t = base;
+        t.d = d;
+        t.team = teams[ti];
+        if (spec) t.k_max = kms[ki];
+        t.stop_key = D == KINF ? 0 : D;
+        sssp_stats st;
+        rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
+        if (rc == PBH_EINVAL) continue;  // e.g. the LDS levels do not fit with this team
+        if (rc) return rc;
+        if (st.kernel_ms < best) {
+          best = st.kernel_ms;
+          bm = mult;
+          bt = teams[ti];
+          bk = spec ? kms[ki] : user.k_max;
+        }
+      }
   }
   if (best == 1e300) return fail(PBH_EINTERNAL, "sssp_autotune: every candidate failed");
   *mult_out = bm;
   *kmax_out = bk;
   *maxdeg_out = maxdeg;
+  *team_out = bt;
   return PBH_OK;
 }
 
@@ -847,12 +877,14 @@ extern "C" {
 int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n,
                   uint64_t m, uint32_t source, uint64_t* dist_out, sssp_opts* opts, void* stream) {
   if (!opts) return fail(PBH_EINVAL, "sssp_autotune: opts is NULL");
-  u32 mult = 1, kmax = 0, maxdeg = 1;
-  int rc = tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg);
+  u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
+  int rc =
+      tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg, &team);
   if (rc) return rc;
   opts->d = maxdeg * mult;
   opts->d_scale = 0;
   opts->k_max = kmax;
+  opts->team = team;
   return PBH_OK;
 }
 
@@ -868,13 +900,14 @@ int sssp_batch_autotune(const sssp_query* queries, uint32_t nq, sssp_opts* opts,
   const sssp_query& q = queries[big];
   if (!q.offsets || !q.dist_out || (q.m > 0 && (!q.targets || !q.weights)) || q.n == 0 || q.source >= q.n)
     return fail(PBH_EINVAL, "sssp_batch_autotune: query %u is malformed", big);
-  u32 mult = 1, kmax = 0, maxdeg = 1;
+  u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
   int rc = tune_query(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, *opts, stream, &mult, &kmax,
-                      &maxdeg);
+                      &maxdeg, &team);
   if (rc) return rc;
   opts->d = 0;
   opts->d_scale = mult;
   opts->k_max = kmax;
+  opts->team = team;
   return PBH_OK;
 }
 

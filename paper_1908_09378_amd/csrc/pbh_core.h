@@ -1175,17 +1175,33 @@ PBH_INL void record_trace(const T& t, const Geom& g, SP st, const SpecCfg& sc, A
 template <class T, class GA>
 PBH_INL u32 intake_list(const T& t, GA U, u32 n, GA W, const u64* dist, int idbits) {
   u32 out = 0;
-  for (u32 base = 0; base < n; base += (u32)T::kNT) {
-    u32 x = base + (u32)t.tid();
-    bool keep = x < n && t.load_cur(dist + U.v[x]) == U.k[x];
-    u64 k = x < n ? U.k[x] : 0;
-    u32 v = x < n ? U.v[x] : 0;
-    u32 tot;
-    u32 o = out + t.scan_excl(keep ? 1u : 0u, &tot);
-    if (keep) {
-      W.k[o] = k;
-      W.v[o] = v;
+  constexpr int RE = 4;  // elements per thread per pass, loads issued together
+  for (u32 base = 0; base < n; base += (u32)T::kNT * RE) {
+    u64 k[RE], c[RE];
+    u32 v[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      k[r] = x < n ? U.k[x] : 0;
+      v[r] = x < n ? U.v[x] : 0;
     }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      c[r] = x < n ? t.load_cur(dist + v[r]) : ~k[r];
+    }
+    u32 cnt = 0;
+#pragma unroll
+    for (int r = 0; r < RE; ++r) cnt += c[r] == k[r] ? 1u : 0u;
+    u32 tot;
+    u32 o = out + t.scan_excl(cnt, &tot);
+#pragma unroll
+    for (int r = 0; r < RE; ++r)
+      if (c[r] == k[r]) {
+        W.k[o] = k[r];
+        W.v[o] = v[r];
+        ++o;
+      }
     out += tot;
   }
   t.sync();
@@ -1245,31 +1261,53 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
   t.sync();
   G U{(decltype(G::k))sc.uk, (decltype(G::v))sc.uv};
   u32 nu = 0;
-  for (u32 eb = 0; eb < E; eb += (u32)T::kNT) {
-    u32 e = eb + (u32)t.tid();
-    bool imp = false;
-    u64 cand = 0;
-    u32 v = 0;
-    if (e < E) {
-      u32 lo = 0, hi = take;  // largest j with exd[j] <= e
-      while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
-        if (t.sh->exd[mid] <= e)
-          lo = mid;
-        else
-          hi = mid;
+  // RE edges per thread per pass: their CSR loads and atomics are all in
+  // flight before any result is waited for; one scan places the improvements.
+  constexpr int RE = 4;
+  for (u32 eb = 0; eb < E; eb += (u32)T::kNT * RE) {
+    u64 ei[RE], cand[RE];
+    u32 v[RE];
+    bool imp[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u32 e = eb + (u32)r * (u32)T::kNT + (u32)t.tid();
+      ei[r] = 0;
+      cand[r] = 0;
+      if (e < E) {
+        u32 lo = 0, hi = take;  // largest j with exd[j] <= e
+        while (hi - lo > 1) {
+          u32 mid = (lo + hi) >> 1;
+          if (t.sh->exd[mid] <= e)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        ei[r] = t.sh->ex0[lo] + (e - t.sh->exd[lo]);
+        cand[r] = X.k[lo];
       }
-      u64 ei = t.sh->ex0[lo] + (e - t.sh->exd[lo]);
-      v = tg[ei];
-      cand = X.k[lo] + (u64)wt[ei];
-      imp = cand < t.atomic_min(dist + v, cand);
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const bool in = eb + (u32)r * (u32)T::kNT + (u32)t.tid() < E;
+      v[r] = in ? tg[ei[r]] : 0u;
+      cand[r] += in ? (u64)wt[ei[r]] : 0ull;
+    }
+    u32 cnt = 0;
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const bool in = eb + (u32)r * (u32)T::kNT + (u32)t.tid() < E;
+      imp[r] = in && cand[r] < t.atomic_min(dist + v[r], cand[r]);
+      cnt += imp[r] ? 1u : 0u;
     }
     u32 tot;
-    u32 p = t.scan_excl(imp ? 1u : 0u, &tot);
-    if (imp) {
-      U.k[nu + p] = cand;
-      U.v[nu + p] = v;
-    }
+    u32 p = nu + t.scan_excl(cnt, &tot);
+#pragma unroll
+    for (int r = 0; r < RE; ++r)
+      if (imp[r]) {
+        U.k[p] = cand[r];
+        U.v[p] = v[r];
+        ++p;
+      }
     nu += tot;
   }
   t.sync();

@@ -46,4 +46,8 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
 // ascending by (key, id); *count_out = number written.
 int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out);
 
+// Totals over the merge writing passes so far: launches, algorithmic bytes
+// (12 B per input and per output element) and HIP-event time.
+void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms);
+
 }  // namespace bkt

@@ -34,6 +34,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int WE = 8;
 constexpr u32 TILE = NT * WE;  // 2048
+static_assert(TILE / 32 == 64, "the merge's drop bitmap is scanned by one wavefront");
 constexpr int SEL_BITS = 8;
 constexpr int SEL_BINS = 1 << SEL_BITS;  // one bin per thread of the pick kernel
 constexpr u32 CANDMAX = NT;              // candidates ranked by one workgroup
@@ -216,168 +217,118 @@ __device__ __forceinline__ u32 upper_id(const u32* v, u32 n, u32 x) {
 // One tile of merge(A, B) by id with DeleteDuplicates: the outputs at merge
 // positions [t*TILE, (t+1)*TILE), whose inputs are A[i0, i1) and B[j0, j1).
 // Every element finds its position in the tile by a binary search of its id
-// in the other input's window (ties: A first), independently of the others.
-// The copy of an id present in both inputs is decided at A's slot (pair_keep)
-// and B's slot is dropped; a partner just outside the window is A[i0-1] or
-// B[j1].  Counting pass: tcnt[t] = kept outputs.  Writing pass: the tile is
-// laid out in merge order in LDS, compacted, and stored coalesced at C +
-// toff[t]; with `stats` it also counts outputs <= (pk, pv) and the key range.
+// in the other input's window (only the ids sit in LDS; ties: A first).  The
+// copy of an id present in both inputs is decided at A's slot (pair_keep) and
+// B's slot is dropped; a partner just outside the window is A[i0-1] or B[j1].
+// Counting pass: tcnt[t] = kept outputs.  Writing pass: dropped positions are
+// marked in an LDS bitmap, and each kept element goes straight to C at
+// toff[t] + its position - the drops before it (the tile's output range is
+// contiguous, so the L2 gathers the writes into full lines).  With `stats`
+// the writing pass also counts outputs <= (pk, pv) and the key range.
 template <bool WRITE>
 __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Ctl* ctl,
                                               int stats) {
-  __shared__ u64 sk[WRITE ? TILE : 1];
   __shared__ u32 sv[TILE];
-  __shared__ unsigned char skeep[WRITE ? TILE : 1];
+  __shared__ u32 sdrop[TILE / 32];  // bit p: merge position p of the tile is dropped
+  __shared__ u32 spre[TILE / 32];   // dropped positions before word w
   __shared__ u32 sw[NT / 64];
-  __shared__ u32 swr[WE][NT / 64];
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   const u32 t = blockIdx.x, total = a.na + a.nb;
   const u32 d0 = t * TILE, d1 = min(d0 + TILE, total);
   const u32 i0 = part[t], i1 = part[t + 1];
   const u32 j0 = d0 - i0, j1 = d1 - i1;
   const u32 nA = i1 - i0, nT = d1 - d0, nB = nT - nA;
-  {
-    // all of the thread's loads are issued before any is waited for
-    u64 lk[WE];
-    u32 lv[WE];
+  // the thread's own elements: tile slots tid + q*NT (all loads issued first)
+  u64 ko[WE];
+  u32 vo[WE];
 #pragma unroll
-    for (int q = 0; q < WE; ++q) {
-      const u32 x = threadIdx.x + (u32)q * NT;
-      const bool fromA = x < nA;
-      const u32 g = fromA ? i0 + x : j0 + (x - nA);
-      lv[q] = 0;
-      lk[q] = 0;
-      if (x < nT) {
-        lv[q] = fromA ? a.av[g] : a.bv[g];
-        if constexpr (WRITE) lk[q] = fromA ? a.ak[g] : a.bk[g];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < WE; ++q) {
-      const u32 x = threadIdx.x + (u32)q * NT;
-      if (x < nT) {
-        sv[x] = lv[q];
-        if constexpr (WRITE) sk[x] = lk[q];
-      }
+  for (int q = 0; q < WE; ++q) {
+    const u32 x = threadIdx.x + (u32)q * NT;
+    const bool fromA = x < nA;
+    const u32 g = fromA ? i0 + x : j0 + (x - nA);
+    vo[q] = 0;
+    ko[q] = 0;
+    if (x < nT) {
+      vo[q] = fromA ? a.av[g] : a.bv[g];
+      if constexpr (WRITE) ko[q] = fromA ? a.ak[g] : a.bk[g];
     }
   }
+#pragma unroll
+  for (int q = 0; q < WE; ++q) {
+    const u32 x = threadIdx.x + (u32)q * NT;
+    if (x < nT) sv[x] = vo[q];
+  }
+  if (WRITE && threadIdx.x < TILE / 32) sdrop[threadIdx.x] = 0;
   const bool hasPrev = i0 > 0, hasNext = j1 < a.nb;
   const u32 aprev = hasPrev ? a.av[i0 - 1] : 0u, bnext = hasNext ? a.bv[j1] : 0u;
   __syncthreads();
   const u32* sA = sv;
   const u32* sB = sv + nA;
   u32 pos[WE];
-  u64 ko[WE];
-  u32 vo[WE];
   u32 keep = 0;
 #pragma unroll
   for (int q = 0; q < WE; ++q) {
     const u32 x = threadIdx.x + (u32)q * NT;
     pos[q] = 0;
-    ko[q] = 0;
-    vo[q] = 0;
     if (x >= nT) continue;
-    const u32 v = sv[x];
+    const u32 v = vo[q];
     bool kp = true;
-    u64 k = 0;
-    if constexpr (WRITE) k = sk[x];
     if (x < nA) {
       const u32 lb = lower_id(sB, nB, v);
       pos[q] = x + lb;
       const bool dup = lb < nB ? sB[lb] == v : (hasNext && bnext == v);
       if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
-        u64 ka, kb;
-        if constexpr (WRITE) {
-          ka = k;
-          kb = lb < nB ? sk[nA + lb] : a.bk[j1];
-        } else {
-          ka = a.ak[i0 + x];
-          kb = lb < nB ? a.bk[j0 + lb] : a.bk[j1];
-        }
+        const u64 ka = WRITE ? ko[q] : a.ak[i0 + x];
+        const u64 kb = a.bk[lb < nB ? j0 + lb : j1];
+        u64 k = ka;
         kp = pair_keep(a, ka, kb, v, &k);
+        ko[q] = k;
       }
     } else {
       const u32 j = x - nA;
       const u32 ub = upper_id(sA, nA, v);
       pos[q] = j + ub;
       kp = !(ub > 0 ? sA[ub - 1] == v : (hasPrev && aprev == v));
-      if (kp && a.filterB) {
-        if constexpr (!WRITE) k = a.bk[j0 + j];
-        kp = a.cur[v] == k;
-      }
+      if (kp && a.filterB) kp = a.cur[v] == (WRITE ? ko[q] : a.bk[j0 + j]);
     }
-    ko[q] = k;
-    vo[q] = v;
     keep |= (u32)kp << q;
   }
   if constexpr (!WRITE) {
     const u32 tot = block_sum<NT>((u32)__builtin_popcount(keep), sw);
     if (threadIdx.x == 0) tcnt[t] = tot;
   } else {
-    __syncthreads();  // every read of the input windows is done
 #pragma unroll
     for (int q = 0; q < WE; ++q)
-      if (threadIdx.x + (u32)q * NT < nT) {
-        sk[pos[q]] = ko[q];
-        sv[pos[q]] = vo[q];
-        skeep[pos[q]] = (unsigned char)((keep >> q) & 1u);
-      }
+      if (threadIdx.x + (u32)q * NT < nT && !((keep >> q) & 1u))
+        atomicOr(&sdrop[pos[q] >> 5], 1u << (pos[q] & 31));
     __syncthreads();
-    // compaction in merge order: round q covers positions [q*NT, (q+1)*NT)
-    const int w = (int)(threadIdx.x >> 6);
-    u32 kbits = 0;
-#pragma unroll
-    for (int q = 0; q < WE; ++q) {
-      const u32 x = threadIdx.x + (u32)q * NT;
-      const bool kp = x < nT && skeep[x];
-      kbits |= (u32)kp << q;
-      const u64 m = __ballot(kp);
-      if ((threadIdx.x & 63) == 0) swr[q][w] = (u32)__builtin_popcountll(m);
-      ko[q] = kp ? sk[x] : 0;
-      vo[q] = kp ? sv[x] : 0;
+    if (threadIdx.x < TILE / 32) {
+      const u32 c = (u32)__builtin_popcount(sdrop[threadIdx.x]);
+      spre[threadIdx.x] = wave_incl(c) - c;  // TILE / 32 == 64: one wavefront
     }
     __syncthreads();
-    // output slot = kept outputs of earlier rounds + of earlier waves in this
-    // round + of lower lanes in this wave
-    u32 acc = 0;
-#pragma unroll
-    for (int q = 0; q < WE; ++q) {
-      u32 base = acc;
-#pragma unroll
-      for (int ww = 0; ww < NT / 64; ++ww) {
-        if (ww < w) base += swr[q][ww];
-        acc += swr[q][ww];
-      }
-      const u64 m = __ballot((kbits >> q) & 1u);
-      pos[q] = base + (u32)__builtin_popcountll(m & ((1ull << (threadIdx.x & 63)) - 1ull));
-    }
-    const u32 tot = acc;
-    __syncthreads();
+    const u32 base = toff[t];
     u32 nle = 0;
     u64 lo = KINF, hi = 0;
 #pragma unroll
     for (int q = 0; q < WE; ++q)
-      if ((kbits >> q) & 1u) {
-        sk[pos[q]] = ko[q];
-        sv[pos[q]] = vo[q];
+      if ((keep >> q) & 1u) {
+        const u32 p = pos[q], w = p >> 5;
+        const u32 o = base + p - (spre[w] + (u32)__builtin_popcount(sdrop[w] & ((1u << (p & 31)) - 1u)));
+        a.ck[o] = ko[q];
+        a.cv[o] = vo[q];
         if (stats) {
           nle += kv_le(KV{ko[q], vo[q]}, KV{a.pk, a.pv});
           lo = ko[q] < lo ? ko[q] : lo;
           hi = ko[q] > hi ? ko[q] : hi;
         }
       }
-    __syncthreads();
-    const u32 base = toff[t];
-    for (u32 x = threadIdx.x; x < tot; x += NT) {
-      a.ck[base + x] = sk[x];
-      a.cv[base + x] = sv[x];
-    }
     if (stats) {
       nle = block_sum<NT>(nle, sw);
       block_minmax<NT>(lo, hi, swl, swh);
       if (threadIdx.x == 0) {
         if (nle) atomic_add32(&ctl->num_le, nle);
-        if (tot) {
+        if (lo <= hi) {
           atomic_min64(&ctl->kmin, lo);
           atomic_max64(&ctl->kmax, hi);
         }
@@ -919,6 +870,10 @@ struct WideScratch {
   u32* tmp_v = nullptr;
   u32 maxtiles = 0;
   hipStream_t s = 0;
+  // HIP-event timing of the merge writing pass (the engine's largest kernel)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  u64 merge_launches = 0, merge_bytes = 0;
+  double merge_ms = 0.0;
 };
 
 namespace {
@@ -953,12 +908,19 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->ctl,
                      0);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
+  WCHK(hipEventRecord(w->ev0, w->s));
   hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->ctl,
                      stats ? 1 : 0);
+  WCHK(hipEventRecord(w->ev1, w->s));
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->hctl->total;
   *num_le = w->hctl->num_le;
+  float ms = 0.f;
+  WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+  w->merge_ms += ms;
+  w->merge_bytes += 12ull * (total + *m);
+  w->merge_launches += 1;
   return 0;
 }
 
@@ -1171,7 +1133,15 @@ int wide_create(WideScratch** out, u32 d) {
   WCHK(hipMalloc(&w->tmp_k, 4ull * d * sizeof(u64)));
   WCHK(hipMalloc(&w->tmp_v, 4ull * d * sizeof(u32)));
   WCHK(hipMemset(w->ctl, 0, sizeof(Ctl)));
+  WCHK(hipEventCreate(&w->ev0));
+  WCHK(hipEventCreate(&w->ev1));
   return wide_reserve(w, 4ull * d);
+}
+
+void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms) {
+  *launches = w->merge_launches;
+  *bytes = w->merge_bytes;
+  *ms = w->merge_ms;
 }
 
 void wide_destroy(WideScratch* w) {
@@ -1186,6 +1156,8 @@ void wide_destroy(WideScratch* w) {
   if (w->cand_v) (void)hipFree(w->cand_v);
   if (w->tmp_k) (void)hipFree(w->tmp_k);
   if (w->tmp_v) (void)hipFree(w->tmp_v);
+  if (w->ev0) (void)hipEventDestroy(w->ev0);
+  if (w->ev1) (void)hipEventDestroy(w->ev1);
   delete w;
 }
 
