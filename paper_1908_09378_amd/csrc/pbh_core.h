@@ -1092,10 +1092,26 @@ PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
     t.sh->mlp_h[j] = gelu(a);
   }
   t.sync();
-  for (int j = t.tid(); j < MLP_H; j += T::kNT) {
-    float a = b2[j];
-    for (int i = 0; i < MLP_H; ++i) a += bf16r(W2[i * MLP_H + j]) * t.sh->mlp_h[i];
-    t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
+  if constexpr (T::kNT >= 256) {
+    // four threads per hidden unit, each summing a quarter of the inputs
+    const int j = t.tid() & (MLP_H - 1), qtr = t.tid() >> 6;
+    if (t.tid() < 4 * MLP_H) {
+      float a = 0.0f;
+      for (int i = qtr * (MLP_H / 4); i < (qtr + 1) * (MLP_H / 4); ++i) a += bf16r(W2[i * MLP_H + j]) * t.sh->mlp_h[i];
+      t.sh->mlp_p[t.tid()] = a;
+    }
+    t.sync();
+    if (t.tid() < MLP_H) {
+      float a = b2[j];
+      for (int q = 0; q < 4; ++q) a += t.sh->mlp_p[q * MLP_H + j];
+      t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
+    }
+  } else {
+    for (int j = t.tid(); j < MLP_H; j += T::kNT) {
+      float a = b2[j];
+      for (int i = 0; i < MLP_H; ++i) a += bf16r(W2[i * MLP_H + j]) * t.sh->mlp_h[i];
+      t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
+    }
   }
   t.sync();
   float y = b3[0];
@@ -1263,7 +1279,7 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
   u32 nu = 0;
   // RE edges per thread per pass: their CSR loads and atomics are all in
   // flight before any result is waited for; one scan places the improvements.
-  constexpr int RE = 4;
+  constexpr int RE = 8;
   for (u32 eb = 0; eb < E; eb += (u32)T::kNT * RE) {
     u64 ei[RE], cand[RE];
     u32 v[RE];

@@ -38,6 +38,7 @@ struct TeamShared {
   u32 exd[257];  // prefix sums of their out-degrees
   float mlp_h[64];
   float mlp_z[64];
+  float mlp_p[NW >= 4 ? 256 : 1];  // partial sums of the second layer (teams of >= 256)
 };
 
 // DPP lane moves (gfx9 encodings): row_shr:n = 0x110 + n within rows of 16

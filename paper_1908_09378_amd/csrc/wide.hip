@@ -225,8 +225,17 @@ __device__ __forceinline__ u32 upper_id(const u32* v, u32 n, u32 x) {
 // toff[t] + its position - the drops before it (the tile's output range is
 // contiguous, so the L2 gathers the writes into full lines).  With `stats`
 // the writing pass also counts outputs <= (pk, pv) and the key range.
+// Per-workgroup partial results (a count and a key range), reduced by
+// k_reduce: thousands of workgroups updating the same word with atomics would
+// serialise in the L2.
+struct Partials {
+  u32* cnt;
+  u64* lo;
+  u64* hi;
+};
+
 template <bool WRITE>
-__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Ctl* ctl,
+__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Partials pt,
                                               int stats) {
   __shared__ u32 sv[TILE];
   __shared__ u32 sdrop[TILE / 32];  // bit p: merge position p of the tile is dropped
@@ -327,12 +336,35 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
       nle = block_sum<NT>(nle, sw);
       block_minmax<NT>(lo, hi, swl, swh);
       if (threadIdx.x == 0) {
-        if (nle) atomic_add32(&ctl->num_le, nle);
-        if (lo <= hi) {
-          atomic_min64(&ctl->kmin, lo);
-          atomic_max64(&ctl->kmax, hi);
-        }
+        pt.cnt[t] = nle;
+        pt.lo[t] = lo;
+        pt.hi[t] = hi;
       }
+    }
+  }
+}
+
+// Sums n partial counts into *sum (when sum != null) and folds the partial
+// key ranges into ctl->kmin / kmax.  One workgroup.
+__global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32, u64* sum64, Ctl* c) {
+  __shared__ u32 sw[16];
+  __shared__ u64 swl[16], swh[16];
+  u64 tot = 0, lo = KINF, hi = 0;
+  for (u32 x = threadIdx.x; x < n; x += 1024) {
+    tot += pt.cnt[x];
+    if (pt.lo) {
+      lo = pt.lo[x] < lo ? pt.lo[x] : lo;
+      hi = pt.hi[x] > hi ? pt.hi[x] : hi;
+    }
+  }
+  const u32 s = block_sum<1024>((u32)tot, sw);
+  block_minmax<1024>(lo, hi, swl, swh);
+  if (threadIdx.x == 0) {
+    if (sum32) *sum32 = s;
+    if (sum64) *sum64 = s;
+    if (pt.lo) {
+      c->kmin = lo;
+      c->kmax = hi;
     }
   }
 }
@@ -632,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const 
   }
 }
 
-__global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Ctl* c) {
+__global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Partials pt) {
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   u64 lo = KINF, hi = 0;
   const u64 step = (u64)gridDim.x * NT;
@@ -648,16 +680,17 @@ __global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Ctl* c) {
       }
   }
   block_minmax<NT>(lo, hi, swl, swh);
-  if (threadIdx.x == 0 && lo <= hi) {
-    atomic_min64(&c->kmin, lo);
-    atomic_max64(&c->kmax, hi);
+  if (threadIdx.x == 0) {
+    pt.cnt[blockIdx.x] = 0;
+    pt.lo[blockIdx.x] = lo;
+    pt.hi[blockIdx.x] = hi;
   }
 }
 
 // ------------------------------------------------------------------ intake
 
 __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, u64 count, u64* cur, u32* bitmap,
-                                               Ctl* c) {
+                                               Partials pt) {
   __shared__ u32 sw[NT / 64];
   u32 newly = 0;
   const u64 step = (u64)gridDim.x * NT;
@@ -681,7 +714,7 @@ __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, 
       }
   }
   newly = block_sum<NT>(newly, sw);
-  if (threadIdx.x == 0 && newly) atomic_add64(&c->newly, newly);
+  if (threadIdx.x == 0) pt.cnt[blockIdx.x] = newly;
 }
 
 // Bitmap compaction: set bits in increasing id order -> (cur[id], id); the
@@ -868,6 +901,7 @@ struct WideScratch {
   u32* cand_v = nullptr;
   u64* tmp_k = nullptr;  // sort scratch (4d elements)
   u32* tmp_v = nullptr;
+  Partials pt{nullptr, nullptr, nullptr};  // one slot per tile / workgroup (maxtiles, >= GRID_STRIDE)
   u32 maxtiles = 0;
   hipStream_t s = 0;
   // HIP-event timing of the merge writing pass (the engine's largest kernel)
@@ -905,13 +939,15 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
   hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
-  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->ctl,
+  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
                      0);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
   WCHK(hipEventRecord(w->ev0, w->s));
-  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->ctl,
+  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->pt,
                      stats ? 1 : 0);
   WCHK(hipEventRecord(w->ev1, w->s));
+  if (stats)
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->ctl->num_le, (u64*)nullptr, w->ctl);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->hctl->total;
@@ -928,8 +964,9 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
 // (from the merge that wrote A) unless have_range is false.
 int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
   if (!have_range) {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
-    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n)), dim3(NT), 0, w->s, A.k, n, w->ctl);
+    const u32 gm = grid_for(n);
+    hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
   }
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(NT), 0, w->s, w->ctl, r, n);
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
@@ -1108,16 +1145,24 @@ int grow_if_needed(WideScratch* w, WideHeap* h) {
 }  // namespace
 
 int wide_reserve(WideScratch* w, u64 elems) {
-  const u64 need = (elems + TILE - 1) / TILE + 2;
+  u64 need = (elems + TILE - 1) / TILE + 2;
+  if (need < (u64)GRID_STRIDE) need = GRID_STRIDE;
   if (need <= w->maxtiles) return 0;
   if (w->part) (void)hipFree(w->part);
   if (w->tc) (void)hipFree(w->tc);
   if (w->toff) (void)hipFree(w->toff);
+  if (w->pt.cnt) (void)hipFree(w->pt.cnt);
+  if (w->pt.lo) (void)hipFree(w->pt.lo);
+  if (w->pt.hi) (void)hipFree(w->pt.hi);
   w->part = w->tc = w->toff = nullptr;
+  w->pt = Partials{nullptr, nullptr, nullptr};
   w->maxtiles = 0;
   WCHK(hipMalloc(&w->part, (need + 1) * sizeof(u32)));
   WCHK(hipMalloc(&w->tc, 3 * need * sizeof(u32)));
   WCHK(hipMalloc(&w->toff, 3 * need * sizeof(u32)));
+  WCHK(hipMalloc(&w->pt.cnt, need * sizeof(u32)));
+  WCHK(hipMalloc(&w->pt.lo, need * sizeof(u64)));
+  WCHK(hipMalloc(&w->pt.hi, need * sizeof(u64)));
   w->maxtiles = (u32)need;
   return 0;
 }
@@ -1152,6 +1197,9 @@ void wide_destroy(WideScratch* w) {
   if (w->part) (void)hipFree(w->part);
   if (w->tc) (void)hipFree(w->tc);
   if (w->toff) (void)hipFree(w->toff);
+  if (w->pt.cnt) (void)hipFree(w->pt.cnt);
+  if (w->pt.lo) (void)hipFree(w->pt.lo);
+  if (w->pt.hi) (void)hipFree(w->pt.hi);
   if (w->cand_k) (void)hipFree(w->cand_k);
   if (w->cand_v) (void)hipFree(w->cand_v);
   if (w->tmp_k) (void)hipFree(w->tmp_k);
@@ -1168,9 +1216,10 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
   HeapState* st = h->st;
   if (count == 0) return 0;
   if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
-  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
-  hipLaunchKernelGGL(k_intake, dim3(grid_for(count)), dim3(NT), 0, w->s, keys, ids, count, h->cur, h->bitmap,
-                     w->ctl);
+  const u32 gi = grid_for(count);
+  hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, h->bitmap, w->pt);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
+                     (u32*)nullptr, &w->ctl->newly, w->ctl);
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, w->tc, (const u32*)nullptr,
