@@ -254,12 +254,13 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
 
 /*
  * sssp_autotune: picks opts->d and opts->k_max for this query by timing trial
- * runs on the query itself.  A plain trial of a few rounds finds a distance
+ * runs on the query itself.  A plain trial of n/32 rounds finds a distance
  * frontier D (the smallest key left after them); then each candidate
  * (d = max out-degree * 1, 2, 4, ... up to 2048; team 64 or 256 threads for
  * d in [64, 2048] unless opts->team fixes it; k_max 64 or 256 when
  * k_rule != 0) runs until every vertex closer than D is settled, which is the
- * same work for every candidate, and the fastest is written back into *opts
+ * same work for every candidate; the three fastest run again to the frontier
+ * of n/8 plain rounds, and the fastest there is written back into *opts
  * (d, team, k_max; the other fields are kept and used for the trials).
  * dist_out is used as scratch.  Errors: those of sssp_ex.
  */

@@ -803,9 +803,16 @@ int sssp(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weigh
 namespace {
 
 // Frontier trials on one query: a plain run of a few rounds gives the
-// distance frontier D; every candidate (d = maxdeg * mult, k_max) then runs
-// until all vertices closer than D are settled -- the same work for each --
-// and the fastest wins.  Returns the winning multiple and k_max.
+// distance frontier D; every candidate (d = maxdeg * mult, team, k_max) then
+// runs until all vertices closer than D are settled -- the same work for
+// each -- and is timed.  The three fastest are timed again on a frontier four
+// times deeper (the heap and the frontier grow during a run, so the early
+// ranking can mislead), and the fastest there wins.
+struct TuneCand {
+  u32 d, team, kmax;
+  double ms;
+};
+
 int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
                uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream, u32* mult_out,
                u32* kmax_out, u32* maxdeg_out, u32* team_out) {
@@ -815,58 +822,63 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
   base.trace_features = nullptr;
   base.d = 0;
   base.d_scale = 0;
-  sssp_opts t0 = base;
-  t0.k_rule = 0;
-  t0.max_rounds = std::min<u32>(65536u, std::max<u32>(256u, n / 32));
-  sssp_stats s0;
-  int rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t0, &s0, stream);
-  if (rc) return rc;
-  const u32 maxdeg = s0.d;
-  const u64 D = s0.last_key;  // UINT64_MAX: the whole run fits in the trial; candidates run to the end
+  // frontiers: after n/32 and n/8 plain rounds
+  u64 D[2] = {KINF, KINF};
+  u32 maxdeg = 1;
+  const u32 rounds[2] = {std::min<u32>(65536u, std::max<u32>(256u, n / 32)),
+                         std::min<u32>(262144u, std::max<u32>(1024u, n / 8))};
+  for (int s = 0; s < 2; ++s) {
+    sssp_opts t0 = base;
+    t0.k_rule = 0;
+    t0.max_rounds = rounds[s];
+    sssp_stats s0;
+    int rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t0, &s0, stream);
+    if (rc) return rc;
+    maxdeg = s0.d;
+    D[s] = s0.last_key;  // UINT64_MAX: the whole run fits; candidates run to the end
+  }
   const bool spec = user.k_rule != 0;
   const u32 kms[2] = {64, 256};
-  double best = 1e300;
-  u32 bm = 1, bk = user.k_max, bt = user.team;
+  std::vector<TuneCand> cands;
   for (u32 mult = 1; (u64)maxdeg * mult <= 2048 || mult == 1; mult *= 2) {
     const u32 d = maxdeg * mult;
-    // team sizes worth trying at this d (a caller's fixed team is kept)
-    u32 teams[2] = {0, 0};
-    int nt = 1;
-    if (user.team) {
-      teams[0] = user.team;
-    } else if (d < 64) {
-      teams[0] = 64;
-    } else if (d <= 2048) {
-      teams[0] = 64;
-      teams[1] = 256;
-      nt = 2;
-    } else {
-      teams[0] = 1024;
-    }
-    for (int ti = 0; ti < nt; ++ti)
-      for (int ki = 0; ki < (spec ? 2 : 1); ++ki) {
-        sssp_opts t = base;
-        t.d = d;
-        t.team = teams[ti];
-        if (spec) t.k_max = kms[ki];
-        t.stop_key = D == KINF ? 0 : D;
-        sssp_stats st;
-        rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
-        if (rc == PBH_EINVAL) continue;  // e.g. the LDS levels do not fit with this team
-        if (rc) return rc;
-        if (st.kernel_ms < best) {
-          best = st.kernel_ms;
-          bm = mult;
-          bt = teams[ti];
-          bk = spec ? kms[ki] : user.k_max;
-        }
-      }
+    std::vector<u32> teams;
+    if (user.team)
+      teams = {user.team};
+    else if (d < 64)
+      teams = {64};
+    else if (d <= 2048)
+      teams = {64, 256};
+    else
+      teams = {1024};
+    for (u32 tm : teams)
+      for (int ki = 0; ki < (spec ? 2 : 1); ++ki) cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0});
   }
-  if (best == 1e300) return fail(PBH_EINTERNAL, "sssp_autotune: every candidate failed");
-  *mult_out = bm;
-  *kmax_out = bk;
+  auto trial = [&](TuneCand& c, u64 stop) -> int {
+    sssp_opts t = base;
+    t.d = c.d;
+    t.team = c.team;
+    t.k_max = c.kmax;
+    t.stop_key = stop == KINF ? 0 : stop;
+    sssp_stats st;
+    int rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
+    c.ms = rc ? 1e300 : st.kernel_ms;
+    return rc == PBH_EINVAL ? 0 : rc;  // a candidate whose LDS levels do not fit is skipped
+  };
+  for (TuneCand& c : cands)
+    if (int rc = trial(c, D[0])) return rc;
+  std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
+  if (cands.empty() || cands[0].ms >= 1e300) return fail(PBH_EINTERNAL, "sssp_autotune: every candidate failed");
+  if (cands.size() > 3) cands.resize(3);
+  if (D[0] != KINF) {
+    for (TuneCand& c : cands)
+      if (int rc = trial(c, D[1])) return rc;
+    std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
+  }
+  *mult_out = cands[0].d / maxdeg;
+  *kmax_out = cands[0].kmax;
   *maxdeg_out = maxdeg;
-  *team_out = bt;
+  *team_out = cands[0].team;
   return PBH_OK;
 }
 
