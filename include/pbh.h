@@ -168,7 +168,7 @@ typedef struct {
                              2 = learned: the MLP in k_model chooses k each round;
                              3 = k_seq[round % k_seq_len] */
   uint32_t k_fixed;
-  uint32_t k_max;         /* cap on k (0 = 2d; never above 256) */
+  uint32_t k_max;         /* cap on k (0 = 2d; never above 256); 1 makes every rule the plain one */
   uint32_t k_seq_len;
   const uint32_t *k_seq;  /* device array (rule 3) */
   const float *k_model;   /* device array of PBH_MLP_BLOB floats (rule 2): W1[8][64], b1[64],
@@ -257,8 +257,9 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
  * runs on the query itself.  A plain trial of n/32 rounds finds a distance
  * frontier D (the smallest key left after them); then each candidate
  * (d = max out-degree * 1, 2, 4, ... up to 2048; team 64 or 256 threads for
- * d in [64, 2048] unless opts->team fixes it; k_max 64 or 256 when
- * k_rule != 0) runs until every vertex closer than D is settled, which is the
+ * d in [64, 2048] unless opts->team fixes it; k_max 1 (the plain rule), 64
+ * or 256 when k_rule != 0) runs until every vertex closer than D is settled,
+ * which is the
  * same work for every candidate; the three fastest run again to the frontier
  * of n/8 plain rounds, and the fastest there is written back into *opts
  * (d, team, k_max; the other fields are kept and used for the trials).

@@ -190,7 +190,8 @@ int spec_from_opts(const sssp_opts& o, u32 d, SpecCfg* sc, u32* kmax_out) {
   u32 kmax = o.k_max ? o.k_max : 2 * d;
   if (kmax > (u32)KMAX_ROUND) kmax = KMAX_ROUND;
   if (kmax < 1) kmax = 1;
-  sc->rule = (int)o.k_rule;
+  // k capped at 1 is the plain rule; its round path is the cheaper one
+  sc->rule = kmax == 1 ? 0 : (int)o.k_rule;
   sc->kfix = o.k_fixed ? o.k_fixed : 1;
   sc->kmax = kmax;
   if (o.k_rule == 2 && !o.k_model) return fail(PBH_EINVAL, "sssp: k_rule 2 needs k_model");
@@ -838,7 +839,7 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
     D[s] = s0.last_key;  // UINT64_MAX: the whole run fits; candidates run to the end
   }
   const bool spec = user.k_rule != 0;
-  const u32 kms[2] = {64, 256};
+  const u32 kms[3] = {1, 64, 256};  // k_max 1 = the plain rule, for graphs where pulling ahead does not pay
   std::vector<TuneCand> cands;
   for (u32 mult = 1; (u64)maxdeg * mult <= 2048 || mult == 1; mult *= 2) {
     const u32 d = maxdeg * mult;
@@ -852,7 +853,7 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
     else
       teams = {1024};
     for (u32 tm : teams)
-      for (int ki = 0; ki < (spec ? 2 : 1); ++ki) cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0});
+      for (int ki = 0; ki < (spec ? 3 : 1); ++ki) cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0});
   }
   auto trial = [&](TuneCand& c, u64 stop) -> int {
     sssp_opts t = base;
