@@ -304,6 +304,16 @@ int mlp_grad(const float *X, const float *Y, uint32_t n, const float *blob, floa
 int mlp_train(const float *X, const float *Y, uint32_t n, float *blob, uint32_t batch, uint32_t steps, float lr,
               float *loss_trace);
 
+/*
+ * mlp_infer: the round loop's own inference of the model on n given feature
+ * rows (device X[8n], blob as k_model, y[n] out): y[r] = scale * (network
+ * output), i.e. k = 2^y before clamping.  team 64 or 256 selects the code
+ * path the round loop uses with that team size (the wider one splits the
+ * second layer over four threads per unit).  Errors: PBH_EINVAL (NULL
+ * arrays, team not 64/256), PBH_EDEVICE.
+ */
+int mlp_infer(const float *X, uint32_t n, const float *blob, uint32_t team, float *y);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char *pbh_last_error(void);
 

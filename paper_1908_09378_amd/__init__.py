@@ -62,7 +62,7 @@ class SsspQuery(C.Structure):
 _lib = None
 EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
-           "mlp_grad", "mlp_train", "pbh_last_error"]
+           "mlp_grad", "mlp_train", "mlp_infer", "pbh_last_error"]
 
 
 def lib():
@@ -91,6 +91,7 @@ def lib():
         L.mlp_feature_stats.argtypes = [vp, u32, vp]
         L.mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
         L.mlp_train.argtypes = [vp, vp, u32, vp, u32, u32, C.c_float, C.POINTER(C.c_float)]
+        L.mlp_infer.argtypes = [vp, u32, vp, u32, vp]
         L.pbh_last_error.restype = C.c_char_p
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = C.c_int
@@ -289,6 +290,12 @@ def mlp_trace_labels(trace_keys, trace_ids, trace_query, count: int, dists, labe
 
 def mlp_feature_stats(X, blob) -> None:
     _check(lib().mlp_feature_stats(_ptr(X, 4), X.shape[0], _ptr(blob, 4)))
+
+
+def mlp_infer(X, blob, y, team: int = 256) -> None:
+    """The round loop's inference on rows of X (n x 8 float32, device):
+    y[r] = scale * network output (k = 2^y before clamping)."""
+    _check(lib().mlp_infer(_ptr(X, 4), X.shape[0], _ptr(blob, 4), team, _ptr(y, 4)))
 
 
 def mlp_grad(X, Y, blob, grad, loss) -> None:

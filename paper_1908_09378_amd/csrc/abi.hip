@@ -364,6 +364,15 @@ int pbh_extract_min(pbh_t* h, uint64_t k, uint64_t* keys_out, uint32_t* ids_out,
   return PBH_OK;
 }
 
+int mlp_infer(const float* X, uint32_t n, const float* blob, uint32_t team, float* y) {
+  if (n == 0) return PBH_OK;
+  if (!X || !blob || !y) return fail(PBH_EINVAL, "mlp_infer: NULL array");
+  if (team != 64 && team != 256) return fail(PBH_EINVAL, "mlp_infer: team must be 64 or 256");
+  HIPCHK(launch_mlp_infer((int)team, X, n, blob, y, 0));
+  HIPCHK(hipDeviceSynchronize());
+  return PBH_OK;
+}
+
 int pbh_merge_profile(pbh_t* h, uint64_t* launches, uint64_t* bytes, double* ms) {
   if (!h || !launches || !bytes || !ms) return fail(PBH_EINVAL, "pbh_merge_profile: NULL argument");
   u64 l = 0, b = 0;

@@ -246,6 +246,30 @@ hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStrea
   }
 }
 
+// The round loop's MLP inference (mlp_forward) on given feature rows, one
+// team per row: y[r] = the model output for features X[8r .. 8r+7].
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mlp_infer(const float* X, u32 n, const float* blob, float* y) {
+  __shared__ TeamShared<NT / 64> ts;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  const u32 r = blockIdx.x;
+  if (r >= n) return;
+  float f[NFEAT];
+#pragma unroll
+  for (int i = 0; i < NFEAT; ++i) f[i] = X[(u64)r * NFEAT + i];
+  const float v = mlp_forward(t, blob, f);
+  if (threadIdx.x == 0) y[r] = v;
+}
+
+hipError_t launch_mlp_infer(int team, const float* X, u32 n, const float* blob, float* y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (team == 64)
+    hipLaunchKernelGGL(k_mlp_infer<64>, dim3(n), dim3(64), 0, s, X, n, blob, y);
+  else
+    hipLaunchKernelGGL(k_mlp_infer<256>, dim3(n), dim3(256), 0, s, X, n, blob, y);
+  return hipGetLastError();
+}
+
 hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_pbh_update<1024>, dim3(1), dim3(1024), 0, s, p);
   return hipGetLastError();

@@ -1068,8 +1068,9 @@ PBH_INL float bf16r(float x) {
 
 PBH_INL float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 
-// MLP 8 -> 64 -> 64 -> 1 with GELU (exact, x * Phi(x)); thread j computes
-// hidden unit j of each layer (weights stored input-major, so the loads of
+// MLP 8 -> 64 -> 64 -> 1 with GELU (exact, x * Phi(x)); every parameter is
+// used rounded to bfloat16, as in training; thread j computes hidden unit j of
+// each layer (weights stored input-major, so the loads of
 // one input row are contiguous), the output is reduced through LDS.  BF16
 // weights, FP32 accumulation.  Returns y (k = 2^(s * y)).
 template <class T>
@@ -1086,7 +1087,7 @@ PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
 #pragma unroll
   for (int i = 0; i < NFEAT; ++i) x[i] = (f[i] - mu[i]) / sd[i];
   for (int j = t.tid(); j < MLP_H; j += T::kNT) {
-    float a = b1[j];
+    float a = bf16r(b1[j]);
 #pragma unroll
     for (int i = 0; i < NFEAT; ++i) a += bf16r(W1[i * MLP_H + j]) * x[i];
     t.sh->mlp_h[j] = gelu(a);
@@ -1102,19 +1103,19 @@ PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
     }
     t.sync();
     if (t.tid() < MLP_H) {
-      float a = b2[j];
+      float a = bf16r(b2[j]);
       for (int q = 0; q < 4; ++q) a += t.sh->mlp_p[q * MLP_H + j];
       t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
     }
   } else {
     for (int j = t.tid(); j < MLP_H; j += T::kNT) {
-      float a = b2[j];
+      float a = bf16r(b2[j]);
       for (int i = 0; i < MLP_H; ++i) a += bf16r(W2[i * MLP_H + j]) * t.sh->mlp_h[i];
       t.sh->mlp_z[j] = bf16r(w3[j]) * gelu(a);
     }
   }
   t.sync();
-  float y = b3[0];
+  float y = bf16r(b3[0]);
   for (int j = 0; j < MLP_H; ++j) y += t.sh->mlp_z[j];
   t.sync();
   return y * sd[NFEAT];

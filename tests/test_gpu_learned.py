@@ -133,3 +133,18 @@ def test_trained_model_beats_plain():
           f"{st1['extracted']} extracted {st1['kernel_ms']:.1f} ms", flush=True)
     assert st1["rounds"] < 0.5 * st0["rounds"]
     assert st1["kernel_ms"] < st0["kernel_ms"]
+
+
+@pytest.mark.parametrize("team", [64, 256])
+def test_inference_matches_fp64_oracle(team):
+    """The round loop's own MLP inference (both code paths) against the FP64
+    model oracle on the bfloat16-rounded parameters; FP32 accumulation."""
+    rng = np.random.default_rng(11 + team)
+    b = _blob(5, scale=0.5)
+    b[-1] = 1.7  # output scale s (k = 2^(s * y))
+    X = (rng.normal(size=(200, 8)) * 2 + 1).astype(np.float32)
+    y = torch.zeros(200, dtype=torch.float32, device=DEV)
+    pkg.mlp_infer(torch.from_numpy(X).to(DEV), torch.from_numpy(b).to(DEV), y, team=team)
+    ref = mlp.forward(mlp.rounded(b), X.astype(np.float64)) * float(b[-1])
+    got = y.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * max(1.0, float(np.max(np.abs(ref))))
