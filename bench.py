@@ -100,7 +100,8 @@ def run_multi(args):
     tuned = pkg.sssp_batch_autotune(qs, k_rule=2, k_model=blob)
     tuned["tune_s"] = time.perf_counter() - t0
     print(f"[bench] batch autotune: {tuned}", file=sys.stderr, flush=True)
-    lr = timed(k_rule=2, k_model=blob, d_scale=tuned["d_scale"], k_max=tuned["k_max"], team=tuned["team"])
+    lr = timed(k_rule=2, k_model=blob, d_scale=tuned["d_scale"], k_max=tuned["k_max"], team=tuned["team"],
+               k_scale=tuned["k_scale"])
     pr = timed()
     line = {
         "metric": METRIC, "value": lr["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -355,9 +356,10 @@ def main():
         blob = torch.from_numpy(learn.load_model()).to(dev)
         t = tune(k_rule=2, k_model=blob)
         r = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"],
-                          team=t["team"]),
+                          team=t["team"], k_scale=t["k_scale"]),
                    "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) picks how many "
-                   "minima each round extracts, improved vertices are re-inserted; d and k_max autotuned")
+                   "minima each round extracts, improved vertices are re-inserted; d, team, k_max and k_scale "
+                   "autotuned")
         r["autotune"] = t
         runs["learned"] = r
     if args.method in ("both", "plain"):

@@ -44,7 +44,7 @@ class SsspOpts(C.Structure):
                 ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
                 ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
-                ("d_scale", C.c_uint32)]
+                ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("reserved", C.c_uint32)]
 
 
 class SsspStats(C.Structure):
@@ -129,8 +129,9 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
-          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0):
+          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0):
     o = SsspOpts()
+    o.k_scale = k_scale
     o.d, o.team, o.schedule, o.lds_levels, o.heap_capacity = d, team, schedule, lds_levels, heap_capacity
     o.k_rule, o.k_fixed, o.k_max = k_rule, k_fixed, k_max
     o.stop_key, o.max_rounds, o.d_scale = stop_key, max_rounds, d_scale
@@ -162,7 +163,7 @@ def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *,
 
 
 def _tuned(o) -> dict:
-    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max, team=o.team)
+    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max, team=o.team, k_scale=o.k_scale)
 
 
 def sssp_autotune(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:

@@ -201,6 +201,8 @@ int spec_from_opts(const sssp_opts& o, u32 d, SpecCfg* sc, u32* kmax_out) {
   sc->model = o.k_model;
   sc->stop_key = o.stop_key;
   sc->max_rounds = o.max_rounds;
+  sc->kscale = o.k_scale > 0.0f ? o.k_scale : 1.0f;
+  if (o.reserved) return fail(PBH_EINVAL, "sssp: opts.reserved must be zero");
   *kmax_out = kmax;
   return PBH_OK;
 }
@@ -821,11 +823,12 @@ namespace {
 struct TuneCand {
   u32 d, team, kmax;
   double ms;
+  float scale = 0.0f;  // k_scale of the trial (0: the caller's)
 };
 
 int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
                uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream, u32* mult_out,
-               u32* kmax_out, u32* maxdeg_out, u32* team_out) {
+               u32* kmax_out, u32* maxdeg_out, u32* team_out, float* scale_out) {
   sssp_opts base = user;
   base.stop_key = 0;
   base.max_rounds = 0;
@@ -862,7 +865,8 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
     else
       teams = {1024};
     for (u32 tm : teams)
-      for (int ki = 0; ki < (spec ? 3 : 1); ++ki) cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0});
+      for (int ki = 0; ki < (spec ? 3 : 1); ++ki)
+        cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0, 0.0f});
   }
   auto trial = [&](TuneCand& c, u64 stop) -> int {
     sssp_opts t = base;
@@ -885,10 +889,29 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
       if (int rc = trial(c, D[1])) return rc;
     std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
   }
+  // the learned rule's output scale, on the winner with k up to 256
+  float bscale = user.k_scale > 0.0f ? user.k_scale : 1.0f;
+  if (user.k_rule == 2 && cands[0].kmax > 1) {
+    TuneCand best = cands[0];
+    const u64 stop = D[0] != KINF ? D[1] : KINF;
+    for (float f : {1.5f, 2.0f}) {
+      TuneCand c = best;
+      c.kmax = 256;
+      base.k_scale = bscale * f;
+      if (int rc = trial(c, stop)) return rc;
+      if (c.ms < best.ms) {
+        best = c;
+        best.scale = base.k_scale;
+      }
+    }
+    base.k_scale = user.k_scale;
+    cands[0] = best;
+  }
   *mult_out = cands[0].d / maxdeg;
   *kmax_out = cands[0].kmax;
   *maxdeg_out = maxdeg;
   *team_out = cands[0].team;
+  *scale_out = cands[0].scale > 0.0f ? cands[0].scale : bscale;
   return PBH_OK;
 }
 
@@ -900,13 +923,15 @@ int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32
                   uint64_t m, uint32_t source, uint64_t* dist_out, sssp_opts* opts, void* stream) {
   if (!opts) return fail(PBH_EINVAL, "sssp_autotune: opts is NULL");
   u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
-  int rc =
-      tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg, &team);
+  float scale = 1.0f;
+  int rc = tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg, &team,
+                      &scale);
   if (rc) return rc;
   opts->d = maxdeg * mult;
   opts->d_scale = 0;
   opts->k_max = kmax;
   opts->team = team;
+  opts->k_scale = scale;
   return PBH_OK;
 }
 
@@ -923,13 +948,15 @@ int sssp_batch_autotune(const sssp_query* queries, uint32_t nq, sssp_opts* opts,
   if (!q.offsets || !q.dist_out || (q.m > 0 && (!q.targets || !q.weights)) || q.n == 0 || q.source >= q.n)
     return fail(PBH_EINVAL, "sssp_batch_autotune: query %u is malformed", big);
   u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
+  float scale = 1.0f;
   int rc = tune_query(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, *opts, stream, &mult, &kmax,
-                      &maxdeg, &team);
+                      &maxdeg, &team, &scale);
   if (rc) return rc;
   opts->d = 0;
   opts->d_scale = mult;
   opts->k_max = kmax;
   opts->team = team;
+  opts->k_scale = scale;
   return PBH_OK;
 }
 

@@ -1000,6 +1000,7 @@ struct SpecCfg {
   // stop_key (0 = none) or after max_rounds rounds (0 = none)
   u64 stop_key;
   u32 max_rounds;
+  float kscale;  // learned rule: multiplies log2 k
 };
 
 struct SsspCounters {
@@ -1132,7 +1133,7 @@ PBH_INL u32 propose_k(const T& t, const Geom& g, SP st, const SpecCfg& sc, A0 B,
   } else if (sc.rule == 2) {
     float f[NFEAT];
     round_features(t, g, st, B, nB, memo, f);
-    float y = mlp_forward(t, sc.model, f);
+    float y = mlp_forward(t, sc.model, f) * sc.kscale;
     // fall back to the plain rule on anything that is not a finite number
     if (y == y && y > -64.0f && y < 64.0f) {
       float kk = __builtin_exp2f(y);

@@ -244,6 +244,7 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   sc.kseq = kseq;
   sc.kseq_len = kseq_len;
   sc.model = model;
+  sc.kscale = 1.0f;
   sc.stop_key = stop_key;
   sc.max_rounds = max_rounds;
   std::vector<u64> uk(2ull * sc.kmax * d);
