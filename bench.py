@@ -358,8 +358,7 @@ def main():
         r = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"],
                           team=t["team"], k_scale=t["k_scale"]),
                    "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) picks how many "
-                   "minima each round extracts, improved vertices are re-inserted; d, team, k_max and k_scale "
-                   "autotuned")
+                   "minima each round extracts, improved vertices are re-inserted; d, team and k_max autotuned")
         r["autotune"] = t
         runs["learned"] = r
     if args.method in ("both", "plain"):

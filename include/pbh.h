@@ -264,8 +264,8 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
  * which is the
  * same work for every candidate; the three fastest run again to the frontier
  * of n/8 plain rounds, and the fastest there is written back into *opts
- * (d, team, k_max; with the learned rule also k_scale, tried at 1, 1.5 and 2
- * on the winner; the other fields are kept and used for the trials).
+ * (d, team, k_max; the other fields, k_scale included, are kept and used
+ * for the trials).
  * dist_out is used as scratch.  Errors: those of sssp_ex.
  */
 int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,

@@ -889,24 +889,7 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
       if (int rc = trial(c, D[1])) return rc;
     std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
   }
-  // the learned rule's output scale, on the winner with k up to 256
-  float bscale = user.k_scale > 0.0f ? user.k_scale : 1.0f;
-  if (user.k_rule == 2 && cands[0].kmax > 1) {
-    TuneCand best = cands[0];
-    const u64 stop = D[0] != KINF ? D[1] : KINF;
-    for (float f : {1.5f, 2.0f}) {
-      TuneCand c = best;
-      c.kmax = 256;
-      base.k_scale = bscale * f;
-      if (int rc = trial(c, stop)) return rc;
-      if (c.ms < best.ms) {
-        best = c;
-        best.scale = base.k_scale;
-      }
-    }
-    base.k_scale = user.k_scale;
-    cands[0] = best;
-  }
+  const float bscale = user.k_scale > 0.0f ? user.k_scale : 1.0f;
   *mult_out = cands[0].d / maxdeg;
   *kmax_out = cands[0].kmax;
   *maxdeg_out = maxdeg;
