@@ -65,6 +65,19 @@ struct Ctl {
 };
 constexpr size_t CTL_HEAD = offsetof(Ctl, shist);
 
+// What the host reads after a step, written by the step's last kernel into
+// host-mapped coherent memory (a readback is then only a stream sync).
+struct Mail {
+  u32 total;    // output size of a merge or of the bitmap compaction
+  u32 num_le;   // merge outputs <= the counting pivot
+  u32 part[4];  // three-way split sizes
+  u64 newly;    // ids inserted by the intake
+  u64 rk;       // selected element
+  u32 rv;
+  int sfail;    // the selection needs more passes
+  int sbad;     // the selection found no element of the rank (never expected)
+};
+
 __device__ __forceinline__ u64 atomic_min64(u64* p, u64 v) {
   return __hip_atomic_fetch_min((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -640,10 +653,17 @@ __device__ void bitonic_lds(u64* k, u32* v) {
 
 // The remaining candidates (<= 256, distinct (key, id)) are ranked by
 // counting: the one with exactly rank-1 smaller candidates is the answer.
-__global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv) {
+// Publishes the outcome to the host mailbox.
+__global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv, Mail* mail) {
   __shared__ u64 sk[CANDMAX];
   __shared__ u32 sv[CANDMAX];
-  if (!c->sdone || c->sbad) return;
+  if (!c->sdone || c->sbad) {
+    if (threadIdx.x == 0) {
+      mail->sfail = !c->sdone;
+      mail->sbad = c->sbad;
+    }
+    return;
+  }
   const u32 n = c->sncand < CANDMAX ? c->sncand : CANDMAX;
   const u32 r = c->srank;
   if (threadIdx.x < n) {
@@ -651,15 +671,18 @@ __global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const 
     sv[threadIdx.x] = cv[threadIdx.x];
   }
   __syncthreads();
-  if (threadIdx.x == 0 && (r == 0 || r > n || c->sncand != c->scnt)) c->sbad = 1;
+  if (threadIdx.x == 0) {
+    mail->sfail = 0;
+    mail->sbad = (r == 0 || r > n || c->sncand != c->scnt) ? 1 : 0;
+  }
   if (threadIdx.x < n) {
     const u64 k = sk[threadIdx.x];
     const u32 v = sv[threadIdx.x];
     u32 below = 0;
     for (u32 y = 0; y < n; ++y) below += sk[y] < k || (sk[y] == k && sv[y] < v);
     if (below + 1 == r) {
-      c->rk = k;
-      c->rv = v;
+      mail->rk = k;
+      mail->rv = v;
     }
   }
 }
@@ -892,8 +915,9 @@ u32 grid_for(u64 n) {
 
 struct WideScratch {
   u32 d = 0;
-  Ctl* ctl = nullptr;   // device
-  Ctl* hctl = nullptr;  // pinned host copy of the header
+  Ctl* ctl = nullptr;      // device
+  Mail* mail_h = nullptr;  // host-mapped coherent mailbox (host view)
+  Mail* mail_d = nullptr;  // its device address
   u32* part = nullptr;  // tile split points (maxtiles + 1)
   u32* tc = nullptr;    // tile counts, 3 arrays of maxtiles
   u32* toff = nullptr;  // tile offsets, 3 arrays of maxtiles
@@ -917,8 +941,8 @@ namespace {
     if ((x) != hipSuccess) return E_DEVICE;   \
   } while (0)
 
+// Waits for the step; its results are then in the mailbox.
 int fetch(WideScratch* w) {
-  WCHK(hipMemcpyAsync(w->hctl, w->ctl, CTL_HEAD, hipMemcpyDeviceToHost, w->s));
   WCHK(hipStreamSynchronize(w->s));
   return 0;
 }
@@ -941,17 +965,17 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
   hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
                      0);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->mail_d->total);
   WCHK(hipEventRecord(w->ev0, w->s));
   hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->pt,
                      stats ? 1 : 0);
   WCHK(hipEventRecord(w->ev1, w->s));
   if (stats)
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->ctl->num_le, (u64*)nullptr, w->ctl);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->mail_d->num_le, (u64*)nullptr, w->ctl);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
-  *m = w->hctl->total;
-  *num_le = w->hctl->num_le;
+  *m = w->mail_h->total;
+  *num_le = stats ? w->mail_h->num_le : 0u;
   float ms = 0.f;
   WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   w->merge_ms += ms;
@@ -978,12 +1002,12 @@ int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
       hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(NT), 0, w->s, w->ctl);
     }
     hipLaunchKernelGGL(k_sel_collect, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v);
-    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v);
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v, w->mail_d);
     if (int rc = launch_ok()) return rc;
     if (int rc = fetch(w)) return rc;
-    if (w->hctl->sbad) return E_INTERNAL;
-    if (!w->hctl->sfail) {
-      *out = KV{w->hctl->rk, w->hctl->rv};
+    if (w->mail_h->sbad) return E_INTERNAL;
+    if (!w->mail_h->sfail) {
+      *out = KV{w->mail_h->rk, w->mail_h->rv};
       return 0;
     }
   }
@@ -1000,13 +1024,13 @@ int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr 
   if (nt > w->maxtiles) return E_INTERNAL;
   PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}};
   hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
-  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->ctl->part);
+  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->mail_d->part);
   hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
-  *n0 = w->hctl->part[0];
-  *n1 = w->hctl->part[1];
-  *n2 = w->hctl->part[2];
+  *n0 = w->mail_h->part[0];
+  *n1 = w->mail_h->part[1];
+  *n2 = w->mail_h->part[2];
   return 0;
 }
 
@@ -1172,7 +1196,9 @@ int wide_create(WideScratch** out, u32 d) {
   w->d = d;
   *out = w;
   WCHK(hipMalloc(&w->ctl, sizeof(Ctl)));
-  WCHK(hipHostMalloc(&w->hctl, sizeof(Ctl), hipHostMallocDefault));
+  WCHK(hipHostMalloc(&w->mail_h, sizeof(Mail), hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(w->mail_h, 0, sizeof(Mail));
+  WCHK(hipHostGetDevicePointer((void**)&w->mail_d, w->mail_h, 0));
   WCHK(hipMalloc(&w->cand_k, CANDMAX * sizeof(u64)));
   WCHK(hipMalloc(&w->cand_v, CANDMAX * sizeof(u32)));
   WCHK(hipMalloc(&w->tmp_k, 4ull * d * sizeof(u64)));
@@ -1193,7 +1219,7 @@ void wide_destroy(WideScratch* w) {
   if (!w) return;
   (void)hipDeviceSynchronize();
   if (w->ctl) (void)hipFree(w->ctl);
-  if (w->hctl) (void)hipHostFree(w->hctl);
+  if (w->mail_h) (void)hipHostFree(w->mail_h);
   if (w->part) (void)hipFree(w->part);
   if (w->tc) (void)hipFree(w->tc);
   if (w->toff) (void)hipFree(w->toff);
@@ -1215,28 +1241,39 @@ void wide_destroy(WideScratch* w) {
 int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* ids, u64 count) {
   HeapState* st = h->st;
   if (count == 0) return 0;
+  // A batch of at most d pairs is one piece: the compaction writes it straight
+  // into S_0 (empty between operations).
+  const bool direct = count <= h->g.d;
+  if (direct)
+    if (int rc = grow_if_needed(w, h)) return rc;
   if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
   const u32 gi = grid_for(count);
   hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, h->bitmap, w->pt);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                     (u32*)nullptr, &w->ctl->newly, w->ctl);
+                     (u32*)nullptr, &w->mail_d->newly, w->ctl);
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
+  const Arr S0 = lbuf(h->g, 0, 3);
+  u64* uk = direct ? S0.k : h->ukeys;
+  u32* uv = direct ? S0.v : h->uids;
   hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, w->tc, (const u32*)nullptr,
-                     (const u64*)h->cur, h->ukeys, h->uids);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->ctl->total);
+                     (const u64*)h->cur, uk, uv);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->mail_d->total);
   hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, (u32*)nullptr, w->toff,
-                     (const u64*)h->cur, h->ukeys, h->uids);
+                     (const u64*)h->cur, uk, uv);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
-  const u64 nu = w->hctl->total;
-  st->live += w->hctl->newly;
+  const u64 nu = w->mail_h->total;
+  st->live += w->mail_h->newly;
   for (u64 c0 = 0; c0 < nu;) {
-    if (int rc = grow_if_needed(w, h)) return rc;
+    if (!direct)
+      if (int rc = grow_if_needed(w, h)) return rc;
     const u32 len = (u32)((nu - c0) < h->g.d ? (nu - c0) : h->g.d);
     Arr S = lbuf(h->g, 0, 3);
-    WCHK(hipMemcpyAsync(S.k, h->ukeys + c0, len * sizeof(u64), hipMemcpyDeviceToDevice, w->s));
-    WCHK(hipMemcpyAsync(S.v, h->uids + c0, len * sizeof(u32), hipMemcpyDeviceToDevice, w->s));
+    if (!direct) {
+      WCHK(hipMemcpyAsync(S.k, h->ukeys + c0, len * sizeof(u64), hipMemcpyDeviceToDevice, w->s));
+      WCHK(hipMemcpyAsync(S.v, h->uids + c0, len * sizeof(u32), hipMemcpyDeviceToDevice, w->s));
+    }
     st->L[0].nS = len;
     st->L[0].ssel = 0;
     if (st->ell < 0) st->ell = 0;
