@@ -176,8 +176,8 @@ typedef struct {
                              (weights input-major, already rounded to bfloat16); the
                              model maps 8 per-round features to y, k = 2^(scale*y) */
   /* Training traces: every trace_every-th round writes 8 features to
-   * trace_features[8*i], the 32 smallest (key, id) of B_0 in key order to
-   * trace_keys[32*i] / trace_ids[32*i] (UINT64_MAX keys pad short lists) and the
+   * trace_features[8*i], the PBH_TRACE_K smallest (key, id) of B_0 in key order to
+   * trace_keys[PBH_TRACE_K*i] / trace_ids[PBH_TRACE_K*i] (UINT64_MAX keys pad short lists) and the
    * query's index (0 for sssp_ex, the position in the queries array for
    * sssp_batch) to trace_query[i] (may be NULL), where i = atomicAdd(trace_count,
    * 1) while i < trace_cap.  All device arrays. */
@@ -199,6 +199,7 @@ typedef struct {
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+#define PBH_TRACE_K 64 /* (key, id) pairs per trace record */
 #define PBH_MLP_BLOB (PBH_MLP_PARAMS + 2 * 8 + 1)
 
 /* Statistics of one sssp_ex run (host struct). */

@@ -21,6 +21,9 @@
 
 using namespace bkt;
 
+static_assert(PBH_TRACE_K == TRACE_K, "trace record length of the header and the kernels");
+static_assert(PBH_MLP_BLOB == MLP_BLOB, "model size of the header and the kernels");
+
 namespace {
 
 thread_local char g_err[512] = "";

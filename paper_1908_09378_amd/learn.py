@@ -4,8 +4,10 @@ FP32 accumulation) that picks how many minima each parDijkstra round pulls.
 
 Pipeline (all device work in the library's kernels):
   1. plain parDijkstra runs over training graphs in one batched launch, with
-     traces: every `every`-th round records 8 features and the 32 smallest
-     (key, id) of B_0 in key order;
+     traces: every `every`-th round records 8 features and the TRACE_K (64)
+     smallest (key, id) of B_0 in key order; the runs are repeated with the
+     heap's bulk size d at 1x and 4x the maximum out-degree, so the model sees
+     the d values the autotuner picks and B_0 prefixes longer than 2d;
   2. labels: log2 of the longest traced prefix whose keys are already final
      distances (the pull size that wastes no relaxation);
   3. feature normalisation and Adam training on the GPU;
@@ -29,7 +31,8 @@ from . import MLP_BLOB, MLP_PARAMS, mlp_feature_stats, mlp_trace_labels, mlp_tra
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(HERE, "models", "k_mlp.bin")
 MAGIC = b"PBHKMLP1"
-NF, H, TK = 8, 64, 32
+NF, H = 8, 64
+TK = 64  # trace record length (PBH_TRACE_K)
 
 
 def save_model(blob: np.ndarray, path: str) -> None:
@@ -75,9 +78,10 @@ def init_blob(seed: int = 0) -> np.ndarray:
     return b
 
 
-def collect(graphs, every: int = 16, cap: int = 1 << 21, source: int = 0):
-    """Plain runs with traces over `graphs` (one query each, one launch).
-    Returns device tensors X [n, 8] and Y [n] (labels) and the run's stats."""
+def collect(graphs, every: int = 16, cap: int = 1 << 22, source: int = 0, d_scales=(1, 4)):
+    """Plain runs with traces over `graphs` (one query each, one launch per
+    d_scale).  Returns device tensors X [n, 8] and Y [n] (labels) and the
+    last run's stats."""
     import torch
     dev = torch.device("cuda:0")
     qs, keep, dists = [], [], []
@@ -94,7 +98,8 @@ def collect(graphs, every: int = 16, cap: int = 1 << 21, source: int = 0):
     tv = torch.zeros(cap * TK, dtype=torch.int32, device=dev)
     tq = torch.zeros(cap, dtype=torch.int32, device=dev)
     cnt = torch.zeros(1, dtype=torch.int32, device=dev)
-    st = sssp_batch(qs, trace=(tf, tk, tv, cnt, tq, every))
+    for ds in d_scales:
+        st = sssp_batch(qs, trace=(tf, tk, tv, cnt, tq, every), d_scale=ds)
     n = min(int(cnt.item()), cap)
     labels = torch.empty(n, dtype=torch.float32, device=dev)
     mlp_trace_labels(tk, tv, tq, n, dists, labels)

@@ -57,8 +57,9 @@ def test_trace_labels_match_oracle():
     # reproduce labels with the oracle from the traces and final distances
     cap = 1 << 14
     tf = torch.zeros(cap * 8, dtype=torch.float32, device=DEV)
-    tk = torch.zeros(cap * 32, dtype=torch.int64, device=DEV)
-    tv = torch.zeros(cap * 32, dtype=torch.int32, device=DEV)
+    TK = learn.TK
+    tk = torch.zeros(cap * TK, dtype=torch.int64, device=DEV)
+    tv = torch.zeros(cap * TK, dtype=torch.int32, device=DEV)
     tq = torch.zeros(cap, dtype=torch.int32, device=DEV)
     cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
     qs, keep, dists = [], [], []
@@ -74,7 +75,7 @@ def test_trace_labels_match_oracle():
     m = int(cnt.item())
     lab = torch.empty(m, dtype=torch.float32, device=DEV)
     pkg.mlp_trace_labels(tk, tv, tq, m, dists, lab)
-    K, V, Q = host64(tk).reshape(-1, 32), host32(tv).reshape(-1, 32), host32(tq)
+    K, V, Q = host64(tk).reshape(-1, TK), host32(tv).reshape(-1, TK), host32(tq)
     D = [oracle.dijkstra(g, 0) for g in gs]
     for r in range(m):
         ref = mlp.zero_waste_label(K[r], V[r], D[Q[r]])
