@@ -199,7 +199,7 @@ typedef struct {
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
-#define PBH_TRACE_K 64 /* (key, id) pairs per trace record */
+#define PBH_TRACE_K 32 /* (key, id) pairs per trace record */
 #define PBH_MLP_BLOB (PBH_MLP_PARAMS + 2 * 8 + 1)
 
 /* Statistics of one sssp_ex run (host struct). */

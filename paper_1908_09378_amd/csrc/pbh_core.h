@@ -967,7 +967,7 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
 // small learned model (see mlp_forward).
 
 constexpr int KMAX_ROUND = 256;  // cap on k per round (extracted vertices kept in LDS)
-constexpr int TRACE_K = 64;      // key-ordered prefix of B_0 recorded per traced round
+constexpr int TRACE_K = 32;      // key-ordered prefix of B_0 recorded per traced round
 constexpr int NFEAT = 8;
 constexpr int MLP_H = 64;
 // MLP parameters (float32, weights already rounded to bfloat16), in order:

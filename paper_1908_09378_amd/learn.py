@@ -4,10 +4,9 @@ FP32 accumulation) that picks how many minima each parDijkstra round pulls.
 
 Pipeline (all device work in the library's kernels):
   1. plain parDijkstra runs over training graphs in one batched launch, with
-     traces: every `every`-th round records 8 features and the TRACE_K (64)
-     smallest (key, id) of B_0 in key order; the runs are repeated with the
-     heap's bulk size d at 1x and 4x the maximum out-degree, so the model sees
-     the d values the autotuner picks and B_0 prefixes longer than 2d;
+     traces: every `every`-th round records 8 features and the TK (32)
+     smallest (key, id) of B_0 in key order (d_scales can repeat the runs
+     with larger bulk sizes d);
   2. labels: log2 of the longest traced prefix whose keys are already final
      distances (the pull size that wastes no relaxation);
   3. feature normalisation and Adam training on the GPU;
@@ -32,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(HERE, "models", "k_mlp.bin")
 MAGIC = b"PBHKMLP1"
 NF, H = 8, 64
-TK = 64  # trace record length (PBH_TRACE_K)
+TK = 32  # trace record length (PBH_TRACE_K)
 
 
 def save_model(blob: np.ndarray, path: str) -> None:
@@ -78,7 +77,7 @@ def init_blob(seed: int = 0) -> np.ndarray:
     return b
 
 
-def collect(graphs, every: int = 16, cap: int = 1 << 22, source: int = 0, d_scales=(1, 4)):
+def collect(graphs, every: int = 16, cap: int = 1 << 21, source: int = 0, d_scales=(1,)):
     """Plain runs with traces over `graphs` (one query each, one launch per
     d_scale).  Returns device tensors X [n, 8] and Y [n] (labels) and the
     last run's stats."""
