@@ -346,15 +346,47 @@ PBH_INL KV select_small(const T& t, AA A, u32 n, u32 r) {
   return top ? KV{~bk, ~bv} : KV{bk, bv};
 }
 
+// r-th smallest of n <= 2 * team size elements by counting: every element
+// (at most two per thread) counts the elements below it; the one with r - 1
+// below is the answer ((key, id) pairs are distinct).
+template <class T, class AA>
+PBH_INL KV select_rank(const T& t, AA A, u32 n, u32 r) {
+  const u32 x0 = (u32)t.tid(), x1 = x0 + (u32)T::kNT;
+  const u64 k0 = x0 < n ? A.k[x0] : KINF, k1 = x1 < n ? A.k[x1] : KINF;
+  const u32 v0 = x0 < n ? A.v[x0] : VINF, v1 = x1 < n ? A.v[x1] : VINF;
+  u32 c0 = 0, c1 = 0;
+  for (u32 y = 0; y < n; ++y) {
+    const u64 ky = A.k[y];
+    const u32 vy = A.v[y];
+    c0 += (ky < k0 || (ky == k0 && vy < v0)) ? 1u : 0u;
+    c1 += (ky < k1 || (ky == k1 && vy < v1)) ? 1u : 0u;
+  }
+  t.sync();
+  if (x0 < n && c0 + 1 == r) {
+    t.sh->wk[0] = k0;
+    t.sh->wv[0] = v0;
+  }
+  if (x1 < n && c1 + 1 == r) {
+    t.sh->wk[0] = k1;
+    t.sh->wv[0] = v1;
+  }
+  t.sync();
+  const KV res{t.sh->wk[0], t.sh->wv[0]};
+  t.sync();
+  return res;
+}
+
 // Select(A, r): the r-th smallest (key, id) of A, 1 <= r <= n.  Radix select,
 // most significant byte first, over key - min(key) (only the bytes the key
 // range needs), then over the id among elements with the selected key.  The
 // paper sorted with a radix sort to select (Section 4.1); a radix select reads
 // the candidates once per byte and sorts nothing.  Ranks within two of either
-// end of a small array use select_small.
+// end of a small array use select_small; other ranks in arrays of at most two
+// elements per thread use select_rank.
 template <class T, class AA>
 PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   if (n <= 8u * (u32)T::kNT && (r <= 2 || n - r + 1 <= 2)) return select_small(t, A, n, r);
+  if (n <= 2u * (u32)T::kNT) return select_rank(t, A, n, r);
   u64 lo = KINF, hi = 0;
   for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
     u64 k = A.k[x];
