@@ -4,10 +4,12 @@
 //   k_mpart / k_merge<false> / k_scan / k_merge<true>
 //       Merge of two id-sorted arrays with DeleteDuplicates (Section 2.1):
 //       merge-path split points per tile, a counting pass, a scan of the tile
-//       counts, and a writing pass that stages the tile in LDS and stores it
-//       coalesced.  The writing pass also counts outputs <= a pivot (the count
-//       in Resolve's EMPTY step) and the key range (the start of Select).
-//   k_part<false> / k_scan3 / k_part<true>
+//       counts, and a writing pass in which every element finds its position
+//       by a binary search in the other input's window and stores itself
+//       directly.  The writing pass can also count outputs <= a pivot (the
+//       count in Resolve's EMPTY step) and the key range (the start of Select),
+//       as per-workgroup partials folded by k_reduce.
+//   k_part<false> / k_scan (three arrays) / k_part<true>
 //       Stable three-way split by two (key, id) pivots.
 //   k_sel_*
 //       Select: radix selection on the 96-bit (key, id) value, 8 bits per
@@ -21,6 +23,8 @@
 //       LDS, then merge passes.
 //   k_absent
 //       Marks extracted ids absent.
+// The few results the host needs after a step (sizes, the selected element)
+// are written by the step's last kernel into host-mapped memory.
 #include "wide.h"
 
 #include <algorithm>
@@ -41,14 +45,10 @@ constexpr u32 CANDMAX = NT;              // candidates ranked by one workgroup
 constexpr int GRID_STRIDE = 2048;        // workgroups of the grid-stride kernels
 constexpr int GRID_HIST = 512;           // workgroups of a Select pass (each flushes <= 256 atomics)
 
-// Results of the device steps, copied to the host after each step.
+// Device-side state of a selection (read and written by the Select kernels)
+// and the key range of the array it runs on.
 struct Ctl {
-  u32 total;    // output size of a merge or the bitmap compaction
-  u32 num_le;   // merge outputs <= the counting pivot
-  u32 part[4];  // three-way split sizes
   u64 kmin, kmax;
-  u64 newly;    // ids inserted (absent before) by the intake
-  // selection state
   u64 spk;
   u32 spv;
   int snb;      // leading bits of (key, id) fixed so far
@@ -58,12 +58,8 @@ struct Ctl {
   int sfail;    // the gather ran before the passes were done
   int sbad;     // no bin held the rank (never expected)
   u32 sncand;
-  u64 rk;       // the selected element
-  u32 rv;
-  u32 pad;
   u32 shist[SEL_BINS];
 };
-constexpr size_t CTL_HEAD = offsetof(Ctl, shist);
 
 // What the host reads after a step, written by the step's last kernel into
 // host-mapped coherent memory (a readback is then only a stream sync).
@@ -81,14 +77,8 @@ struct Mail {
 __device__ __forceinline__ u64 atomic_min64(u64* p, u64 v) {
   return __hip_atomic_fetch_min((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ u64 atomic_max64(u64* p, u64 v) {
-  return __hip_atomic_fetch_max((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ u32 atomic_add32(u32* p, u32 v) {
   return __hip_atomic_fetch_add((u32 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ u64 atomic_add64(u64* p, u64 v) {
-  return __hip_atomic_fetch_add((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Exclusive scan over the workgroup (NTH threads); *total = the sum.
@@ -400,16 +390,6 @@ __global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride
   if (threadIdx.x == 0) total[blockIdx.x] = carry;
 }
 
-__global__ void k_ctl_reset(Ctl* c) {
-  if (threadIdx.x == 0) {
-    c->total = 0;
-    c->num_le = 0;
-    c->part[0] = c->part[1] = c->part[2] = c->part[3] = 0;
-    c->kmin = KINF;
-    c->kmax = 0;
-    c->newly = 0;
-  }
-}
 
 // ------------------------------------------------------------------ three-way split
 
@@ -961,7 +941,6 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   const u32 nt = cdiv(total, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
-  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, w->s, w->ctl);
   hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
   hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
                      0);
