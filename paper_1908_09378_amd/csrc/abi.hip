@@ -168,7 +168,6 @@ WideHeap wide_view(pbh* h) {
   w.g = pbh_geom(h);
   w.st = &h->host;
   w.cur = h->cur;
-  w.bitmap = h->bitmap;
   w.nwords = h->nwords;
   w.sched = h->sched;
   w.ukeys = h->ukeys;

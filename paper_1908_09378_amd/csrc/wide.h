@@ -23,8 +23,7 @@ struct WideHeap {
   Geom g;
   HeapState* st;  // host-side state, authoritative for this engine
   u64* cur;       // device: current key of every id (KINF = absent)
-  u32* bitmap;    // device: one bit per id, all zero between calls
-  u32 nwords;
+  u32 nwords;     // id capacity / 32, rounded up
   int sched;
   u64* ukeys;     // device: room for min(count, id_capacity) update pairs
   u32* uids;

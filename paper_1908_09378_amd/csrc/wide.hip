@@ -16,8 +16,8 @@
 //       pass from the first bit where the keys differ, until at most 256
 //       candidates remain; those are gathered and ranked in one workgroup.
 //   k_intake / k_bits<false> / k_bits<true>
-//       BulkUpdate intake: atomicMin on the current keys, an id bitmap of the
-//       ids whose key dropped, and its compaction into U sorted by id.
+//       BulkUpdate intake: atomicMin on the current keys, a mark byte per id
+//       whose key dropped, and their compaction into U sorted by id.
 //   k_tsort / k_spart / k_smerge
 //       Sorting the extracted minima by (key, id): bitonic sort of tiles in
 //       LDS, then merge passes.
@@ -28,6 +28,8 @@
 #include "wide.h"
 
 #include <algorithm>
+#include <chrono>
+#include <cstddef>
 #include <cstring>
 
 #include "pbh_team.h"
@@ -35,10 +37,11 @@
 namespace bkt {
 namespace {
 
+using u8 = unsigned char;
+
 constexpr int NT = 256;
 constexpr int WE = 8;
 constexpr u32 TILE = NT * WE;  // 2048
-static_assert(TILE / 32 == 64, "the merge's drop bitmap is scanned by one wavefront");
 constexpr int SEL_BITS = 8;
 constexpr int SEL_BINS = 1 << SEL_BITS;  // one bin per thread of the pick kernel
 constexpr u32 CANDMAX = NT;              // candidates ranked by one workgroup
@@ -61,10 +64,11 @@ struct Ctl {
   u32 shist[SEL_BINS];
 };
 
-// What the host reads after a step, written by the step's last kernel into
-// host-mapped coherent memory (a readback is then only a stream sync).
+// What the host reads after a step.  The step's kernels write it in device
+// memory; k_post then copies it into host-mapped coherent memory and writes
+// the step's sequence number last, which the host polls.
 struct Mail {
-  u32 total;    // output size of a merge or of the bitmap compaction
+  u32 total;    // output size of a merge or of the mark compaction
   u32 num_le;   // merge outputs <= the counting pivot
   u32 part[4];  // three-way split sizes
   u64 newly;    // ids inserted by the intake
@@ -72,7 +76,11 @@ struct Mail {
   u32 rv;
   int sfail;    // the selection needs more passes
   int sbad;     // the selection found no element of the rank (never expected)
+  u32 seq;      // number of the last step published (host copy only)
 };
+static_assert(offsetof(Mail, seq) + sizeof(u32) == sizeof(Mail) && sizeof(Mail) % 4 == 0,
+              "k_post copies whole words and writes seq last");
+constexpr u32 MAIL_WORDS = sizeof(Mail) / 4;
 
 __device__ __forceinline__ u64 atomic_min64(u64* p, u64 v) {
   return __hip_atomic_fetch_min((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -147,6 +155,42 @@ __device__ __forceinline__ u32 mpath(KP ak, VP av, u32 na, KP bk, VP bv, u32 nb,
   return lo;
 }
 
+// The same split as mpath, found by one wavefront: each round every lane
+// tests one of 64 evenly spaced probes and the ballot's popcount (the tests
+// are true on a prefix) narrows the range 65-fold, so a split of arrays of
+// millions costs about four dependent global loads instead of twenty-odd.
+// All 64 lanes must call it with the same arguments.
+template <bool BYKV, class KP, class VP>
+__device__ __forceinline__ u32 mpath_wave(KP ak, VP av, u32 na, KP bk, VP bv, u32 nb, u32 diag) {
+  const u32 lane = threadIdx.x & 63u;
+  u32 lo = diag > nb ? diag - nb : 0u, hi = diag < na ? diag : na;
+  while (lo < hi) {
+    const u32 len = hi - lo;
+    const bool small = len <= 64u;
+    const u32 mid = small ? lo + lane : lo + (u32)(((u64)(lane + 1) * len) / 65u);
+    bool afirst = false;
+    if (!small || lane < len) {
+      const u32 jb = diag - 1 - mid;
+      if constexpr (BYKV) {
+        const u64 ka = ak[mid], kb = bk[jb];
+        afirst = ka < kb || (ka == kb && av[mid] <= bv[jb]);
+      } else {
+        afirst = av[mid] <= bv[jb];
+      }
+    }
+    const u32 c = (u32)__popcll(__ballot(afirst));
+    if (small) return lo + c;
+    if (c == 0) {
+      hi = lo + (u32)(len / 65u);
+    } else {
+      const u32 nlo = lo + (u32)(((u64)c * len) / 65u) + 1u;
+      if (c < 64u) hi = lo + (u32)(((u64)(c + 1) * len) / 65u);
+      lo = nlo;
+    }
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ merge by id
 
 struct MArgs {
@@ -184,50 +228,33 @@ __device__ __forceinline__ bool pair_keep(const MArgs& a, u64 ka, u64 kb, u32 v,
   return true;
 }
 
-__global__ void k_mpart(const u32* av, u32 na, const u32* bv, u32 nb, u32 ntiles, u32* part) {
-  u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+// Split points of the tiles (one wavefront per split, SPW per workgroup).
+constexpr u32 SPW = NT / 64;
+__global__ __launch_bounds__(NT) void k_mpart(const u32* av, u32 na, const u32* bv, u32 nb, u32 ntiles, u32* part) {
+  const u32 t = blockIdx.x * SPW + (threadIdx.x >> 6);
   if (t > ntiles) return;
-  u64 total = (u64)na + nb;
-  u64 dg = (u64)t * TILE;
-  u32 diag = (u32)(dg < total ? dg : total);
-  part[t] = mpath<false>((const u64*)nullptr, av, na, (const u64*)nullptr, bv, nb, diag);
-}
-
-// First index in v[0, n) whose id is >= x (lower) or > x (upper).
-__device__ __forceinline__ u32 lower_id(const u32* v, u32 n, u32 x) {
-  u32 lo = 0, hi = n;
-  while (lo < hi) {
-    u32 mid = (lo + hi) >> 1;
-    if (v[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-__device__ __forceinline__ u32 upper_id(const u32* v, u32 n, u32 x) {
-  u32 lo = 0, hi = n;
-  while (lo < hi) {
-    u32 mid = (lo + hi) >> 1;
-    if (v[mid] <= x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
+  const u64 total = (u64)na + nb;
+  const u64 dg = (u64)t * TILE;
+  const u32 diag = (u32)(dg < total ? dg : total);
+  const u32 i = mpath_wave<false>((const u64*)nullptr, av, na, (const u64*)nullptr, bv, nb, diag);
+  if ((threadIdx.x & 63u) == 0) part[t] = i;
 }
 
 // One tile of merge(A, B) by id with DeleteDuplicates: the outputs at merge
-// positions [t*TILE, (t+1)*TILE), whose inputs are A[i0, i1) and B[j0, j1).
-// Every element finds its position in the tile by a binary search of its id
-// in the other input's window (only the ids sit in LDS; ties: A first).  The
-// copy of an id present in both inputs is decided at A's slot (pair_keep) and
-// B's slot is dropped; a partner just outside the window is A[i0-1] or B[j1].
-// Counting pass: tcnt[t] = kept outputs.  Writing pass: dropped positions are
-// marked in an LDS bitmap, and each kept element goes straight to C at
-// toff[t] + its position - the drops before it (the tile's output range is
-// contiguous, so the L2 gathers the writes into full lines).  With `stats`
-// the writing pass also counts outputs <= (pk, pv) and the key range.
+// positions [t*TILE, (t+1)*TILE), whose inputs are A[i0, i1) and B[j0, j1)
+// (staged in LDS: ids, and keys in the writing pass).  Each thread takes WE
+// consecutive merge positions: one merge-path search in LDS finds where they
+// start, then a sequential walk merges them (ties: A first), so a copy of an
+// id present in both inputs sits right after A's copy.  The pair is decided
+// at A's slot (pair_keep) and B's slot is dropped; a partner just outside the
+// tile is A[i0-1] or B[j1].  Counting pass: tcnt[t] = kept outputs.  Writing
+// pass: a scan of the threads' kept counts gives each output its place in the
+// tile's output range; the outputs are transposed through LDS (reusing the
+// input staging, at index o + o/8 so that the threads' runs of WE spread over
+// the banks) and stored coalesced at toff[t] + o.  Stored straight from the
+// walk, each store instruction would touch 64 cache lines (a thread's
+// outputs are consecutive), which measured 1.6x slower.  With `stats` the
+// writing pass also counts outputs <= (pk, pv) and the key range.
 // Per-workgroup partial results (a count and a key range), reduced by
 // k_reduce: thousands of workgroups updating the same word with atomics would
 // serialise in the L2.
@@ -240,9 +267,10 @@ struct Partials {
 template <bool WRITE>
 __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Partials pt,
                                               int stats) {
-  __shared__ u32 sv[TILE];
-  __shared__ u32 sdrop[TILE / 32];  // bit p: merge position p of the tile is dropped
-  __shared__ u32 spre[TILE / 32];   // dropped positions before word w
+  constexpr u32 NONE = 0xFFFFFFFFu;  // exhausted input (ids are < 2^32 - 1)
+  constexpr u32 PAD = WRITE ? TILE / 8 : 0;  // room for the transposed index o + o/8
+  __shared__ u32 sv[TILE + PAD];
+  __shared__ u64 sk[WRITE ? TILE + PAD : 1];
   __shared__ u32 sw[NT / 64];
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   const u32 t = blockIdx.x, total = a.na + a.nb;
@@ -250,91 +278,110 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
   const u32 i0 = part[t], i1 = part[t + 1];
   const u32 j0 = d0 - i0, j1 = d1 - i1;
   const u32 nA = i1 - i0, nT = d1 - d0, nB = nT - nA;
-  // the thread's own elements: tile slots tid + q*NT (all loads issued first)
-  u64 ko[WE];
-  u32 vo[WE];
+  {
+    u64 lk[WE];
+    u32 lv[WE];
 #pragma unroll
-  for (int q = 0; q < WE; ++q) {
-    const u32 x = threadIdx.x + (u32)q * NT;
-    const bool fromA = x < nA;
-    const u32 g = fromA ? i0 + x : j0 + (x - nA);
-    vo[q] = 0;
-    ko[q] = 0;
-    if (x < nT) {
-      vo[q] = fromA ? a.av[g] : a.bv[g];
-      if constexpr (WRITE) ko[q] = fromA ? a.ak[g] : a.bk[g];
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      const bool fromA = x < nA;
+      const u32 g = fromA ? i0 + x : j0 + (x - nA);
+      lv[q] = 0;
+      lk[q] = 0;
+      if (x < nT) {
+        lv[q] = fromA ? a.av[g] : a.bv[g];
+        if constexpr (WRITE) lk[q] = fromA ? a.ak[g] : a.bk[g];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      if (x < nT) {
+        sv[x] = lv[q];
+        if constexpr (WRITE) sk[x] = lk[q];
+      }
     }
   }
-#pragma unroll
-  for (int q = 0; q < WE; ++q) {
-    const u32 x = threadIdx.x + (u32)q * NT;
-    if (x < nT) sv[x] = vo[q];
-  }
-  if (WRITE && threadIdx.x < TILE / 32) sdrop[threadIdx.x] = 0;
   const bool hasPrev = i0 > 0, hasNext = j1 < a.nb;
   const u32 aprev = hasPrev ? a.av[i0 - 1] : 0u, bnext = hasNext ? a.bv[j1] : 0u;
   __syncthreads();
   const u32* sA = sv;
   const u32* sB = sv + nA;
-  u32 pos[WE];
+  const u32 p0 = min((u32)threadIdx.x * WE, nT), p1 = min(p0 + WE, nT);
+  u32 i = mpath<false>((const u64*)nullptr, sA, nA, (const u64*)nullptr, sB, nB, p0);
+  u32 j = p0 - i;
+  u32 va = i < nA ? sA[i] : NONE, vb = j < nB ? sB[j] : NONE;
+  bool havePrevA = i > 0 || hasPrev;
+  u32 prevA = i > 0 ? sA[i - 1] : aprev;
+  u64 ko[WE];
+  u32 vo[WE];
   u32 keep = 0;
 #pragma unroll
   for (int q = 0; q < WE; ++q) {
-    const u32 x = threadIdx.x + (u32)q * NT;
-    pos[q] = 0;
-    if (x >= nT) continue;
-    const u32 v = vo[q];
+    ko[q] = 0;
+    vo[q] = 0;
+    if (p0 + (u32)q >= p1) continue;
     bool kp = true;
-    if (x < nA) {
-      const u32 lb = lower_id(sB, nB, v);
-      pos[q] = x + lb;
-      const bool dup = lb < nB ? sB[lb] == v : (hasNext && bnext == v);
+    if (va <= vb) {  // A's element (first on equal ids)
+      const u32 v = va;
+      u64 k = WRITE ? sk[i] : 0ull;
+      const bool dup = j < nB ? vb == v : (hasNext && bnext == v);
       if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
-        const u64 ka = WRITE ? ko[q] : a.ak[i0 + x];
-        const u64 kb = a.bk[lb < nB ? j0 + lb : j1];
-        u64 k = ka;
+        const u64 ka = WRITE ? k : a.ak[i0 + i];
+        const u64 kb = j < nB ? (WRITE ? sk[nA + j] : a.bk[j0 + j]) : a.bk[j1];
         kp = pair_keep(a, ka, kb, v, &k);
-        ko[q] = k;
       }
-    } else {
-      const u32 j = x - nA;
-      const u32 ub = upper_id(sA, nA, v);
-      pos[q] = j + ub;
-      kp = !(ub > 0 ? sA[ub - 1] == v : (hasPrev && aprev == v));
-      if (kp && a.filterB) kp = a.cur[v] == (WRITE ? ko[q] : a.bk[j0 + j]);
+      vo[q] = v;
+      ko[q] = k;
+      prevA = v;
+      havePrevA = true;
+      ++i;
+      va = i < nA ? sA[i] : NONE;
+    } else {  // B's element: dropped when A holds the id
+      const u32 v = vb;
+      const u64 k = WRITE ? sk[nA + j] : 0ull;
+      kp = !(havePrevA && prevA == v);
+      if (kp && a.filterB) kp = a.cur[v] == (WRITE ? k : a.bk[j0 + j]);
+      vo[q] = v;
+      ko[q] = k;
+      ++j;
+      vb = j < nB ? sB[j] : NONE;
     }
     keep |= (u32)kp << q;
   }
+  const u32 nk = (u32)__builtin_popcount(keep);
   if constexpr (!WRITE) {
-    const u32 tot = block_sum<NT>((u32)__builtin_popcount(keep), sw);
+    const u32 tot = block_sum<NT>(nk, sw);
     if (threadIdx.x == 0) tcnt[t] = tot;
   } else {
-#pragma unroll
-    for (int q = 0; q < WE; ++q)
-      if (threadIdx.x + (u32)q * NT < nT && !((keep >> q) & 1u))
-        atomicOr(&sdrop[pos[q] >> 5], 1u << (pos[q] & 31));
-    __syncthreads();
-    if (threadIdx.x < TILE / 32) {
-      const u32 c = (u32)__builtin_popcount(sdrop[threadIdx.x]);
-      spre[threadIdx.x] = wave_incl(c) - c;  // TILE / 32 == 64: one wavefront
-    }
-    __syncthreads();
-    const u32 base = toff[t];
+    u32 tot;
+    u32 o = block_scan<NT>(nk, &tot, sw);  // its barriers also end every walk's reads of sv / sk
     u32 nle = 0;
     u64 lo = KINF, hi = 0;
 #pragma unroll
     for (int q = 0; q < WE; ++q)
       if ((keep >> q) & 1u) {
-        const u32 p = pos[q], w = p >> 5;
-        const u32 o = base + p - (spre[w] + (u32)__builtin_popcount(sdrop[w] & ((1u << (p & 31)) - 1u)));
-        a.ck[o] = ko[q];
-        a.cv[o] = vo[q];
+        const u32 z = o + (o >> 3);
+        sk[z] = ko[q];
+        sv[z] = vo[q];
+        ++o;
         if (stats) {
           nle += kv_le(KV{ko[q], vo[q]}, KV{a.pk, a.pv});
           lo = ko[q] < lo ? ko[q] : lo;
           hi = ko[q] > hi ? ko[q] : hi;
         }
       }
+    __syncthreads();
+    const u32 base = toff[t];
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const u32 x = threadIdx.x + (u32)q * NT;
+      if (x < tot) {
+        const u32 z = x + (x >> 3);
+        a.ck[base + x] = sk[z];
+        a.cv[base + x] = sv[z];
+      }
+    }
     if (stats) {
       nle = block_sum<NT>(nle, sw);
       block_minmax<NT>(lo, hi, swl, swh);
@@ -690,9 +737,29 @@ __global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Partials pt)
   }
 }
 
+// ------------------------------------------------------------------ publishing
+
+// Copies a step's results (box, device memory) into the host-mapped mailbox,
+// then writes the sequence number with a system-scope release.  Each lane
+// fences its own word before the barrier, so every word is visible to the
+// host before seq is.
+__global__ __launch_bounds__(64) void k_post(const Mail* box, Mail* mail, u32 seq) {
+  const u32 l = threadIdx.x;
+  if (l + 1 < MAIL_WORDS) {
+    ((u32*)mail)[l] = ((const u32*)box)[l];
+    __threadfence_system();
+  }
+  __syncthreads();
+  if (l == 0) __hip_atomic_store(&mail->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ------------------------------------------------------------------ intake
 
-__global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, u64 count, u64* cur, u32* bitmap,
+// cur[id] = min(cur[id], key) for every pair (atomicMin); an id whose key
+// dropped gets its mark byte set by a plain store (every writer stores the
+// same 1, so no atomic is needed: a random atomic costs a round trip to the
+// memory side, a byte store is merged in the L2).
+__global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, u64 count, u64* cur, u8* marks,
                                                Partials pt) {
   __shared__ u32 sw[NT / 64];
   u32 newly = 0;
@@ -711,8 +778,7 @@ __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, 
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (k[q] < old[q]) {
-        __hip_atomic_fetch_or((u32 PBH_GLB*)(bitmap + (id[q] >> 5)), 1u << (id[q] & 31), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
+        marks[id[q]] = 1;
         newly += old[q] == KINF;
       }
   }
@@ -720,25 +786,41 @@ __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, 
   if (threadIdx.x == 0) pt.cnt[blockIdx.x] = newly;
 }
 
-// Bitmap compaction: set bits in increasing id order -> (cur[id], id); the
-// words are cleared.  Tile t = words [t*TILE, (t+1)*TILE) in WE rounds.
+// Mark compaction: marked ids in increasing order -> (cur[id], id); the
+// marks are cleared.  Each thread takes 32 consecutive ids (two 16-byte loads)
+// per round, turned into a 32-bit mask; tile t = ids [t*TILE*32, (t+1)*TILE*32)
+// in WE rounds.
+__device__ __forceinline__ u32 mark_mask(uint4 m) {
+  const u32 w[4] = {m.x, m.y, m.z, m.w};
+  u32 bits = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bits |= (u32)(((w[j] >> (8 * b)) & 0xFFu) != 0u) << (4 * j + b);
+  return bits;
+}
 template <bool WRITE>
-__global__ __launch_bounds__(NT) void k_bits(u32* bitmap, u32 nwords, u32* tc, const u32* toff, const u64* cur,
+__global__ __launch_bounds__(NT) void k_bits(u8* marks, u32 nwords, u32* tc, const u32* toff, const u64* cur,
                                              u64* uk, u32* uv) {
   __shared__ u32 sw[NT / 64];
   const u32 t = blockIdx.x;
   u32 run = WRITE ? toff[t] : 0u, cnt = 0;
+  uint4* m4 = (uint4*)marks;
 #pragma unroll
   for (int r = 0; r < WE; ++r) {
     const u64 w = (u64)t * TILE + (u64)r * NT + threadIdx.x;
-    u32 bits = w < nwords ? bitmap[w] : 0u;
+    u32 bits = 0;
+    if (w < nwords) bits = mark_mask(m4[2 * w]) | (mark_mask(m4[2 * w + 1]) << 16);
     u32 pc = (u32)__builtin_popcount(bits);
     if constexpr (!WRITE) {
       cnt += pc;
     } else {
       u32 tot;
       u32 o = run + block_scan<NT>(pc, &tot, sw);
-      if (bits) bitmap[w] = 0u;
+      if (bits) {
+        m4[2 * w] = make_uint4(0u, 0u, 0u, 0u);
+        m4[2 * w + 1] = make_uint4(0u, 0u, 0u, 0u);
+      }
       while (bits) {
         const u32 b = (u32)__builtin_ctz(bits);
         bits &= bits - 1;
@@ -804,12 +886,13 @@ __device__ __forceinline__ void run_pair(u32 n, u32 L, u64 s, u32* base, u32* na
   *nb = (u32)(end - mid);
 }
 
-__global__ void k_spart(const u64* K, const u32* V, u32 n, u32 L, u32 ntiles, u32* part) {
-  const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(NT) void k_spart(const u64* K, const u32* V, u32 n, u32 L, u32 ntiles, u32* part) {
+  const u32 t = blockIdx.x * SPW + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   u32 b, na, nb;
   run_pair(n, L, (u64)t * TILE, &b, &na, &nb);
-  part[t] = mpath<true>(K + b, V + b, na, K + b + na, V + b + na, nb, t * TILE - b);
+  const u32 i = mpath_wave<true>(K + b, V + b, na, K + b + na, V + b + na, nb, t * TILE - b);
+  if ((threadIdx.x & 63u) == 0) part[t] = i;
 }
 
 __global__ __launch_bounds__(NT) void k_smerge(const u64* K, const u32* V, u32 n, u32 L, const u32* part, u64* DK,
@@ -896,8 +979,12 @@ u32 grid_for(u64 n) {
 struct WideScratch {
   u32 d = 0;
   Ctl* ctl = nullptr;      // device
+  Mail* box = nullptr;     // device: results of the current step
   Mail* mail_h = nullptr;  // host-mapped coherent mailbox (host view)
   Mail* mail_d = nullptr;  // its device address
+  u32 seq = 0;             // steps published so far
+  u8* marks = nullptr;     // one byte per id (32 per 32-id word), zero between calls
+  u64 marks_n = 0;
   u32* part = nullptr;  // tile split points (maxtiles + 1)
   u32* tc = nullptr;    // tile counts, 3 arrays of maxtiles
   u32* toff = nullptr;  // tile offsets, 3 arrays of maxtiles
@@ -921,13 +1008,25 @@ namespace {
     if ((x) != hipSuccess) return E_DEVICE;   \
   } while (0)
 
-// Waits for the step; its results are then in the mailbox.
-int fetch(WideScratch* w) {
-  WCHK(hipStreamSynchronize(w->s));
-  return 0;
-}
-
 int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : E_DEVICE; }
+
+// Ends a step: publishes its results and waits until the host sees them, by
+// polling the mailbox's sequence number (a stream synchronisation would add
+// the runtime's completion path and a system-scope cache write-back to every
+// step).  Should the number not arrive within a second, the stream is
+// synchronised, which also reports a failed kernel.
+int fetch(WideScratch* w) {
+  const u32 want = ++w->seq;
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, w->s, w->box, w->mail_d, want);
+  if (int rc = launch_ok()) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (u32 spin = 1;; ++spin) {
+    if (__atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want) return 0;
+    if ((spin & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) break;
+  }
+  WCHK(hipStreamSynchronize(w->s));
+  return __atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want ? 0 : E_DEVICE;
+}
 
 // C = DeleteDuplicates(Merge(A, B)) by id; *num_le = outputs <= piv.
 int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, int prefer, bool filterB, KV piv,
@@ -941,21 +1040,22 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   const u32 nt = cdiv(total, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
-  hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, 256)), dim3(256), 0, w->s, A.v, na, B.v, nb, nt, w->part);
+  hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, SPW)), dim3(NT), 0, w->s, A.v, na, B.v, nb, nt, w->part);
   hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
                      0);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->mail_d->total);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
   WCHK(hipEventRecord(w->ev0, w->s));
   hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->pt,
                      stats ? 1 : 0);
   WCHK(hipEventRecord(w->ev1, w->s));
   if (stats)
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->mail_d->num_le, (u64*)nullptr, w->ctl);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->mail_h->total;
   *num_le = stats ? w->mail_h->num_le : 0u;
   float ms = 0.f;
+  WCHK(hipEventSynchronize(w->ev1));  // already passed: the step has ended
   WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
   w->merge_ms += ms;
   w->merge_bytes += 12ull * (total + *m);
@@ -973,15 +1073,17 @@ int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
   }
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(NT), 0, w->s, w->ctl, r, n);
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
-  // Each pass fixes 8 more of the 96 bits, so 12 passes always finish;
-  // typically two do.  Passes after the last needed one return at once.
+  // Each pass fixes 8 more of the 96 bits, so 12 passes (4 rounds of 3)
+  // always finish; two or three typically do (three when the keys crowd at
+  // one end of their range, as decreased keys do).  Passes after the last
+  // needed one return at once.
   for (int round = 0; round < 4; ++round) {
-    for (int p = 0; p < (round == 0 ? 2 : 4); ++p) {
+    for (int p = 0; p < 3; ++p) {
       hipLaunchKernelGGL(k_sel_hist, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl);
       hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(NT), 0, w->s, w->ctl);
     }
     hipLaunchKernelGGL(k_sel_collect, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v);
-    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v, w->mail_d);
+    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v, w->box);
     if (int rc = launch_ok()) return rc;
     if (int rc = fetch(w)) return rc;
     if (w->mail_h->sbad) return E_INTERNAL;
@@ -1003,7 +1105,7 @@ int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr 
   if (nt > w->maxtiles) return E_INTERNAL;
   PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}};
   hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
-  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->mail_d->part);
+  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part);
   hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
@@ -1028,7 +1130,7 @@ int wsort(WideScratch* w, Arr X, u32 n, u64* dk, u32* dv) {
   u64 L = TILE;
   for (int p = 0; p < passes; ++p, L *= 2) {
     Arr to = p == passes - 1 ? Arr{dk, dv} : (src.k == bufs[0].k ? bufs[1] : bufs[0]);
-    hipLaunchKernelGGL(k_spart, dim3(cdiv(nt, 256)), dim3(256), 0, w->s, src.k, src.v, n, (u32)L, nt, w->part);
+    hipLaunchKernelGGL(k_spart, dim3(cdiv(nt, SPW)), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, nt, w->part);
     hipLaunchKernelGGL(k_smerge, dim3(nt), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, w->part, to.k, to.v);
     src = to;
   }
@@ -1175,6 +1277,8 @@ int wide_create(WideScratch** out, u32 d) {
   w->d = d;
   *out = w;
   WCHK(hipMalloc(&w->ctl, sizeof(Ctl)));
+  WCHK(hipMalloc(&w->box, sizeof(Mail)));
+  WCHK(hipMemset(w->box, 0, sizeof(Mail)));
   WCHK(hipHostMalloc(&w->mail_h, sizeof(Mail), hipHostMallocMapped | hipHostMallocCoherent));
   std::memset(w->mail_h, 0, sizeof(Mail));
   WCHK(hipHostGetDevicePointer((void**)&w->mail_d, w->mail_h, 0));
@@ -1183,8 +1287,10 @@ int wide_create(WideScratch** out, u32 d) {
   WCHK(hipMalloc(&w->tmp_k, 4ull * d * sizeof(u64)));
   WCHK(hipMalloc(&w->tmp_v, 4ull * d * sizeof(u32)));
   WCHK(hipMemset(w->ctl, 0, sizeof(Ctl)));
-  WCHK(hipEventCreate(&w->ev0));
-  WCHK(hipEventCreate(&w->ev1));
+  // Timing-only events: without the system-scope fence a record does not
+  // write back the L2 (which would slow the very step being timed).
+  WCHK(hipEventCreateWithFlags(&w->ev0, hipEventDisableSystemFence));
+  WCHK(hipEventCreateWithFlags(&w->ev1, hipEventDisableSystemFence));
   return wide_reserve(w, 4ull * d);
 }
 
@@ -1198,6 +1304,8 @@ void wide_destroy(WideScratch* w) {
   if (!w) return;
   (void)hipDeviceSynchronize();
   if (w->ctl) (void)hipFree(w->ctl);
+  if (w->box) (void)hipFree(w->box);
+  if (w->marks) (void)hipFree(w->marks);
   if (w->mail_h) (void)hipHostFree(w->mail_h);
   if (w->part) (void)hipFree(w->part);
   if (w->tc) (void)hipFree(w->tc);
@@ -1226,19 +1334,27 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
   if (direct)
     if (int rc = grow_if_needed(w, h)) return rc;
   if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
+  if (w->marks_n < 32ull * h->nwords) {
+    if (w->marks) (void)hipFree(w->marks);
+    w->marks = nullptr;
+    w->marks_n = 0;
+    WCHK(hipMalloc(&w->marks, 32ull * h->nwords));
+    WCHK(hipMemsetAsync(w->marks, 0, 32ull * h->nwords, w->s));
+    w->marks_n = 32ull * h->nwords;
+  }
   const u32 gi = grid_for(count);
-  hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, h->bitmap, w->pt);
+  hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, w->marks, w->pt);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                     (u32*)nullptr, &w->mail_d->newly, w->ctl);
+                     (u32*)nullptr, &w->box->newly, w->ctl);
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   const Arr S0 = lbuf(h->g, 0, 3);
   u64* uk = direct ? S0.k : h->ukeys;
   u32* uv = direct ? S0.v : h->uids;
-  hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, w->tc, (const u32*)nullptr,
+  hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, w->tc, (const u32*)nullptr,
                      (const u64*)h->cur, uk, uv);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->mail_d->total);
-  hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, h->bitmap, h->nwords, (u32*)nullptr, w->toff,
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
+  hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, (u32*)nullptr, w->toff,
                      (const u64*)h->cur, uk, uv);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
