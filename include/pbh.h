@@ -115,12 +115,21 @@ int pbh_traffic(pbh_t *h, uint64_t *elements_out);
 
 /*
  * pbh_merge_profile: for the device-wide engine, totals over the writing
- * passes of its merges (Merge + DeleteDuplicates, its largest kernel) since
- * the handle was created: launches, algorithmic bytes (12 per input element
+ * passes of its merges (Merge + DeleteDuplicates, its largest kernel) run
+ * while profiling was on: launches, algorithmic bytes (12 per input element
  * read + 12 per output element written) and summed HIP-event time in ms (host
  * outputs).  Zeros for the one-workgroup engine.
  */
 int pbh_merge_profile(pbh_t *h, uint64_t *launches, uint64_t *bytes, double *ms);
+
+/*
+ * pbh_set_profiling: on != 0 brackets each merge writing pass of the
+ * device-wide engine with HIP events (for pbh_merge_profile); the events add
+ * some microseconds to each merge, so profiling is off by default.  No effect
+ * on results, nor on the one-workgroup engine.  Errors: PBH_EINVAL (NULL
+ * handle).
+ */
+int pbh_set_profiling(pbh_t *h, int on);
 
 /* pbh_destroy: frees the handle and its arena.  NULL is accepted. */
 int pbh_destroy(pbh_t *h);

@@ -60,7 +60,7 @@ class SsspQuery(C.Structure):
 
 
 _lib = None
-EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_destroy",
+EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_set_profiling", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "mlp_infer", "pbh_last_error"]
 
@@ -80,6 +80,7 @@ def lib():
         L.pbh_size.argtypes = [vp, C.POINTER(u64)]
         L.pbh_traffic.argtypes = [vp, C.POINTER(u64)]
         L.pbh_merge_profile.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(C.c_double)]
+        L.pbh_set_profiling.argtypes = [vp, C.c_int]
         L.pbh_destroy.argtypes = [vp]
         L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
@@ -256,6 +257,10 @@ class Heap:
         a, b, t = C.c_uint64(0), C.c_uint64(0), C.c_double(0)
         _check(lib().pbh_merge_profile(self._h, C.byref(a), C.byref(b), C.byref(t)))
         return dict(launches=a.value, bytes=b.value, ms=t.value)
+
+    def set_profiling(self, on: bool) -> None:
+        """Device-wide engine: time each merge writing pass with HIP events."""
+        _check(lib().pbh_set_profiling(self._h, 1 if on else 0))
 
     def traffic(self) -> int:
         """Heap elements read or written by the level operations so far."""

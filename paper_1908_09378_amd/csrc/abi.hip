@@ -388,6 +388,12 @@ int pbh_merge_profile(pbh_t* h, uint64_t* launches, uint64_t* bytes, double* ms)
   return PBH_OK;
 }
 
+int pbh_set_profiling(pbh_t* h, int on) {
+  if (!h) return fail(PBH_EINVAL, "pbh_set_profiling: NULL handle");
+  if (h->wide) wide_set_profiling(h->wide, on != 0);
+  return PBH_OK;
+}
+
 int pbh_traffic(pbh_t* h, uint64_t* elements_out) {
   if (!h || !elements_out) return fail(PBH_EINVAL, "pbh_traffic: NULL argument");
   int rc = pull_state(h);

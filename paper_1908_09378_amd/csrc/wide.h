@@ -45,8 +45,11 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
 // ascending by (key, id); *count_out = number written.
 int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out);
 
-// Totals over the merge writing passes so far: launches, algorithmic bytes
-// (12 B per input and per output element) and HIP-event time.
+// Totals over the merge writing passes timed so far: launches, algorithmic
+// bytes (12 B per input and per output element) and HIP-event time.  Only
+// passes run while profiling is on are timed (the events cost each merge
+// some microseconds).
 void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms);
+void wide_set_profiling(WideScratch* w, bool on);
 
 }  // namespace bkt

@@ -789,7 +789,9 @@ __global__ __launch_bounds__(NT) void k_intake(const u64* keys, const u32* ids, 
 // Mark compaction: marked ids in increasing order -> (cur[id], id); the
 // marks are cleared.  Each thread takes 32 consecutive ids (two 16-byte loads)
 // per round, turned into a 32-bit mask; tile t = ids [t*TILE*32, (t+1)*TILE*32)
-// in WE rounds.
+// in WE rounds.  In the writing pass each round's marked ids are gathered in
+// LDS in order (a scan of the masks' popcounts places them) and then written
+// out coalesced, one output per thread, with cur[id] read alongside.
 __device__ __forceinline__ u32 mark_mask(uint4 m) {
   const u32 w[4] = {m.x, m.y, m.z, m.w};
   u32 bits = 0;
@@ -803,20 +805,26 @@ template <bool WRITE>
 __global__ __launch_bounds__(NT) void k_bits(u8* marks, u32 nwords, u32* tc, const u32* toff, const u64* cur,
                                              u64* uk, u32* uv) {
   __shared__ u32 sw[NT / 64];
+  __shared__ u32 sid[WRITE ? NT * 32 : 1];
   const u32 t = blockIdx.x;
   u32 run = WRITE ? toff[t] : 0u, cnt = 0;
   uint4* m4 = (uint4*)marks;
+  u32 bitsr[WE];
 #pragma unroll
   for (int r = 0; r < WE; ++r) {
     const u64 w = (u64)t * TILE + (u64)r * NT + threadIdx.x;
-    u32 bits = 0;
-    if (w < nwords) bits = mark_mask(m4[2 * w]) | (mark_mask(m4[2 * w + 1]) << 16);
-    u32 pc = (u32)__builtin_popcount(bits);
+    bitsr[r] = w < nwords ? mark_mask(m4[2 * w]) | (mark_mask(m4[2 * w + 1]) << 16) : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < WE; ++r) {
+    const u64 w = (u64)t * TILE + (u64)r * NT + threadIdx.x;
+    u32 bits = bitsr[r];
+    const u32 pc = (u32)__builtin_popcount(bits);
     if constexpr (!WRITE) {
       cnt += pc;
     } else {
       u32 tot;
-      u32 o = run + block_scan<NT>(pc, &tot, sw);
+      u32 o = block_scan<NT>(pc, &tot, sw);  // its barriers also end the previous round's reads of sid
       if (bits) {
         m4[2 * w] = make_uint4(0u, 0u, 0u, 0u);
         m4[2 * w + 1] = make_uint4(0u, 0u, 0u, 0u);
@@ -824,10 +832,13 @@ __global__ __launch_bounds__(NT) void k_bits(u8* marks, u32 nwords, u32* tc, con
       while (bits) {
         const u32 b = (u32)__builtin_ctz(bits);
         bits &= bits - 1;
-        const u32 id = (u32)w * 32u + b;
-        uv[o] = id;
-        uk[o] = cur[id];
-        ++o;
+        sid[o++] = (u32)w * 32u + b;
+      }
+      __syncthreads();
+      for (u32 x = threadIdx.x; x < tot; x += NT) {
+        const u32 id = sid[x];
+        uv[run + x] = id;
+        uk[run + x] = cur[id];
       }
       run += tot;
     }
@@ -995,7 +1006,9 @@ struct WideScratch {
   Partials pt{nullptr, nullptr, nullptr};  // one slot per tile / workgroup (maxtiles, >= GRID_STRIDE)
   u32 maxtiles = 0;
   hipStream_t s = 0;
-  // HIP-event timing of the merge writing pass (the engine's largest kernel)
+  // HIP-event timing of the merge writing pass (the engine's largest kernel),
+  // while profiling is on
+  bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   u64 merge_launches = 0, merge_bytes = 0;
   double merge_ms = 0.0;
@@ -1044,22 +1057,24 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
                      0);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
-  WCHK(hipEventRecord(w->ev0, w->s));
+  if (w->profile) WCHK(hipEventRecord(w->ev0, w->s));
   hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->pt,
                      stats ? 1 : 0);
-  WCHK(hipEventRecord(w->ev1, w->s));
+  if (w->profile) WCHK(hipEventRecord(w->ev1, w->s));
   if (stats)
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->mail_h->total;
   *num_le = stats ? w->mail_h->num_le : 0u;
-  float ms = 0.f;
-  WCHK(hipEventSynchronize(w->ev1));  // already passed: the step has ended
-  WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-  w->merge_ms += ms;
-  w->merge_bytes += 12ull * (total + *m);
-  w->merge_launches += 1;
+  if (w->profile) {
+    float ms = 0.f;
+    WCHK(hipEventSynchronize(w->ev1));  // already passed: the step has ended
+    WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    w->merge_ms += ms;
+    w->merge_bytes += 12ull * (total + *m);
+    w->merge_launches += 1;
+  }
   return 0;
 }
 
@@ -1293,6 +1308,8 @@ int wide_create(WideScratch** out, u32 d) {
   WCHK(hipEventCreateWithFlags(&w->ev1, hipEventDisableSystemFence));
   return wide_reserve(w, 4ull * d);
 }
+
+void wide_set_profiling(WideScratch* w, bool on) { w->profile = on; }
 
 void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms) {
   *launches = w->merge_launches;
