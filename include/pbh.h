@@ -273,9 +273,11 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
  * or 256 when k_rule != 0) runs until every vertex closer than D is settled,
  * which is the
  * same work for every candidate; the three fastest run again to the frontier
- * of n/8 plain rounds, and the fastest there is written back into *opts
- * (d, team, k_max; the other fields, k_scale included, are kept and used
- * for the trials).
+ * of n/8 plain rounds, the two fastest there run to the end (the cost of a
+ * large d grows with the heap, which the early frontiers do not show), and
+ * the faster of those is written back into *opts (d, team, k_max; the other
+ * fields, k_scale included, are kept and used for the trials).  A query that
+ * finishes within a frontier trial skips the later stages.
  * dist_out is used as scratch.  Errors: those of sssp_ex.
  */
 int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,

@@ -896,6 +896,15 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
     for (TuneCand& c : cands)
       if (int rc = trial(c, D[1])) return rc;
     std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
+    // The frontier trials cover the first n/8 settled vertices at most; the
+    // cost of a large d grows with the heap, so the two best are run to the
+    // end and the faster of those wins.
+    if (D[1] != KINF) {
+      if (cands.size() > 2) cands.resize(2);
+      for (TuneCand& c : cands)
+        if (int rc = trial(c, KINF)) return rc;
+      std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
+    }
   }
   const float bscale = user.k_scale > 0.0f ? user.k_scale : 1.0f;
   *mult_out = cands[0].d / maxdeg;
