@@ -286,9 +286,12 @@ int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32
 /*
  * sssp_batch_autotune: picks opts->d_scale (with opts->d = 0), opts->team and
  * opts->k_max for a batch: the largest query (the critical path of the
- * persistent launch) is tuned as by sssp_autotune and its multiple of the
- * maximum out-degree applies to every query.  That query's dist_out is used
- * as scratch.  Errors: those of sssp_ex.
+ * persistent launch) is tuned as by sssp_autotune; its (at most three) best
+ * settings, and every multiple of the maximum out-degree up to d = 2048 with
+ * the best setting's team and k_max (unless that is the plain rule), then
+ * run the whole batch, each query's d being the multiple of its own maximum
+ * out-degree; the fastest launch wins.  Every query's dist_out is used as
+ * scratch.  Errors: those of sssp_ex and sssp_batch.
  */
 int sssp_batch_autotune(const sssp_query *queries, uint32_t nq, sssp_opts *opts, void *stream);
 

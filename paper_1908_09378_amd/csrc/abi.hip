@@ -831,12 +831,14 @@ namespace {
 struct TuneCand {
   u32 d, team, kmax;
   double ms;
-  float scale = 0.0f;  // k_scale of the trial (0: the caller's)
 };
 
+// Ranks candidate settings for one query; *ranked receives at most three,
+// fastest first (the two run to the end, when that stage ran, then the third
+// of the frontier trials), with their d, team and k_max.
 int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
-               uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream, u32* mult_out,
-               u32* kmax_out, u32* maxdeg_out, u32* team_out, float* scale_out) {
+               uint32_t source, uint64_t* dist_out, const sssp_opts& user, void* stream,
+               std::vector<TuneCand>* ranked, u32* maxdeg_out) {
   sssp_opts base = user;
   base.stop_key = 0;
   base.max_rounds = 0;
@@ -874,7 +876,7 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
       teams = {1024};
     for (u32 tm : teams)
       for (int ki = 0; ki < (spec ? 3 : 1); ++ki)
-        cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0, 0.0f});
+        cands.push_back(TuneCand{d, tm, spec ? kms[ki] : user.k_max, 0.0});
   }
   auto trial = [&](TuneCand& c, u64 stop) -> int {
     sssp_opts t = base;
@@ -900,18 +902,16 @@ int tune_query(const uint64_t* offsets, const uint32_t* targets, const uint32_t*
     // cost of a large d grows with the heap, so the two best are run to the
     // end and the faster of those wins.
     if (D[1] != KINF) {
+      std::vector<TuneCand> third(cands.begin() + std::min<size_t>(2, cands.size()), cands.end());
       if (cands.size() > 2) cands.resize(2);
       for (TuneCand& c : cands)
         if (int rc = trial(c, KINF)) return rc;
       std::sort(cands.begin(), cands.end(), [](const TuneCand& a, const TuneCand& b) { return a.ms < b.ms; });
+      cands.insert(cands.end(), third.begin(), third.end());
     }
   }
-  const float bscale = user.k_scale > 0.0f ? user.k_scale : 1.0f;
-  *mult_out = cands[0].d / maxdeg;
-  *kmax_out = cands[0].kmax;
+  *ranked = cands;
   *maxdeg_out = maxdeg;
-  *team_out = cands[0].team;
-  *scale_out = cands[0].scale > 0.0f ? cands[0].scale : bscale;
   return PBH_OK;
 }
 
@@ -922,16 +922,15 @@ extern "C" {
 int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n,
                   uint64_t m, uint32_t source, uint64_t* dist_out, sssp_opts* opts, void* stream) {
   if (!opts) return fail(PBH_EINVAL, "sssp_autotune: opts is NULL");
-  u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
-  float scale = 1.0f;
-  int rc = tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &mult, &kmax, &maxdeg, &team,
-                      &scale);
+  std::vector<TuneCand> ranked;
+  u32 maxdeg = 1;
+  int rc = tune_query(offsets, targets, weights, n, m, source, dist_out, *opts, stream, &ranked, &maxdeg);
   if (rc) return rc;
-  opts->d = maxdeg * mult;
+  opts->d = ranked[0].d;
   opts->d_scale = 0;
-  opts->k_max = kmax;
-  opts->team = team;
-  opts->k_scale = scale;
+  opts->k_max = ranked[0].kmax;
+  opts->team = ranked[0].team;
+  opts->k_scale = opts->k_scale > 0.0f ? opts->k_scale : 1.0f;
   return PBH_OK;
 }
 
@@ -947,16 +946,48 @@ int sssp_batch_autotune(const sssp_query* queries, uint32_t nq, sssp_opts* opts,
   const sssp_query& q = queries[big];
   if (!q.offsets || !q.dist_out || (q.m > 0 && (!q.targets || !q.weights)) || q.n == 0 || q.source >= q.n)
     return fail(PBH_EINVAL, "sssp_batch_autotune: query %u is malformed", big);
-  u32 mult = 1, kmax = 0, maxdeg = 1, team = 0;
-  float scale = 1.0f;
-  int rc = tune_query(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, *opts, stream, &mult, &kmax,
-                      &maxdeg, &team, &scale);
+  std::vector<TuneCand> ranked;
+  u32 maxdeg = 1;
+  int rc = tune_query(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, *opts, stream, &ranked,
+                      &maxdeg);
   if (rc) return rc;
+  // The best settings for the largest query alone need not be the best for
+  // the batch (every query runs with the same multiple, and the largest
+  // query's ranking of close candidates varies from run to run): its (at most
+  // three) best candidates, and every multiple of the maximum out-degree up
+  // to d = 2048 with the winner's team and k_max, run the whole batch, and the
+  // fastest launch wins.  (Not swept when the winner is the plain rule, whose
+  // batch runs are long.)
+  if (ranked[0].kmax != 1)
+    for (u32 mult = 1; (u64)maxdeg * mult <= 2048 || mult == 1; mult *= 2) {
+      TuneCand c{maxdeg * mult, ranked[0].team, ranked[0].kmax, 0.0};
+      bool seen = false;
+      for (const TuneCand& r : ranked) seen = seen || (r.d == c.d && r.team == c.team && r.kmax == c.kmax);
+      if (!seen) ranked.push_back(c);
+    }
+  size_t best = 0;
+  double best_ms = 1e300;
+  for (size_t c = 0; c < ranked.size(); ++c) {
+    sssp_opts t = *opts;
+    t.d = 0;
+    t.d_scale = ranked[c].d / maxdeg;
+    t.k_max = ranked[c].kmax;
+    t.team = ranked[c].team;
+    t.stop_key = 0;
+    t.max_rounds = 0;
+    t.trace_features = nullptr;
+    sssp_stats st;
+    if ((rc = sssp_batch(queries, nq, &t, &st, stream))) return rc;
+    if (st.kernel_ms < best_ms) {
+      best_ms = st.kernel_ms;
+      best = c;
+    }
+  }
   opts->d = 0;
-  opts->d_scale = mult;
-  opts->k_max = kmax;
-  opts->team = team;
-  opts->k_scale = scale;
+  opts->d_scale = ranked[best].d / maxdeg;
+  opts->k_max = ranked[best].kmax;
+  opts->team = ranked[best].team;
+  opts->k_scale = opts->k_scale > 0.0f ? opts->k_scale : 1.0f;
   return PBH_OK;
 }
 
