@@ -44,6 +44,10 @@ def test_null_arguments_are_rejected():
     for bad in (pkg.PbhOpts(3, 0), pkg.PbhOpts(0, 2), pkg.PbhOpts(0, 0, (C.c_uint32 * 6)(1, 0, 0, 0, 0, 0))):
         assert L.pbh_create_ex(C.byref(h), 10, 2, C.byref(bad)) == pkg.PBH_EINVAL
     assert b"pbh_create_ex" in L.pbh_last_error()
+    t = C.c_double(0.0)
+    assert L.pbh_set_profiling(None, 1) == pkg.PBH_EINVAL
+    assert L.pbh_merge_profile(None, C.byref(n), C.byref(n), C.byref(t)) == pkg.PBH_EINVAL
+    assert L.pbh_traffic(None, C.byref(n)) == pkg.PBH_EINVAL
 
 
 def test_sssp_rejects_bad_sizes_before_device_work():

@@ -85,6 +85,53 @@ def test_wide_engine_multi_tile(seed):
     _check_levels(h, d)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_wide_engine_duplicate_heavy(seed):
+    """Batches of 3d pairs over fewer ids than that (every id several times
+    in a batch), few distinct keys (ties decided by id), and extractions in
+    between that leave stale copies in deeper levels: the merges' duplicate
+    deletion across tile edges, with and without a live copy."""
+    cap, d = [3000, 5000, 9000][seed], 2048
+    print(f"[heap] wide duplicate-heavy seed={seed} cap={cap}", flush=True)
+    h = _script(cap, d, W.random_script(30, cap, 3 * d, [100, 7, 1 << 20][seed], 70 + seed), engine=pkg.ENGINE_WIDE,
+                schedule=seed % 2)
+    _check_levels(h, d)
+
+
+def test_merge_profiling_switch():
+    """pbh_set_profiling: merge writing passes are timed only while it is
+    on, and the results are the same either way."""
+    cap, d = 60000, 4096
+    ops = W.random_script(12, cap, 3 * d, 1 << 40, 123)
+    h = pkg.Heap(cap, d, pkg.ENGINE_WIDE)
+    o = oracle.PQ(cap)
+    kmax = max([op[1] for op in ops if op[0] == "extract"] + [1])
+    ko = torch.empty(kmax, dtype=torch.int64, device=DEV)
+    io = torch.empty(kmax, dtype=torch.int32, device=DEV)
+    seen = []
+    for j, op in enumerate(ops):
+        h.set_profiling(j % 2 == 1)
+        before = h.merge_profile()
+        if op[0] == "update":
+            h.bulk_update(dev64(op[1]), dev32(op[2]))
+            o.bulk_update(op[1], op[2])
+        else:
+            n = h.extract_min(op[1], ko, io)
+            ek, ei = o.extract_min(op[1])
+            assert np.array_equal(host64(ko[:n]), ek) and np.array_equal(host32(io[:n]), ei)
+        after = h.merge_profile()
+        grew = after["launches"] - before["launches"]
+        if j % 2 == 0:
+            assert grew == 0 and after["ms"] == before["ms"] and after["bytes"] == before["bytes"]
+        else:
+            seen.append(grew)
+            assert (grew == 0) == (after["ms"] == before["ms"])
+            if grew:
+                assert after["bytes"] > before["bytes"]
+    assert sum(seen) > 0
+    assert h.size() == o.size()
+
+
 def test_invariants_after_ops():
     h = _script(500, 4, W.random_script(40, 500, 30, 1000, 77))
     L = h.debug_levels()
