@@ -11,10 +11,13 @@
 //       as per-workgroup partials folded by k_reduce.
 //   k_part<false> / k_scan (three arrays) / k_part<true>
 //       Stable three-way split by two (key, id) pivots.
-//   k_sel_*
+//   k_sel_pass / k_sel_collect
 //       Select: radix selection on the 96-bit (key, id) value, 8 bits per
 //       pass from the first bit where the keys differ, until at most 256
-//       candidates remain; those are gathered and ranked in one workgroup.
+//       candidates remain; those are gathered and ranked.  The last
+//       workgroup of a pass makes its pick, the last one of the gather ranks
+//       the candidates; the split that follows reads the result on the
+//       device, so Select and split are one host step.
 //   k_intake / k_bits<false> / k_bits<true>
 //       BulkUpdate intake: atomicMin on the current keys, a mark byte per id
 //       whose key dropped, and their compaction into U sorted by id.
@@ -46,7 +49,9 @@ constexpr int SEL_BITS = 8;
 constexpr int SEL_BINS = 1 << SEL_BITS;  // one bin per thread of the pick kernel
 constexpr u32 CANDMAX = NT;              // candidates ranked by one workgroup
 constexpr int GRID_STRIDE = 2048;        // workgroups of the grid-stride kernels
-constexpr int GRID_HIST = 512;           // workgroups of a Select pass (each flushes <= 256 atomics)
+constexpr int GRID_HIST = 512;           // workgroups of a Select pass or gather (each flushes <= 256
+                                         // atomics, and one on the shared pass counter: about 10 ns
+                                         // each on one address, 2048 workgroups measured 20 us)
 
 // Device-side state of a selection (read and written by the Select kernels)
 // and the key range of the array it runs on.
@@ -61,6 +66,7 @@ struct Ctl {
   int sfail;    // the gather ran before the passes were done
   int sbad;     // no bin held the rank (never expected)
   u32 sncand;
+  u32 passdone;  // workgroups finished with the current pass (the last one picks)
   u32 shist[SEL_BINS];
 };
 
@@ -451,11 +457,26 @@ struct PArgs {
   const u64* live;  // class-0 elements whose key is not live[id] are dropped
   u64* ok[3];
   u32* ov[3];
+  // When set, the first pivot is min(the element Select published in this
+  // box, (p1k, p1v)), and a failed Select (sfail / sbad) splits nothing.
+  const Mail* sel;
 };
 
-__device__ __forceinline__ u32 pclass(const PArgs& a, u64 k, u32 v) {
+// The first pivot: (p1k, p1v), or its minimum with the Select result; false:
+// the Select failed, nothing is split.  (The arguments stay untouched: a
+// modified copy of them, indexed by class, would live in scratch memory.)
+__device__ __forceinline__ bool part_pivot(const PArgs& a, KV* p1) {
+  *p1 = KV{a.p1k, a.p1v};
+  if (!a.sel) return true;
+  if (a.sel->sfail || a.sel->sbad) return false;
+  const KV s{a.sel->rk, a.sel->rv};
+  if (kv_less(s, *p1)) *p1 = s;
+  return true;
+}
+
+__device__ __forceinline__ u32 pclass(const PArgs& a, KV p1, u64 k, u32 v) {
   KV e{k, v};
-  u32 c = kv_le(e, KV{a.p1k, a.p1v}) ? 0u : (kv_le(e, KV{a.p2k, a.p2v}) ? 1u : 2u);
+  u32 c = kv_le(e, p1) ? 0u : (kv_le(e, KV{a.p2k, a.p2v}) ? 1u : 2u);
   if (c == 0 && a.live && a.live[v] != k) c = 3;
   return c;
 }
@@ -466,6 +487,8 @@ template <bool WRITE>
 __global__ __launch_bounds__(NT) void k_part(PArgs a, u32* tc, const u32* toff, u32 stride) {
   __shared__ u32 sw[NT / 64];
   const u32 t = blockIdx.x;
+  KV p1;
+  const u32 n = part_pivot(a, &p1) ? a.n : 0u;  // a failed Select: every element counts as dropped
   const u64 base = (u64)t * TILE;
   u32 c01 = 0, c2 = 0;
   u32 run[3] = {0, 0, 0};
@@ -479,15 +502,15 @@ __global__ __launch_bounds__(NT) void k_part(PArgs a, u32* tc, const u32* toff, 
 #pragma unroll
   for (int r = 0; r < WE; ++r) {
     const u64 x = base + (u64)r * NT + threadIdx.x;
-    kk[r] = x < a.n ? a.k[x] : 0;
-    vv[r] = x < a.n ? a.v[x] : 0;
+    kk[r] = x < n ? a.k[x] : 0;
+    vv[r] = x < n ? a.v[x] : 0;
   }
 #pragma unroll
   for (int r = 0; r < WE; ++r) {
     const u64 x = base + (u64)r * NT + threadIdx.x;
     const u64 k = kk[r];
     const u32 v = vv[r];
-    const u32 c = x < a.n ? pclass(a, k, v) : 3u;
+    const u32 c = x < n ? pclass(a, p1, k, v) : 3u;
     if constexpr (!WRITE) {
       c01 += c == 0 ? 1u : (c == 1 ? 1u << 16 : 0u);
       c2 += c == 2;
@@ -531,79 +554,129 @@ __device__ __forceinline__ u32 sel_digit(u64 k, u32 v, int p, int w) {
   return (u32)(((k << 32) | v) >> p) & mask;
 }
 
-// Starts a selection of the element of rank r (1-based) among n, whose keys
-// lie in [ctl->kmin, ctl->kmax].
-__global__ __launch_bounds__(NT) void k_sel_init(Ctl* c, u32 r, u32 n) {
-  for (int b = threadIdx.x; b < SEL_BINS; b += NT) c->shist[b] = 0;
-  if (threadIdx.x == 0) {
-    const u64 mn = c->kmin, mx = c->kmax;
-    int nb;
-    u64 pk;
-    if (mn == mx) {
-      nb = 64;
-      pk = mn;
-    } else {
-      nb = __builtin_clzll(mn ^ mx);
-      pk = nb ? (mn >> (64 - nb)) << (64 - nb) : 0ull;
-    }
-    c->spk = pk;
-    c->spv = 0;
-    c->snb = nb;
-    c->srank = r;
-    c->scnt = n;
-    c->sdone = n <= CANDMAX;
-    c->sfail = 0;
-    c->sbad = 0;
-    c->sncand = 0;
-  }
+// Agent-scope atomic loads and stores: coherent across the XCDs' L2 caches
+// within a launch, for words that workgroups of one launch hand to each
+// other (a plain store can stay in one XCD's L2 until the kernel ends).
+__device__ __forceinline__ u32 ld_a32(const u32* p) {
+  return __hip_atomic_load((const u32 PBH_GLB*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 ld_a64(const u64* p) {
+  return __hip_atomic_load((const u64 PBH_GLB*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_a32(u32* p, u32 v) {
+  __hip_atomic_store((u32 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_a64(u64* p, u64 v) {
+  __hip_atomic_store((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(NT) void k_sel_hist(const u64* K, const u32* V, u32 n, Ctl* c) {
+// Is this workgroup the last of the launch to get here?  Each thread first
+// waits for its own memory operations (its atomics have then been performed),
+// then one counter increment per workgroup; the last one sees gridDim.x - 1
+// and resets the counter for the next launch.
+__device__ __forceinline__ bool last_workgroup(u32* ctr, int* s_last) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u32 prev = __hip_atomic_fetch_add((u32 PBH_GLB*)ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = prev == gridDim.x - 1;
+    if (*s_last) st_a32(ctr, 0u);
+  }
+  __syncthreads();
+  return *s_last != 0;
+}
+
+// The starting prefix of a selection of rank r among n elements whose keys
+// lie in [ctl->kmin, ctl->kmax]: the bits the keys share.
+struct SelState {
+  u64 pk;
+  u32 pv;
+  int nb;
+  u32 rank, cnt;
+  int done;
+};
+__device__ __forceinline__ SelState sel_start(const Ctl* c, u32 r, u32 n) {
+  const u64 mn = c->kmin, mx = c->kmax;
+  SelState q;
+  if (mn == mx) {
+    q.nb = 64;
+    q.pk = mn;
+  } else {
+    q.nb = __builtin_clzll(mn ^ mx);
+    q.pk = q.nb ? (mn >> (64 - q.nb)) << (64 - q.nb) : 0ull;
+  }
+  q.pv = 0;
+  q.rank = r;
+  q.cnt = n;
+  q.done = n <= CANDMAX;
+  return q;
+}
+
+// One radix pass of Select (rank r among A[0, n)): every workgroup histograms
+// its share of the elements that match the prefix fixed so far (LDS, then one
+// atomic per non-empty bin); the last workgroup to finish reads the total,
+// moves the bin holding the rank into the prefix, writes the new state to ctl
+// and clears the histogram.  The first pass (`first`) derives the starting
+// prefix from the key range in ctl (every workgroup the same); later passes
+// read the state, and return at once when the selection is done.
+__global__ __launch_bounds__(NT) void k_sel_pass(const u64* K, const u32* V, u32 n, Ctl* c, u32 r, int first) {
+  static_assert(SEL_BINS == NT, "one bin per thread");
   __shared__ u32 h[SEL_BINS];
-  if (c->sdone) return;
-  const u64 pk = c->spk;
-  const u32 pv = c->spv;
-  const int nb = c->snb;
-  const int w = 96 - nb < SEL_BITS ? 96 - nb : SEL_BITS;
-  const int p = 96 - nb - w;
-  for (int b = threadIdx.x; b < SEL_BINS; b += NT) h[b] = 0;
+  __shared__ u32 sw[NT / 64];
+  __shared__ int s_last;
+  SelState q;
+  if (first) {
+    q = sel_start(c, r, n);
+    if (q.done) {  // few enough elements: no pass needed
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->spk = q.pk;
+        c->spv = q.pv;
+        c->snb = q.nb;
+        c->srank = q.rank;
+        c->scnt = q.cnt;
+        c->sdone = 1;
+        c->sbad = 0;
+      }
+      return;
+    }
+  } else {
+    q.done = c->sdone;
+    if (q.done) return;
+    q.pk = c->spk;
+    q.pv = c->spv;
+    q.nb = c->snb;
+    q.rank = c->srank;
+    q.cnt = c->scnt;
+  }
+  const int w = 96 - q.nb < SEL_BITS ? 96 - q.nb : SEL_BITS;
+  const int p = 96 - q.nb - w;
+  h[threadIdx.x] = 0;
   __syncthreads();
   const u64 step = (u64)gridDim.x * NT;
   for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
     u64 k[4];
     u32 v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u64 x = x0 + q * step;
-      k[q] = x < n ? K[x] : KINF;
-      v[q] = x < n ? V[x] : 0u;
+    for (int j = 0; j < 4; ++j) {
+      const u64 x = x0 + j * step;
+      k[j] = x < n ? K[x] : KINF;
+      v[j] = x < n ? V[x] : 0u;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (x0 + q * step < n && sel_match(k[q], v[q], pk, pv, nb)) atomicAdd(&h[sel_digit(k[q], v[q], p, w)], 1u);
+    for (int j = 0; j < 4; ++j)
+      if (x0 + j * step < n && sel_match(k[j], v[j], q.pk, q.pv, q.nb)) atomicAdd(&h[sel_digit(k[j], v[j], p, w)], 1u);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < SEL_BINS; b += NT)
-    if (h[b]) atomic_add32(&c->shist[b], h[b]);
-}
-
-// One pass's pick: bin b (one per thread) holds the sought rank; its digit
-// joins the prefix.  Clears the histogram for the next pass.
-__global__ __launch_bounds__(NT) void k_sel_pick(Ctl* c) {
-  static_assert(SEL_BINS == NT, "one bin per thread");
-  __shared__ u32 sw[NT / 64];
-  if (c->sdone) return;
+  if (h[threadIdx.x]) atomic_add32(&c->shist[threadIdx.x], h[threadIdx.x]);
+  if (!last_workgroup(&c->passdone, &s_last)) return;
+  // the pick, by the last workgroup: bin b (one per thread) holds the rank
   const u32 b = threadIdx.x;
-  const u32 h = c->shist[b];
+  const u32 hb = ld_a32(&c->shist[b]);
   u32 tot;
-  const u32 before = block_scan<NT>(h, &tot, sw);
-  const u32 rank = c->srank;
-  const int nb = c->snb;
-  const int w = 96 - nb < SEL_BITS ? 96 - nb : SEL_BITS;
-  const int p = 96 - nb - w;
-  if (h && before < rank && rank <= before + h) {
-    u64 pk = c->spk;
-    u32 pv = c->spv;
+  const u32 before = block_scan<NT>(hb, &tot, sw);
+  if (hb && before < q.rank && q.rank <= before + hb) {
+    u64 pk = q.pk;
+    u32 pv = q.pv;
     if (p >= 32) {
       pk |= (u64)b << (p - 32);
     } else {
@@ -614,45 +687,82 @@ __global__ __launch_bounds__(NT) void k_sel_pick(Ctl* c) {
     }
     c->spk = pk;
     c->spv = pv;
-    c->snb = nb + w;
-    c->srank = rank - before;
-    c->scnt = h;
-    c->sdone = h <= CANDMAX || nb + w == 96;
+    c->snb = q.nb + w;
+    c->srank = q.rank - before;
+    c->scnt = hb;
+    c->sdone = hb <= CANDMAX || q.nb + w == 96;
+    c->sbad = 0;
   }
-  if (threadIdx.x == 0 && (rank == 0 || rank > tot)) {
+  if (threadIdx.x == 0 && (q.rank == 0 || q.rank > tot)) {
     c->sbad = 1;
     c->sdone = 1;
   }
-  __syncthreads();
-  c->shist[b] = 0;
+  st_a32(&c->shist[b], 0u);
 }
 
-__global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, u32 n, Ctl* c, u64* ck, u32* cv) {
+// Gathers the elements that match the selected prefix (at most CANDMAX) and,
+// in the last workgroup to finish, ranks them by counting: the one with
+// exactly rank-1 smaller candidates is the answer.  Publishes the outcome to
+// the box (sfail: the passes were not done; sbad: a consistency check failed).
+__global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, u32 n, Ctl* c, u64* ck, u32* cv,
+                                                    Mail* box) {
+  __shared__ u64 sk[CANDMAX];
+  __shared__ u32 sv[CANDMAX];
+  __shared__ int s_last;
   const int done = c->sdone;
-  if (blockIdx.x == 0 && threadIdx.x == 0) c->sfail = !done;
-  if (!done) return;
+  if (!done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      box->sfail = 1;
+      box->sbad = 0;
+    }
+    return;
+  }
   const u64 pk = c->spk;
   const u32 pv = c->spv;
   const int nb = c->snb;
   const u64 step = (u64)gridDim.x * NT;
-  for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
-    u64 k[4];
-    u32 v[4];
+  if (!c->sbad)
+    for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
+      u64 k[4];
+      u32 v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u64 x = x0 + q * step;
-      k[q] = x < n ? K[x] : KINF;
-      v[q] = x < n ? V[x] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (x0 + q * step < n && sel_match(k[q], v[q], pk, pv, nb)) {
-        u32 o = atomic_add32(&c->sncand, 1u);
-        if (o < CANDMAX) {
-          ck[o] = k[q];
-          cv[o] = v[q];
-        }
+      for (int j = 0; j < 4; ++j) {
+        const u64 x = x0 + j * step;
+        k[j] = x < n ? K[x] : KINF;
+        v[j] = x < n ? V[x] : 0u;
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (x0 + j * step < n && sel_match(k[j], v[j], pk, pv, nb)) {
+          const u32 o = atomic_add32(&c->sncand, 1u);
+          if (o < CANDMAX) {
+            st_a64(ck + o, k[j]);
+            st_a32(cv + o, v[j]);
+          }
+        }
+    }
+  if (!last_workgroup(&c->passdone, &s_last)) return;
+  const u32 nc0 = ld_a32(&c->sncand), m = nc0 < CANDMAX ? nc0 : CANDMAX;
+  const u32 r = c->srank;
+  if (threadIdx.x < m) {
+    sk[threadIdx.x] = ld_a64(ck + threadIdx.x);
+    sv[threadIdx.x] = ld_a32(cv + threadIdx.x);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    box->sfail = 0;
+    box->sbad = (c->sbad || r == 0 || r > m || nc0 != c->scnt) ? 1 : 0;
+    st_a32(&c->sncand, 0u);
+  }
+  if (threadIdx.x < m) {
+    const u64 k = sk[threadIdx.x];
+    const u32 v = sv[threadIdx.x];
+    u32 below = 0;
+    for (u32 y = 0; y < m; ++y) below += sk[y] < k || (sk[y] == k && sv[y] < v);
+    if (below + 1 == r) {
+      box->rk = k;
+      box->rv = v;
+    }
   }
 }
 
@@ -676,42 +786,6 @@ __device__ void bitonic_lds(u64* k, u32* v) {
       }
       __syncthreads();
     }
-}
-
-// The remaining candidates (<= 256, distinct (key, id)) are ranked by
-// counting: the one with exactly rank-1 smaller candidates is the answer.
-// Publishes the outcome to the host mailbox.
-__global__ __launch_bounds__(NT) void k_sel_finish(Ctl* c, const u64* ck, const u32* cv, Mail* mail) {
-  __shared__ u64 sk[CANDMAX];
-  __shared__ u32 sv[CANDMAX];
-  if (!c->sdone || c->sbad) {
-    if (threadIdx.x == 0) {
-      mail->sfail = !c->sdone;
-      mail->sbad = c->sbad;
-    }
-    return;
-  }
-  const u32 n = c->sncand < CANDMAX ? c->sncand : CANDMAX;
-  const u32 r = c->srank;
-  if (threadIdx.x < n) {
-    sk[threadIdx.x] = ck[threadIdx.x];
-    sv[threadIdx.x] = cv[threadIdx.x];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    mail->sfail = 0;
-    mail->sbad = (r == 0 || r > n || c->sncand != c->scnt) ? 1 : 0;
-  }
-  if (threadIdx.x < n) {
-    const u64 k = sk[threadIdx.x];
-    const u32 v = sv[threadIdx.x];
-    u32 below = 0;
-    for (u32 y = 0; y < n; ++y) below += sk[y] < k || (sk[y] == k && sv[y] < v);
-    if (below + 1 == r) {
-      mail->rk = k;
-      mail->rv = v;
-    }
-  }
 }
 
 __global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Partials pt) {
@@ -1078,47 +1152,51 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   return 0;
 }
 
-// Element of rank r (1-based) among A[0, n); the key range must be in ctl
-// (from the merge that wrote A) unless have_range is false.
-int wselect(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV* out) {
+// Select(A, r) (rank r, 1-based) followed by the three-way split of A at
+// (min(Select(A, r), cap), p2) into O0 / O1 / O2, as one host step: the
+// split reads the selected element on the device.  *p1 = the split's first
+// pivot.  The key range of A must be in ctl (from the merge that wrote A)
+// unless have_range is false.
+int wpartition3_sel(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, const u64* live, u32* n0,
+                    u32* n1, u32* n2, const Mail* sel);
+int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2, Arr O0, Arr O1, Arr O2,
+             const u64* live, KV* p1, u32* n0, u32* n1, u32* n2) {
+  if (n == 0 || r == 0 || r > n) return E_INTERNAL;
   if (!have_range) {
     const u32 gm = grid_for(n);
     hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
   }
-  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(NT), 0, w->s, w->ctl, r, n);
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
   // Each pass fixes 8 more of the 96 bits, so 12 passes (4 rounds of 3)
   // always finish; two or three typically do (three when the keys crowd at
   // one end of their range, as decreased keys do).  Passes after the last
   // needed one return at once.
   for (int round = 0; round < 4; ++round) {
-    for (int p = 0; p < 3; ++p) {
-      hipLaunchKernelGGL(k_sel_hist, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl);
-      hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(NT), 0, w->s, w->ctl);
-    }
-    hipLaunchKernelGGL(k_sel_collect, dim3(g), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v);
-    hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(NT), 0, w->s, w->ctl, w->cand_k, w->cand_v, w->box);
-    if (int rc = launch_ok()) return rc;
-    if (int rc = fetch(w)) return rc;
+    for (int p = 0; p < 3; ++p)
+      hipLaunchKernelGGL(k_sel_pass, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, r, round == 0 && p == 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_sel_collect, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v, w->box);
+    if (int rc = wpartition3_sel(w, A, n, cap, p2, O0, O1, O2, live, n0, n1, n2, w->box)) return rc;
     if (w->mail_h->sbad) return E_INTERNAL;
     if (!w->mail_h->sfail) {
-      *out = KV{w->mail_h->rk, w->mail_h->rv};
+      *p1 = cap;
+      const KV s{w->mail_h->rk, w->mail_h->rv};
+      if (kv_less(s, cap)) *p1 = s;
       return 0;
     }
   }
   return E_INTERNAL;
 }
 
-int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, const u64* live, u32* n0,
-                u32* n1, u32* n2) {
+int wpartition3_sel(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, const u64* live, u32* n0,
+                    u32* n1, u32* n2, const Mail* sel) {
   if (n == 0) {
     *n0 = *n1 = *n2 = 0;
     return 0;
   }
   const u32 nt = cdiv(n, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
-  PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}};
+  PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}, sel};
   hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
   hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part);
   hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
@@ -1128,6 +1206,11 @@ int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr 
   *n1 = w->mail_h->part[1];
   *n2 = w->mail_h->part[2];
   return 0;
+}
+
+int wpartition3(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, Arr O2, const u64* live, u32* n0,
+                u32* n1, u32* n2) {
+  return wpartition3_sel(w, A, n, p1, p2, O0, O1, O2, live, n0, n1, n2, nullptr);
 }
 
 // Sorts X[0, n) by (key, id) into D (n <= 4d; X is overwritten).
@@ -1173,16 +1256,18 @@ int wresolve(WideScratch* w, const Geom& g, HeapState* st, const u64* cur, int i
     a.bsel ^= 1;
     a.nS = 0;
     a.ssel = 0;
-    if (num > cB) {
-      if ((rc = wselect(w, M, m, cB, true, &pi))) return rc;
-      num = cB;
-      touched += m;
-    }
+    const bool sel = num > cB;
+    if (sel) num = cB;
     if (num < m) {
       if (!nx) return E_CAPACITY;
       Arr Lo = lbuf(g, i, a.bsel ^ 1), Hi = lbuf(g, i, 2);
       u32 n0, n1, n2;
-      if ((rc = wpartition3(w, M, m, pi, kv_inf(), Lo, Hi, Hi, nullptr, &n0, &n1, &n2))) return rc;
+      if (sel) {  // p_i <- Select(B_i, 2d*4^i), and the split at it
+        if ((rc = wselpart(w, M, m, cB, true, kv_inf(), kv_inf(), Lo, Hi, Hi, nullptr, &pi, &n0, &n1, &n2))) return rc;
+        touched += m;
+      } else if ((rc = wpartition3(w, M, m, pi, kv_inf(), Lo, Hi, Hi, nullptr, &n0, &n1, &n2))) {
+        return rc;
+      }
       touched += 3ull * m;
       a.bsel ^= 1;
       a.nB = n0;
@@ -1210,16 +1295,19 @@ int wresolve(WideScratch* w, const Geom& g, HeapState* st, const u64* cur, int i
     b.nB = m2;
     if (m2 > 0) {
       const u32 r = cB - a.nB;
-      KV pnew = kv_inf();
-      if (r < m2) {
-        if ((rc = wselect(w, M2, m2, r, true, &pnew))) return rc;
-        touched += m2;
-      }
-      if (kv_less(pn, pnew)) pnew = pn;
       Arr Up = lbuf(g, i, 2), Bk = lbuf(g, i + 1, b.bsel ^ 1), Sk = lbuf(g, i + 1, 3);
       u32 nu, nb1, ns1;
-      // Elements moving up into B_0 are checked for liveness here, all at once.
-      if ((rc = wpartition3(w, M2, m2, pnew, pn, Up, Bk, Sk, i == 0 ? cur : nullptr, &nu, &nb1, &ns1))) return rc;
+      // p_i <- min(Select(B_{i+1}, r), p_{i+1}), and the split at (p_i,
+      // p_{i+1}); elements moving up into B_0 are checked for liveness here,
+      // all at once.
+      KV pnew = pn;
+      if (r < m2) {
+        if ((rc = wselpart(w, M2, m2, r, true, pn, pn, Up, Bk, Sk, i == 0 ? cur : nullptr, &pnew, &nu, &nb1, &ns1)))
+          return rc;
+        touched += m2;
+      } else if ((rc = wpartition3(w, M2, m2, pnew, pn, Up, Bk, Sk, i == 0 ? cur : nullptr, &nu, &nb1, &ns1))) {
+        return rc;
+      }
       touched += 3ull * m2;
       b.bsel ^= 1;
       b.nB = nb1;
@@ -1422,11 +1510,15 @@ int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, 
     const u32 take = (u32)((k - out) < a0.nB ? (k - out) : a0.nB);
     Arr B = lbuf(h->g, 0, a0.bsel), X = lbuf(h->g, 0, 2);
     KV thr = kv_inf();
-    if (take < a0.nB)
-      if (int rc = wselect(w, B, a0.nB, take, false, &thr)) return rc;
     u32 n0, n1, n2;
-    if (int rc = wpartition3(w, B, a0.nB, thr, kv_inf(), X, lbuf(h->g, 0, a0.bsel ^ 1), X, nullptr, &n0, &n1, &n2))
+    if (take < a0.nB) {
+      if (int rc = wselpart(w, B, a0.nB, take, false, kv_inf(), kv_inf(), X, lbuf(h->g, 0, a0.bsel ^ 1), X, nullptr,
+                            &thr, &n0, &n1, &n2))
+        return rc;
+    } else if (int rc = wpartition3(w, B, a0.nB, thr, kv_inf(), X, lbuf(h->g, 0, a0.bsel ^ 1), X, nullptr, &n0, &n1,
+                                    &n2)) {
       return rc;
+    }
     if (n0 != take) return E_INTERNAL;
     if (int rc = wsort(w, X, take, okeys + out, oids + out)) return rc;
     hipLaunchKernelGGL(k_absent, dim3(grid_for(take)), dim3(NT), 0, w->s, (const u32*)(oids + out), (u64)take,
