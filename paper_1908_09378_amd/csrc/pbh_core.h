@@ -1149,7 +1149,18 @@ PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
   }
   t.sync();
   float y = bf16r(b3[0]);
-  for (int j = 0; j < MLP_H; ++j) y += t.sh->mlp_z[j];
+  if constexpr (T::kNT >= 64) {
+    // every wavefront sums the 64 output terms with a butterfly of lane
+    // exchanges (the same order in every lane), instead of each thread
+    // reading all 64 from LDS one after another
+    static_assert(MLP_H == 64, "one output term per lane");
+    float z = t.sh->mlp_z[t.lane()];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
+    y += z;
+  } else {
+    for (int j = 0; j < MLP_H; ++j) y += t.sh->mlp_z[j];
+  }
   t.sync();
   return y * sd[NFEAT];
 }
