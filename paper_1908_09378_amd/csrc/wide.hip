@@ -22,8 +22,8 @@
 //       BulkUpdate intake: atomicMin on the current keys, a mark byte per id
 //       whose key dropped, and their compaction into U sorted by id.
 //   k_tsort / k_spart / k_smerge
-//       Sorting the extracted minima by (key, id): bitonic sort of tiles in
-//       LDS, then merge passes.
+//       Sorting the extracted minima by (key, id): tiles sorted in registers
+//       and LDS (per-thread sort, then merge-path rounds), then merge passes.
 //   k_absent
 //       Marks extracted ids absent.
 // The few results the host needs after a step (sizes, the selected element)
@@ -766,28 +766,6 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
   }
 }
 
-// Bitonic sort of N (key, id) pairs in LDS by (key, id), NTH threads.
-template <u32 N, int NTH>
-__device__ void bitonic_lds(u64* k, u32* v) {
-  for (u32 size = 2; size <= N; size <<= 1)
-    for (u32 stride = size >> 1; stride > 0; stride >>= 1) {
-      for (u32 q = threadIdx.x; q < N / 2; q += NTH) {
-        const u32 lo = 2 * q - (q & (stride - 1)), hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        u64 ka = k[lo], kb = k[hi];
-        u32 va = v[lo], vb = v[hi];
-        const bool gt = ka > kb || (ka == kb && va > vb);
-        if (gt == up) {
-          k[lo] = kb;
-          k[hi] = ka;
-          v[lo] = vb;
-          v[hi] = va;
-        }
-      }
-      __syncthreads();
-    }
-}
-
 __global__ __launch_bounds__(NT) void k_minmax(const u64* K, u32 n, Partials pt) {
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   u64 lo = KINF, hi = 0;
@@ -930,9 +908,28 @@ __global__ void k_absent(const u32* ids, u64 n, u64* cur) {
 
 // ------------------------------------------------------------------ sort by (key, id)
 
+// Compare-exchange by (key, id).
+__device__ __forceinline__ void cx(u64& ka, u32& va, u64& kb, u32& vb) {
+  if (ka > kb || (ka == kb && va > vb)) {
+    const u64 tk = ka;
+    const u32 tv = va;
+    ka = kb;
+    va = vb;
+    kb = tk;
+    vb = tv;
+  }
+}
+
+// Sorts each tile of TILE (key, id) pairs by (key, id): every thread sorts
+// its WE consecutive elements in registers (odd-even transposition), then
+// rounds merge the runs of WE, 2WE, ..., TILE/2 pairwise in LDS (ping-pong
+// buffers), each thread producing its WE consecutive outputs after one
+// merge-path search.  About a quarter of the LDS accesses of a bitonic sort
+// of the tile in LDS, and 8 barriers instead of 66.  Padding (KINF, VINF)
+// sorts last and is not written.
 __global__ __launch_bounds__(NT) void k_tsort(const u64* sk_, const u32* sv_, u32 n, u64* dk, u32* dv) {
-  __shared__ u64 sk[TILE];
-  __shared__ u32 sv[TILE];
+  __shared__ u64 bk[2][TILE];
+  __shared__ u32 bv[2][TILE];
   const u64 base = (u64)blockIdx.x * TILE;
   {
     u64 lk[WE];
@@ -945,17 +942,71 @@ __global__ __launch_bounds__(NT) void k_tsort(const u64* sk_, const u32* sv_, u3
     }
 #pragma unroll
     for (int q = 0; q < WE; ++q) {
-      sk[threadIdx.x + q * NT] = lk[q];
-      sv[threadIdx.x + q * NT] = lv[q];
+      bk[0][threadIdx.x + q * NT] = lk[q];
+      bv[0][threadIdx.x + q * NT] = lv[q];
     }
   }
   __syncthreads();
-  bitonic_lds<TILE, NT>(sk, sv);
-  for (u32 x = threadIdx.x; x < TILE; x += NT) {
+  const u32 o0 = threadIdx.x * WE;
+  u64 k[WE];
+  u32 v[WE];
+#pragma unroll
+  for (int q = 0; q < WE; ++q) {
+    k[q] = bk[0][o0 + q];
+    v[q] = bv[0][o0 + q];
+  }
+#pragma unroll
+  for (int r = 0; r < WE; ++r)
+#pragma unroll
+    for (int i = r & 1; i + 1 < WE; i += 2) cx(k[i], v[i], k[i + 1], v[i + 1]);
+  int cur = 1;
+  for (u32 L = WE; L < TILE; L *= 2, cur ^= 1) {
+    // (buffer cur was last read two rounds ago, before the previous barrier)
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      bk[cur][o0 + q] = k[q];
+      bv[cur][o0 + q] = v[q];
+    }
+    __syncthreads();
+    const u32 pb = (o0 / (2 * L)) * (2 * L), diag = o0 - pb;
+    const u64* ak = bk[cur] + pb;
+    const u32* av = bv[cur] + pb;
+    const u64* bk2 = ak + L;
+    const u32* bv2 = av + L;
+    u32 i = mpath<true>(ak, av, L, bk2, bv2, L, diag), j = diag - i;
+    u64 xa = i < L ? ak[i] : KINF, xb = j < L ? bk2[j] : KINF;
+    u32 ya = i < L ? av[i] : VINF, yb = j < L ? bv2[j] : VINF;
+#pragma unroll
+    for (int q = 0; q < WE; ++q) {
+      const bool ta = i < L && (j >= L || xa < xb || (xa == xb && ya <= yb));
+      if (ta) {
+        k[q] = xa;
+        v[q] = ya;
+        ++i;
+        xa = i < L ? ak[i] : KINF;
+        ya = i < L ? av[i] : VINF;
+      } else {
+        k[q] = xb;
+        v[q] = yb;
+        ++j;
+        xb = j < L ? bk2[j] : KINF;
+        yb = j < L ? bv2[j] : VINF;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < WE; ++q) {
+    bk[cur][o0 + q] = k[q];
+    bv[cur][o0 + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < WE; ++q) {
+    const u32 x = threadIdx.x + (u32)q * NT;
     const u64 g = base + x;
     if (g < n) {
-      dk[g] = sk[x];
-      dv[g] = sv[x];
+      dk[g] = bk[cur][x];
+      dv[g] = bv[cur][x];
     }
   }
 }
