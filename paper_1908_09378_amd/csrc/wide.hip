@@ -1,14 +1,15 @@
 // Device-wide engine of the parallel bucket heap (see wide.h).
 //
 // Kernels (256 threads per workgroup, tiles of 2048 elements):
-//   k_mpart / k_merge<false> / k_scan / k_merge<true>
+//   k_merge<false> / k_scan / k_merge<true>
 //       Merge of two id-sorted arrays with DeleteDuplicates (Section 2.1):
-//       merge-path split points per tile, a counting pass, a scan of the tile
-//       counts, and a writing pass in which every element finds its position
-//       by a binary search in the other input's window and stores itself
-//       directly.  The writing pass can also count outputs <= a pivot (the
-//       count in Resolve's EMPTY step) and the key range (the start of Select),
-//       as per-workgroup partials folded by k_reduce.
+//       a counting pass (which also finds each tile's merge-path split
+//       points), a scan of the tile counts, and a writing pass; in both passes
+//       each thread walks 8 consecutive merge positions from one merge-path
+//       search in LDS, and the writing pass stores its outputs through an
+//       LDS transpose.  The writing pass can also count outputs <= a pivot
+//       (the count in Resolve's EMPTY step) and the key range (the start of
+//       Select), as per-workgroup partials folded by k_reduce.
 //   k_part<false> / k_scan (three arrays) / k_part<true>
 //       Stable three-way split by two (key, id) pivots.
 //   k_sel_pass / k_sel_collect
@@ -234,17 +235,9 @@ __device__ __forceinline__ bool pair_keep(const MArgs& a, u64 ka, u64 kb, u32 v,
   return true;
 }
 
-// Split points of the tiles (one wavefront per split, SPW per workgroup).
+// Split searches per workgroup of the sort's partition kernel (one
+// wavefront each).
 constexpr u32 SPW = NT / 64;
-__global__ __launch_bounds__(NT) void k_mpart(const u32* av, u32 na, const u32* bv, u32 nb, u32 ntiles, u32* part) {
-  const u32 t = blockIdx.x * SPW + (threadIdx.x >> 6);
-  if (t > ntiles) return;
-  const u64 total = (u64)na + nb;
-  const u64 dg = (u64)t * TILE;
-  const u32 diag = (u32)(dg < total ? dg : total);
-  const u32 i = mpath_wave<false>((const u64*)nullptr, av, na, (const u64*)nullptr, bv, nb, diag);
-  if ((threadIdx.x & 63u) == 0) part[t] = i;
-}
 
 // One tile of merge(A, B) by id with DeleteDuplicates: the outputs at merge
 // positions [t*TILE, (t+1)*TILE), whose inputs are A[i0, i1) and B[j0, j1)
@@ -271,8 +264,8 @@ struct Partials {
 };
 
 template <bool WRITE>
-__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcnt, const u32* toff, Partials pt,
-                                              int stats) {
+__global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* part_out, u32* tcnt, const u32* toff,
+                                              Partials pt, int stats) {
   constexpr u32 NONE = 0xFFFFFFFFu;  // exhausted input (ids are < 2^32 - 1)
   constexpr u32 PAD = WRITE ? TILE / 8 : 0;  // room for the transposed index o + o/8
   __shared__ u32 sv[TILE + PAD];
@@ -281,7 +274,29 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* tcn
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   const u32 t = blockIdx.x, total = a.na + a.nb;
   const u32 d0 = t * TILE, d1 = min(d0 + TILE, total);
-  const u32 i0 = part[t], i1 = part[t + 1];
+  u32 i0, i1;
+  if constexpr (!WRITE) {
+    // The counting pass finds its tile's split points itself (wavefronts 0
+    // and 1, one 65-way search each) and records them for the writing pass.
+    __shared__ u32 ssplit[2];
+    const u32 wv = threadIdx.x >> 6;
+    if (wv < 2) {
+      const u64 dg = (u64)(t + wv) * TILE;
+      const u32 diag = (u32)(dg < total ? dg : total);
+      const u32 i = mpath_wave<false>((const u64*)nullptr, a.av, a.na, (const u64*)nullptr, a.bv, a.nb, diag);
+      if ((threadIdx.x & 63u) == 0) ssplit[wv] = i;
+    }
+    __syncthreads();
+    i0 = ssplit[0];
+    i1 = ssplit[1];
+    if (threadIdx.x == 0) {
+      part_out[t] = i0;
+      if (t + 1 == gridDim.x) part_out[t + 1] = i1;
+    }
+  } else {
+    i0 = part[t];
+    i1 = part[t + 1];
+  }
   const u32 j0 = d0 - i0, j1 = d1 - i1;
   const u32 nA = i1 - i0, nT = d1 - d0, nB = nT - nA;
   {
@@ -1178,13 +1193,12 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   const u32 nt = cdiv(total, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
-  hipLaunchKernelGGL(k_mpart, dim3(cdiv(nt + 1, SPW)), dim3(NT), 0, w->s, A.v, na, B.v, nb, nt, w->part);
-  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, w->part, w->tc, (const u32*)nullptr, w->pt,
-                     0);
+  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
+                     (const u32*)nullptr, w->pt, 0);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
   if (w->profile) WCHK(hipEventRecord(w->ev0, w->s));
-  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, w->toff, w->pt,
-                     stats ? 1 : 0);
+  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, (u32*)nullptr, w->toff,
+                     w->pt, stats ? 1 : 0);
   if (w->profile) WCHK(hipEventRecord(w->ev1, w->s));
   if (stats)
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
