@@ -501,6 +501,14 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       p.spec.uv = g_sssp_list.v;
       p.spec.tk = g_sssp_list.k + (u64)kmax * d;
       p.spec.tv = g_sssp_list.v + (u64)kmax * d;
+      // the LDS left after the levels holds the round's list for the intake
+      // sort when it fits (two buffers, 12 B per pair each)
+      const u64 room = (budget - lds) / 24u;
+      const u64 lcap = std::min<u64>(room, (u64)kmax * d);
+      if (lcap >= 256) {
+        p.spec.lcap = (u32)lcap;
+        lds += (size_t)lcap * 24u;
+      }
     }
     if (o.trace_features) {
       if (!o.trace_keys || !o.trace_ids || !o.trace_count || o.trace_every == 0)

@@ -1033,6 +1033,9 @@ struct SpecCfg {
   u64 stop_key;
   u32 max_rounds;
   float kscale;  // learned rule: multiplies log2 k
+  // LDS room for the round's list after the LDS levels: two buffers of lcap
+  // pairs (keys, then ids); 0 = the intake sorts in global memory
+  u32 lcap;
 };
 
 struct SsspCounters {
@@ -1287,6 +1290,62 @@ PBH_INL u32 intake_list(const T& t, GA U, u32 n, GA W, const u64* dist, int idbi
   return m;
 }
 
+// intake_list with the filtered pairs sorted in LDS (two buffers L1, L2 of at
+// least n pairs): the filter reads U and dist, the radix sort by id runs
+// between L1 and L2, and the deduplicated list is written back to U.
+template <class T, class GA, class LA>
+PBH_INL u32 intake_list_lds(const T& t, GA U, u32 n, LA L1, LA L2, const u64* dist, int idbits) {
+  u32 out = 0;
+  constexpr int RE = 4;
+  for (u32 base = 0; base < n; base += (u32)T::kNT * RE) {
+    u64 k[RE], c[RE];
+    u32 v[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      k[r] = x < n ? U.k[x] : 0;
+      v[r] = x < n ? U.v[x] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      c[r] = x < n ? t.load_cur(dist + v[r]) : ~k[r];
+    }
+    u32 cnt = 0;
+#pragma unroll
+    for (int r = 0; r < RE; ++r) cnt += c[r] == k[r] ? 1u : 0u;
+    u32 tot;
+    u32 o = out + t.scan_excl(cnt, &tot);
+#pragma unroll
+    for (int r = 0; r < RE; ++r)
+      if (c[r] == k[r]) {
+        L1.k[o] = k[r];
+        L1.v[o] = v[r];
+        ++o;
+      }
+    out += tot;
+  }
+  t.sync();
+  const bool in2 = sort_by_id(t, L1, L2, out, idbits);
+  LA S = in2 ? L2 : L1;
+  u32 m = 0;
+  for (u32 base = 0; base < out; base += (u32)T::kNT) {
+    u32 x = base + (u32)t.tid();
+    bool keep = x < out && (x == 0 || S.v[x - 1] != S.v[x]);
+    u64 k = x < out ? S.k[x] : 0;
+    u32 v = x < out ? S.v[x] : 0;
+    u32 tot;
+    u32 o = m + t.scan_excl(keep ? 1u : 0u, &tot);
+    if (keep) {
+      U.k[o] = k;
+      U.v[o] = v;
+    }
+    m += tot;
+  }
+  t.sync();
+  return m;
+}
+
 // One speculative round: extract the `k` smallest of B_0, relax every out-edge
 // of them, collect the improved (dist, v) pairs in the global list U.
 template <class T, class P, class A0>
@@ -1372,8 +1431,20 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
     nu += tot;
   }
   t.sync();
-  G Wt{(decltype(G::k))sc.tk, (decltype(G::v))sc.tv};
-  nu = intake_list(t, U, nu, Wt, dist, idbits);
+  if (sc.lcap != 0 && nu <= sc.lcap) {
+    // the list fits in the LDS after the levels: sort it there
+    using L = typename P::L;
+    unsigned char* lb = reinterpret_cast<unsigned char*>(g.lk) + lvl_off(g.d, g.qlds) * 12ull;
+    L L1, L2;
+    L1.k = (decltype(L1.k))reinterpret_cast<u64*>(lb);
+    L2.k = (decltype(L2.k))reinterpret_cast<u64*>(lb + (u64)sc.lcap * 8u);
+    L1.v = (decltype(L1.v))reinterpret_cast<u32*>(lb + (u64)sc.lcap * 16u);
+    L2.v = (decltype(L2.v))reinterpret_cast<u32*>(lb + (u64)sc.lcap * 20u);
+    nu = intake_list_lds(t, U, nu, L1, L2, dist, idbits);
+  } else {
+    G Wt{(decltype(G::k))sc.tk, (decltype(G::v))sc.tv};
+    nu = intake_list(t, U, nu, Wt, dist, idbits);
+  }
   if (t.tid() == 0) {
     st->L[0].bsel = a0.bsel ^ 1;
     st->L[0].nB = n1;
