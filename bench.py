@@ -313,8 +313,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the bench runs on one GPU only; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
 
     if args.workload == "multi":

@@ -10,7 +10,7 @@
 //   * opq_*       : the priority-queue ADT of Section 1.2 (extractMin / update,
 //                   plus BulkUpdate = update for every element of a batch) as a
 //                   sorted multiset std::set<(key, id)> plus cur[id].
-//                   Readings (also listed in the design doc):
+//                   Readings of the paper:
 //                     - an update whose key is not smaller than the id's current
 //                       key is a no-op (the paper assumes updates only decrease
 //                       priority, footnote in Section 1.2; duplicate resolution
