@@ -6,8 +6,8 @@ with the HIP path (the seeded generators in ``workloads`` are the only common
 module, and they hold none of the method's arithmetic).
 
 * ``PQ``            -- the priority-queue ADT of Section 1.2 (update /
-                       bulk update / batched extractMin) as a sorted multiset
-                       (``oracle.cpp``).
+                       bulk update / delete / batched extractMin) as a sorted
+                       multiset (``oracle.cpp``).
 * ``PQArrays``      -- the same ADT written with numpy arrays (``cur[id]`` plus
                        "the k smallest live (key, id)"), for heap sizes where a
                        std::set per element is too slow.  Pinned against ``PQ``.
@@ -51,6 +51,8 @@ def lib():
         L.opq_destroy.argtypes = [C.c_void_p]
         L.opq_bulk_update.restype = C.c_int64
         L.opq_bulk_update.argtypes = [C.c_void_p, u64p, u32p, C.c_uint64]
+        L.opq_delete.restype = C.c_int64
+        L.opq_delete.argtypes = [C.c_void_p, u32p, C.c_uint64]
         L.opq_extract_min.restype = C.c_uint64
         L.opq_extract_min.argtypes = [C.c_void_p, C.c_uint64, u64p, u32p]
         L.opq_size.restype = C.c_uint64
@@ -96,6 +98,15 @@ class PQ:
             raise ValueError("invalid update (id out of range or key == UINT64_MAX)")
         return int(r)
 
+    def delete(self, ids) -> int:
+        """Delete(e) of Section 1.2 for every listed id (absent ids: no-op);
+        returns how many elements left the queue."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        r = lib().opq_delete(self._h, _p(ids, C.c_uint32), ids.shape[0])
+        if r < 0:
+            raise ValueError("invalid delete (id out of range)")
+        return int(r)
+
     def extract_min(self, k: int):
         k = int(k)
         cap = min(k, self.size())
@@ -135,6 +146,16 @@ class PQArrays:
 
     def size(self) -> int:
         return int(np.count_nonzero(self.cur != INF))
+
+    def delete(self, ids) -> int:
+        """cur[id] = INF for every listed id; returns how many were live."""
+        ids = np.asarray(ids, dtype=np.int64)
+        if ids.size and ids.max() >= self.cur.shape[0]:
+            raise ValueError("invalid delete")
+        u = np.unique(ids)
+        n = int(np.count_nonzero(self.cur[u] != INF))
+        self.cur[u] = INF
+        return n
 
     def extract_min(self, k: int):
         live = np.nonzero(self.cur != INF)[0]

@@ -7,9 +7,9 @@
 // benchmark load it.  It shares no code with the HIP path.
 //
 // Contents
-//   * opq_*       : the priority-queue ADT of Section 1.2 (extractMin / update,
-//                   plus BulkUpdate = update for every element of a batch) as a
-//                   sorted multiset std::set<(key, id)> plus cur[id].
+//   * opq_*       : the priority-queue ADT of Section 1.2 (extractMin / update /
+//                   delete, plus BulkUpdate = update for every element of a
+//                   batch) as a sorted multiset std::set<(key, id)> plus cur[id].
 //                   Readings of the paper:
 //                     - an update whose key is not smaller than the id's current
 //                       key is a no-op (the paper assumes updates only decrease
@@ -20,7 +20,10 @@
 //                       total order on (key, id);
 //                     - a batched extract of k returns the min(k, size) smallest
 //                       elements in ascending order, i.e. k successive
-//                       extractMins with no update in between.
+//                       extractMins with no update in between;
+//                     - delete(id) removes the element with that id if the
+//                       queue holds it and is a no-op otherwise (Section 1.2);
+//                       a batch of deletes is one delete per listed id.
 //   * odijkstra   : Dijkstra's algorithm (Section 1.1) with a binary heap and
 //                   lazy deletion, uint64 distances, UINT64_MAX = unreached,
 //                   relaxation on strictly shorter distance.  Also reports the
@@ -80,6 +83,24 @@ int64_t opq_bulk_update(void* h, const uint64_t* keys, const uint32_t* ids, uint
     }
   }
   return changed;
+}
+
+// Delete(e) for every id of the batch: the element with that id leaves the
+// queue if it is there.  Returns the number removed, or -1 on bad input (an
+// id out of range; nothing is modified then).
+int64_t opq_delete(void* h, const uint32_t* ids, uint64_t count) {
+  Pq* q = static_cast<Pq*>(h);
+  for (uint64_t i = 0; i < count; ++i)
+    if (ids[i] >= q->cur.size()) return -1;
+  int64_t removed = 0;
+  for (uint64_t i = 0; i < count; ++i) {
+    uint32_t id = ids[i];
+    if (q->cur[id] == kInf) continue;
+    q->items.erase({q->cur[id], id});
+    q->cur[id] = kInf;
+    ++removed;
+  }
+  return removed;
 }
 
 // Removes and returns the min(k, size) smallest (key, id), ascending.

@@ -31,6 +31,9 @@ class BrutePQ:
         if i not in self.live or k < self.live[i]:
             self.live[i] = k
 
+    def delete(self, i):
+        self.live.pop(i, None)
+
     def extract(self, k):
         out = []
         for _ in range(k):
@@ -50,6 +53,8 @@ def _run_script(pq, ops):
     for op in ops:
         if op[0] == "update":
             pq.bulk_update(op[1], op[2])
+        elif op[0] == "delete":
+            res.append(pq.delete(op[1]))
         else:
             k, v = pq.extract_min(op[1])
             res.append(list(zip(k.tolist(), v.tolist())))
@@ -79,6 +84,88 @@ def test_pq_arrays_matches_multiset(seed):
     a = _run_script(oracle.PQ(cap), ops)
     b = _run_script(oracle.PQArrays(cap), ops)
     assert a == b
+
+
+def _brute(ops):
+    bp = BrutePQ()
+    expect = []
+    for op in ops:
+        if op[0] == "update":
+            for k, i in zip(op[1].tolist(), op[2].tolist()):
+                bp.update(k, i)
+        elif op[0] == "delete":
+            before = len(bp.live)
+            for i in op[1].tolist():
+                bp.delete(i)
+            expect.append(before - len(bp.live))
+        else:
+            expect.append([tuple(x) for x in bp.extract(op[1])])
+    return expect
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_pq_delete_matches_brute_force(seed):
+    """Scripts mixing bulk updates, deletes (of present and absent ids, with
+    repeats) and batched extracts: every extract sequence and every count of
+    removed elements equals the dictionary brute force."""
+    cap = [1, 5, 17, 64][seed % 4]
+    ops = W.random_script(50, cap, 9, [0, 3, 1000][seed % 3], seed, deletes=True)
+    assert any(op[0] == "delete" for op in ops)
+    got = _run_script(oracle.PQ(cap), ops)
+    exp = _brute(ops)
+    assert [g if isinstance(g, int) else [tuple(x) for x in g] for g in got] == exp
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_pq_arrays_delete_matches_multiset(seed):
+    cap = [3, 40, 300][seed % 3]
+    ops = W.random_script(60, cap, 30, [2, 10**6][seed % 2], 200 + seed, deletes=True)
+    assert _run_script(oracle.PQ(cap), ops) == _run_script(oracle.PQArrays(cap), ops)
+
+
+def test_pq_delete_then_drain_is_a_sort_of_the_rest():
+    """Deleting a set of ids, then extracting everything, gives the sorted
+    (key, id) list of the pairs that were not deleted (library sort)."""
+    keys, ids = W.heap_init_pairs(3000, key_bits=10, seed=8)
+    gone = ids[::3]
+    for cls in (oracle.PQ, oracle.PQArrays):
+        pq = cls(3000)
+        pq.bulk_update(keys, ids)
+        assert pq.delete(gone) == gone.shape[0]
+        assert pq.delete(gone) == 0                                      # already absent
+        k, v = pq.extract_min(5000)
+        keep = np.ones(3000, bool)
+        keep[gone] = False
+        kk, vv = keys[keep[ids]], ids[keep[ids]]
+        order = np.lexsort((vv, kk))
+        assert np.array_equal(k, kk[order]) and np.array_equal(v, vv[order])
+
+
+def test_pq_delete_worked_example():
+    ex = json.load(open(os.path.join(GOLD, "pq_delete_worked_example.json")))
+    for cls in (oracle.PQ, oracle.PQArrays):
+        pq = cls(ex["id_capacity"])
+        for st in ex["steps"]:
+            if st["op"] == "update":
+                p = np.array(st["pairs"], dtype=np.uint64).reshape(-1, 2)
+                pq.bulk_update(p[:, 0], p[:, 1].astype(np.uint32))
+            elif st["op"] == "delete":
+                assert pq.delete(np.array(st["ids"], np.uint32)) == st["removed"]
+            else:
+                k, v = pq.extract_min(st["k"])
+                assert [[int(a), int(b)] for a, b in zip(k, v)] == st["expect"]
+            if "live_after" in st:
+                cur = pq.cur() if cls is oracle.PQ else pq.cur
+                live = {str(i): int(cur[i]) for i in np.nonzero(cur != INF)[0]}
+                assert live == st["live_after"]
+
+
+def test_pq_delete_rejects_bad_input():
+    pq = oracle.PQ(4)
+    pq.bulk_update([3], [1])
+    with pytest.raises(ValueError):
+        pq.delete([0, 4])
+    assert pq.size() == 1                                                # nothing was applied
 
 
 def test_pq_without_updates_is_a_sort():

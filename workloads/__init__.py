@@ -325,16 +325,24 @@ def decrease_batch(live_ids: np.ndarray, live_keys_of, count: int, seed: int, rn
     return (old - dec).astype(np.uint64), ids.astype(np.uint32)
 
 
-def random_script(n_ops: int, id_cap: int, max_batch: int, key_max: int, seed: int):
+def random_script(n_ops: int, id_cap: int, max_batch: int, key_max: int, seed: int, deletes: bool = False):
     """A random script of heap operations for tests:
-    list of ("update", keys, ids) / ("extract", k)."""
-    s = stream_seed(seed, 30)
+    list of ("update", keys, ids) / ("extract", k), and with ``deletes`` also
+    ("delete", ids) (ids drawn from the whole id range, so some are absent)."""
+    s = stream_seed(seed, 31 if deletes else 30)
     ctr = 0
     ops = []
     for _ in range(n_ops):
         r = rand_u64(s, np.array([ctr], dtype=np.uint64))[0]
         ctr += 1
-        if r % np.uint64(3) != 0:
+        if deletes and r % np.uint64(4) == 1:
+            cnt = int(rand_int(s, np.array([ctr], np.uint64), 0, max_batch)[0])
+            ctr += 1
+            c = np.arange(ctr, ctr + cnt, dtype=np.uint64)
+            ctr += cnt
+            ids = rand_int(s, c, 0, id_cap - 1).astype(np.uint32) if cnt else np.zeros(0, np.uint32)
+            ops.append(("delete", ids))
+        elif r % np.uint64(3) != 0:
             cnt = int(rand_int(s, np.array([ctr], np.uint64), 0, max_batch)[0])
             ctr += 1
             c = np.arange(ctr, ctr + 2 * cnt, dtype=np.uint64)
@@ -377,8 +385,19 @@ def rgg_batch(n_graphs: int = 64, sources_per_graph: int = 4, lo_log2: int = 12,
     if workers == 1:
         return [_rgg_item(it) for it in items]
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(_rgg_item, items, chunksize=1)
+    # close + join rather than the context manager, whose exit terminates
+    # (signals) the workers; inside a profiled process that signal is caught
+    # by the profiler's handlers.
+    pool = mp.get_context("fork").Pool(workers)
+    try:
+        out = pool.map(_rgg_item, items, chunksize=1)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
 
 
 def training_graphs(count: int = 200, lo_log2: int = 14, hi_log2: int = 18, seed: int = 70):
