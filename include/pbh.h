@@ -101,6 +101,20 @@ int pbh_bulk_update(pbh_t *h, const uint64_t *keys, const uint32_t *ids, uint64_
 int pbh_extract_min(pbh_t *h, uint64_t k, uint64_t *keys_out, uint32_t *ids_out,
                     uint64_t *count_out);
 
+/*
+ * pbh_delete: Delete(e) of Section 1.2 for each of the count ids (device
+ * array): the element with that id leaves the heap if the heap holds it;
+ * absent ids and repeats are no-ops.  Section 2.1 sends a DEL priority down
+ * the levels that removes matching elements when it meets them in a merge;
+ * here the id's current key becomes "absent", which every merge and every
+ * move into the top bucket treat the same way, and the top bucket is filtered
+ * at once, followed by Resolve(0) and the schedule as after any operation.
+ * Errors: PBH_EINVAL (NULL handle, NULL ids with count > 0, any id >=
+ * id_capacity; nothing is applied), PBH_ECAPACITY, PBH_EDEVICE,
+ * PBH_EINTERNAL.
+ */
+int pbh_delete(pbh_t *h, const uint32_t *ids, uint64_t count);
+
 /* pbh_size: number of elements in the heap (host *size_out). */
 int pbh_size(pbh_t *h, uint64_t *size_out);
 
@@ -302,7 +316,10 @@ int sssp_batch_autotune(const sssp_query *queries, uint32_t nq, sssp_opts *opts,
  * mlp_trace_labels: labels[r] = log2 of the longest prefix of trace record r
  *   (its keys in order) whose keys equal dists[trace_query[r]][id], i.e. how
  *   many minima the round could have pulled with no wasted relaxation.
- *   dists is a device array of per-query distance arrays (final distances).
+ *   dists is a device array of nq per-query distance arrays (final
+ *   distances) and dist_n a device array of their lengths; a record whose
+ *   query index is >= nq or whose ids are not below that query's length is
+ *   rejected with PBH_EINVAL before any label is written.
  * mlp_feature_stats: writes the feature means and standard deviations of
  *   X[n][8] into blob (the mu and sd fields).
  * mlp_grad: gradient of the mean squared error of the model on (X[n][8],
@@ -316,7 +333,8 @@ int sssp_batch_autotune(const sssp_query *queries, uint32_t nq, sssp_opts *opts,
  * Errors: PBH_EINVAL (NULL or empty arguments), PBH_ENOMEM, PBH_EDEVICE.
  */
 int mlp_trace_labels(const uint64_t *trace_keys, const uint32_t *trace_ids, const uint32_t *trace_query,
-                     uint32_t count, const uint64_t *const *dists, float *labels);
+                     uint32_t count, const uint64_t *const *dists, const uint32_t *dist_n, uint32_t nq,
+                     float *labels);
 int mlp_feature_stats(const float *X, uint32_t n, float *blob);
 int mlp_grad(const float *X, const float *Y, uint32_t n, const float *blob, float *grad, float *loss);
 int mlp_train(const float *X, const float *Y, uint32_t n, float *blob, uint32_t batch, uint32_t steps, float lr,

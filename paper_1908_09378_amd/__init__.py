@@ -60,7 +60,7 @@ class SsspQuery(C.Structure):
 
 
 _lib = None
-EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_set_profiling", "pbh_destroy",
+EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_delete", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_set_profiling", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "mlp_infer", "pbh_last_error"]
 
@@ -76,6 +76,7 @@ def lib():
         L.pbh_create.argtypes = [C.POINTER(vp), u32, u32]
         L.pbh_create_ex.argtypes = [C.POINTER(vp), u32, u32, C.POINTER(PbhOpts)]
         L.pbh_bulk_update.argtypes = [vp, vp, vp, u64]
+        L.pbh_delete.argtypes = [vp, vp, u64]
         L.pbh_extract_min.argtypes = [vp, u64, vp, vp, C.POINTER(u64)]
         L.pbh_size.argtypes = [vp, C.POINTER(u64)]
         L.pbh_traffic.argtypes = [vp, C.POINTER(u64)]
@@ -88,7 +89,7 @@ def lib():
         L.sssp_batch.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.sssp_autotune.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), vp]
         L.sssp_batch_autotune.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), vp]
-        L.mlp_trace_labels.argtypes = [vp, vp, vp, u32, vp, vp]
+        L.mlp_trace_labels.argtypes = [vp, vp, vp, u32, vp, vp, u32, vp]
         L.mlp_feature_stats.argtypes = [vp, u32, vp]
         L.mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
         L.mlp_train.argtypes = [vp, vp, u32, vp, u32, u32, C.c_float, C.POINTER(C.c_float)]
@@ -238,6 +239,12 @@ class Heap:
         _check(lib().pbh_bulk_update(self._h, _ptr(keys, 8) if count else None,
                                      _ptr(ids, 4) if count else None, count))
 
+    def delete(self, ids) -> None:
+        """Delete (Section 1.2) of every id in `ids` (uint32 data, device);
+        absent ids are no-ops."""
+        count = ids.numel()
+        _check(lib().pbh_delete(self._h, _ptr(ids, 4) if count else None, count))
+
     def extract_min(self, k: int, keys_out, ids_out) -> int:
         if k and (keys_out.numel() < k or ids_out.numel() < k):
             raise ValueError("output arrays shorter than k")
@@ -290,8 +297,9 @@ def mlp_trace_labels(trace_keys, trace_ids, trace_query, count: int, dists, labe
     sequence of per-query distance tensors (device)."""
     import torch
     ptrs = torch.tensor([d.data_ptr() for d in dists], dtype=torch.int64, device=labels.device)
+    lens = torch.tensor([d.numel() for d in dists], dtype=torch.int32, device=labels.device)
     _check(lib().mlp_trace_labels(_ptr(trace_keys, 8), _ptr(trace_ids, 4), _ptr(trace_query, 4), count,
-                                  _ptr(ptrs, 8), _ptr(labels, 4)))
+                                  _ptr(ptrs, 8), _ptr(lens, 4), len(dists), _ptr(labels, 4)))
 
 
 def mlp_feature_stats(X, blob) -> None:

@@ -333,6 +333,42 @@ int pbh_bulk_update(pbh_t* h, const uint64_t* keys, const uint32_t* ids, uint64_
   return PBH_OK;
 }
 
+int pbh_delete(pbh_t* h, const uint32_t* ids, uint64_t count) {
+  if (!h) return fail(PBH_EINVAL, "pbh_delete: NULL handle");
+  if (count == 0) return PBH_OK;
+  if (!ids) return fail(PBH_EINVAL, "pbh_delete: NULL ids");
+  if (h->host.err) return state_error(h->host);
+  HIPCHK(hipMemset(h->flag, 0, sizeof(u64)));
+  HIPCHK(launch_check_update(nullptr, ids, count, h->id_cap, h->flag, 0));
+  u64 bad = 0;
+  HIPCHK(hipMemcpy(&bad, h->flag, sizeof(u64), hipMemcpyDeviceToHost));
+  if (bad) return fail(PBH_EINVAL, "pbh_delete: id >= id_capacity");
+  if (h->wide) {
+    WideHeap w = wide_view(h);
+    return wide_result(h, wide_delete(h->wide, &w, ids, count));
+  }
+  h->host.aux[1] = h->host.aux[3] = 0;
+  int rc = push_state(h);
+  if (rc) return rc;
+  for (;;) {
+    PbhParams p{};
+    p.g = pbh_geom(h);
+    p.gst = h->gst;
+    p.cur = h->cur;
+    p.id_cap = h->id_cap;
+    p.sched = h->sched;
+    p.idbits = ceil_log2(h->id_cap) < 1 ? 1 : ceil_log2(h->id_cap);
+    p.ids = ids;
+    p.count = count;
+    HIPCHK(launch_pbh_delete(p, 0));
+    if ((rc = pull_state(h))) return rc;
+    if ((rc = state_error(h->host))) return rc;
+    if (h->host.aux[3] == 0) break;
+    if ((rc = pbh_grow(h))) return rc;
+  }
+  return PBH_OK;
+}
+
 int pbh_extract_min(pbh_t* h, uint64_t k, uint64_t* keys_out, uint32_t* ids_out, uint64_t* count_out) {
   if (!h || !count_out) return fail(PBH_EINVAL, "pbh_extract_min: NULL handle or count_out");
   *count_out = 0;
@@ -433,8 +469,15 @@ static Arena g_sssp_list;         // round update lists of speculative rounds
 static SsspDevStats* g_sssp_stats = nullptr;
 static CsrCheck* g_csr = nullptr;
 
-int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
-            uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// sssp_ex with the query index that trace records carry (0 for a single
+// query; a batch re-running one of its queries passes that query's index).
+// The caller holds g_sssp_mu.
+int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
+             uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream, u32 qid) {
   if (!offsets || !dist_out || (m > 0 && (!targets || !weights)))
     return fail(PBH_EINVAL, "sssp: NULL array argument");
   if (n == 0) return fail(PBH_EINVAL, "sssp: n == 0");
@@ -442,7 +485,6 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
   sssp_opts o{};
   if (opts) o = *opts;
   hipStream_t s = (hipStream_t)stream;
-  std::lock_guard<std::mutex> lock(g_sssp_mu);
   if (!g_csr) HIPCHK(hipMalloc(&g_csr, sizeof(CsrCheck)));
   if (!g_sssp_stats) HIPCHK(hipMalloc(&g_sssp_stats, sizeof(SsspDevStats)));
   HIPCHK(hipMemsetAsync(g_csr, 0, sizeof(CsrCheck), s));
@@ -457,10 +499,15 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
   int team = (int)o.team;
   if (team == 0) team = d <= 256 ? 64 : (d <= 4096 ? 256 : 1024);
   if (team != 64 && team != 256 && team != 1024) return fail(PBH_EINVAL, "sssp: team must be 64, 256 or 1024");
-  // Heap capacity: every inserted element is a strict improvement of some
-  // vertex, so at most m + 1 elements are ever inserted.  The default starts
-  // smaller and retries with that bound if a level overflows.
-  u64 safe = m + 1;
+  // Heap capacity: the arena is sized for hcap elements.  With the plain rule
+  // every inserted element is a strict improvement from one scanned edge, so
+  // at most m + 1 are ever inserted; rules that pull ahead re-insert vertices
+  // whose distance improves again, so their insertions are bounded only by
+  // the relaxations.  The default starts at min(m + 1, 4n + 4096); if the
+  // deepest level overflows, the run is repeated with at least one more level
+  // (the plain rule's bound m + 1 first, then 4x per retry) until it fits or
+  // MAXL levels are reached.
+  const u64 safe = m + 1;
   u64 hcap = o.heap_capacity ? o.heap_capacity : (safe < 4ull * n + 4096 ? safe : 4ull * n + 4096);
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -518,7 +565,7 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
       p.spec.trace_v = o.trace_ids;
       p.spec.trace_count = o.trace_count;
       p.spec.trace_q = o.trace_query;
-      p.spec.qid = 0;
+      p.spec.qid = qid;
       p.spec.trace_every = o.trace_every;
       p.spec.trace_cap = o.trace_cap;
     }
@@ -549,11 +596,13 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (ds.err == E_CAPACITY && hcap < safe) {
-      hcap = safe;
+    if (ds.err == E_CAPACITY && q < MAXL) {
+      // at least one more level: the deepest nominal bucket must grow past hcap
+      const u64 grown = std::max<u64>(safe, nomB(d, q - 1) * 4ull);
+      hcap = std::max<u64>(hcap * 4ull, grown);
       continue;
     }
-    if (ds.err == E_CAPACITY) return fail(PBH_ECAPACITY, "sssp: heap levels overflowed");
+    if (ds.err == E_CAPACITY) return fail(PBH_ECAPACITY, "sssp: heap levels overflowed at %d levels", q);
     if (ds.err) return fail(PBH_EINTERNAL, "sssp: device-side heap check failed (code %lld)", ds.err);
     if (stats) {
       std::memset(stats, 0, sizeof *stats);
@@ -572,6 +621,16 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
     }
     return PBH_OK;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
+            uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream) {
+  std::lock_guard<std::mutex> lock(g_sssp_mu);
+  return sssp_run(offsets, targets, weights, n, m, source, dist_out, opts, stats, stream, 0u);
 }
 
 // ------------------------------------------------------------ sssp_batch
@@ -797,7 +856,11 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
     stats->lds_levels = (u32)(lds / 12);
     stats->kernel_ms = ms;
   }
-  // Queries whose heap outgrew its slice run again alone with the safe bound.
+  // Queries whose heap outgrew its slice run again alone, starting from the
+  // plain rule's bound m + 1 (and growing further if that overflows too).
+  // Their trace records keep the query's index; the records of the rounds
+  // the first run traced before it stopped stay as well (the same rounds are
+  // traced again, so those rounds appear twice).
   for (u32 i : redo) {
     const sssp_query& q = queries[i];
     sssp_opts o2 = o;
@@ -805,9 +868,7 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
     o2.team = (u32)team;
     o2.heap_capacity = q.m + 1;
     sssp_stats s2;
-    g_sssp_mu.unlock();
-    int rc = sssp_ex(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, &o2, &s2, stream);
-    g_sssp_mu.lock();
+    int rc = sssp_run(q.offsets, q.targets, q.weights, q.n, q.m, q.source, q.dist_out, &o2, &s2, stream, i);
     if (rc) return rc;
     if (stats) {
       stats->rounds += s2.rounds;

@@ -8,6 +8,7 @@
 //                  then pieces of at most d into S_0, each followed by
 //                  Resolve(0) and the schedule).
 //  k_pbh_extract   batched ExtractMin of a host call.
+//  k_pbh_delete    Delete of a batch of ids of a host call.
 //  k_fill_dist, k_check_csr, k_check_update: grid-wide helpers.
 #include "pbh_launch.h"
 
@@ -45,7 +46,7 @@ __global__ void k_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrChec
 __global__ void k_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad) {
   u64 b = 0;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (u64)gridDim.x * blockDim.x)
-    if (ids[i] >= id_cap || keys[i] == KINF) b = 1;
+    if (ids[i] >= id_cap || (keys && keys[i] == KINF)) b = 1;
   if (b) atomicOr(bad, 1ull);
 }
 
@@ -142,6 +143,17 @@ __global__ __launch_bounds__(NT) void k_pbh_update(PbhParams p) {
   DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
   load_state(t, st, p.gst);
   pbh_update_body<DevTeam<NT>, DevPolicy>(t, p.g, st, p);
+  store_state(t, st, p.gst);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pbh_delete(PbhParams p) {
+  __shared__ TeamShared<NT / 64> ts;
+  __shared__ HeapState st_lds;
+  HeapState PBH_LDS* st = (HeapState PBH_LDS*)&st_lds;
+  DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
+  load_state(t, st, p.gst);
+  pbh_delete_body<DevTeam<NT>, DevPolicy>(t, p.g, st, p);
   store_state(t, st, p.gst);
 }
 
@@ -272,6 +284,11 @@ hipError_t launch_mlp_infer(int team, const float* X, u32 n, const float* blob, 
 
 hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_pbh_update<1024>, dim3(1), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pbh_delete(const PbhParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_pbh_delete<1024>, dim3(1), dim3(1024), 0, s, p);
   return hipGetLastError();
 }
 

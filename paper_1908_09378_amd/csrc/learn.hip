@@ -35,6 +35,22 @@ __device__ __forceinline__ float gelu_d(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * phi;
 }
 
+// Every record names a query < nq, and every traced id (padding keys KINF
+// aside) is a vertex of that query's graph; *bad != 0 otherwise.
+__global__ void k_trace_check(const u64* tk, const u32* tv, const u32* tq, u32 count, const u32* dist_n, u32 nq,
+                              u32* bad) {
+  for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < count; r += gridDim.x * blockDim.x) {
+    const u32 q = tq[r];
+    bool b = q >= nq;
+    if (!b) {
+      const u32 n = dist_n[q];
+      for (int k = 0; k < TRACE_K; ++k)
+        b = b || (tk[(u64)r * TRACE_K + k] != KINF && tv[(u64)r * TRACE_K + k] >= n);
+    }
+    if (b) atomicOr(bad, 1u);
+  }
+}
+
 __global__ void k_trace_labels(const u64* tk, const u32* tv, const u32* tq, u32 count, const u64* const* dists,
                                float* labels) {
   for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < count; r += gridDim.x * blockDim.x) {
@@ -210,11 +226,29 @@ std::mutex g_learn_mu;
 extern "C" {
 
 int mlp_trace_labels(const uint64_t* trace_keys, const uint32_t* trace_ids, const uint32_t* trace_query,
-                     uint32_t count, const uint64_t* const* dists, float* labels) {
+                     uint32_t count, const uint64_t* const* dists, const uint32_t* dist_n, uint32_t nq,
+                     float* labels) {
   if (count == 0) return PBH_OK;
-  if (!trace_keys || !trace_ids || !trace_query || !dists || !labels) return PBH_EINVAL;
+  if (!trace_keys || !trace_ids || !trace_query || !dists || !dist_n || nq == 0 || !labels) return PBH_EINVAL;
   u32 grid = (count + 255) / 256;
   grid = grid > 4096 ? 4096 : grid;
+  std::lock_guard<std::mutex> lock(g_learn_mu);
+  u32* bad = nullptr;
+  LCHK(hipMalloc(&bad, sizeof(u32)));
+  u32 hbad = 0;
+  hipError_t e = hipMemset(bad, 0, sizeof(u32));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_trace_check, dim3(grid), dim3(256), 0, 0, (const u64*)trace_keys, trace_ids, trace_query,
+                       count, dist_n, nq, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(&hbad, bad, sizeof(u32), hipMemcpyDeviceToHost);
+  (void)hipFree(bad);
+  LCHK(e);
+  if (hbad) {
+    snprintf(g_lerr, sizeof g_lerr, "mlp_trace_labels: a record names a query >= nq or an id >= its n");
+    return PBH_EINVAL;
+  }
   hipLaunchKernelGGL(k_trace_labels, dim3(grid), dim3(256), 0, 0, (const u64*)trace_keys, trace_ids, trace_query,
                      count, (const u64* const*)dists, labels);
   LCHK(hipGetLastError());

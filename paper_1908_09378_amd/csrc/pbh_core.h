@@ -1699,6 +1699,52 @@ PBH_INL void pbh_update_body(const T& t, const Geom& g, typename P::SP st, const
   }
 }
 
+// Delete(e) of one call (Section 1.2) for a batch of ids (absent ids: no-op).
+// The paper sends a DEL priority down the levels that removes the matching
+// elements when they meet in a merge.  Here the id's current key is set to
+// "absent" (KINF) instead: every merge and every move into B_0 already drops
+// copies whose key is not the current one (the duplicate reading used for
+// updates), so copies in deeper levels leave when they next meet a merge or
+// move up.  B_0 must hold only live elements, so it is filtered at once; then
+// Resolve(0) and the schedule run, as after any operation.  Resumable like
+// the update: aux[1] = ids marked and B_0 filtered, aux[3] = stopped because a
+// level must be added.
+template <class T, class P>
+PBH_INL void pbh_delete_body(const T& t, const Geom& g, typename P::SP st, const PbhParams& p) {
+  using G = typename P::G;
+  if (st->aux[1] == 0) {
+    u32 gone = 0;
+    for (u64 x = (u64)t.tid(); x < p.count; x += (u64)T::kNT)
+      gone += t.atomic_exch(p.cur + p.ids[x], KINF) != KINF ? 1u : 0u;
+    gone = t.sum(gone);
+    t.fence();
+    t.sync();
+    const Lvl a0 = lvl_load(st, 0);
+    u32 n0 = 0, n1 = 0, n2 = 0;
+    if (a0.nB) {
+      G B = as_arr<G>(lbuf(g, 0, a0.bsel)), O = as_arr<G>(lbuf(g, 0, a0.bsel ^ 1)), X = as_arr<G>(lbuf(g, 0, 2));
+      partition3(t, B, a0.nB, kv_inf(), kv_inf(), O, X, X, &n0, &n1, &n2, p.cur);
+    }
+    if (t.tid() == 0) {
+      if (a0.nB) {
+        st->L[0].bsel = a0.bsel ^ 1;
+        st->L[0].nB = n0;
+        st->elems += (u64)a0.nB + n0;
+      }
+      st->live -= gone;
+      st->aux[1] = 1;
+      fix_ell(st, g.q);
+    }
+    t.sync();
+  }
+  if (need_grow(g, st)) {
+    if (t.tid() == 0) st->aux[3] = 1;
+    t.sync();
+    return;
+  }
+  drive<T, P>(t, g, st, p.cur, p.sched, DRIVE_AFTER);
+}
+
 // Batched ExtractMin of one call: repeatedly take the smallest min(k_left,
 // |B_0|) elements of B_0 (B_0 <= p_0 < everything else, and B_0 holds only
 // live elements), output them sorted by (key, id), mark their ids absent, then

@@ -43,7 +43,9 @@ hipError_t launch_fill_multi(const SsspParams* qs, u32 nq, u32 maxn, u32* counte
 int multi_occupancy(int team, size_t lds);
 hipError_t launch_pbh_update(const PbhParams& p, hipStream_t s);
 hipError_t launch_pbh_extract(const PbhParams& p, hipStream_t s);
+hipError_t launch_pbh_delete(const PbhParams& p, hipStream_t s);
 hipError_t launch_mlp_infer(int team, const float* X, u32 n, const float* blob, float* y, hipStream_t s);
+// keys may be NULL (a delete batch: ids only).
 hipError_t launch_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad,
                                hipStream_t s);
 

@@ -217,6 +217,9 @@ struct DevTeam {
   __device__ __forceinline__ u32 atomic_add32(u32* p, u32 v) const {
     return __hip_atomic_fetch_add((u32 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __device__ __forceinline__ u64 atomic_exch(u64* p, u64 v) const {
+    return __hip_atomic_exchange((u64 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __device__ __forceinline__ u32 atomic_or32(u32* p, u32 v) const {
     return __hip_atomic_fetch_or((u32 PBH_GLB*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -266,6 +269,11 @@ struct HostTeam {
   u32 atomic_add32(u32* p, u32 v) const {
     u32 o = *p;
     *p = o + v;
+    return o;
+  }
+  u64 atomic_exch(u64* p, u64 v) const {
+    u64 o = *p;
+    *p = v;
     return o;
   }
   u64 load_cur(const u64* p) const { return *p; }

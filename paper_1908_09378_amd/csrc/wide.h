@@ -41,6 +41,8 @@ int wide_reserve(WideScratch* w, u64 elems);
 
 // BulkUpdate of `count` pairs (device arrays, already validated).
 int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* ids, u64 count);
+// Delete of `count` ids (device array, already validated).
+int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count);
 // Batched ExtractMin of up to k elements into device arrays okeys/oids,
 // ascending by (key, id); *count_out = number written.
 int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out);

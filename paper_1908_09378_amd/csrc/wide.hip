@@ -25,8 +25,8 @@
 //   k_tsort / k_spart / k_smerge
 //       Sorting the extracted minima by (key, id): tiles sorted in registers
 //       and LDS (per-thread sort, then merge-path rounds), then merge passes.
-//   k_absent
-//       Marks extracted ids absent.
+//   k_absent, k_delete
+//       Mark extracted or deleted ids absent.
 // The few results the host needs after a step (sizes, the selected element)
 // are written by the step's last kernel into host-mapped memory.
 #include "wide.h"
@@ -916,6 +916,21 @@ __global__ __launch_bounds__(NT) void k_bits(u8* marks, u32 nwords, u32* tc, con
   }
 }
 
+// Delete of a batch of ids: cur[id] = KINF; each workgroup counts the ids
+// that were present (the exchange returns the old key, so repeats in the
+// batch count once).
+__global__ __launch_bounds__(NT) void k_delete(const u32* ids, u64 count, u64* cur, Partials pt) {
+  __shared__ u32 sw[NT / 64];
+  u32 gone = 0;
+  for (u64 x = (u64)blockIdx.x * NT + threadIdx.x; x < count; x += (u64)gridDim.x * NT)
+    gone += __hip_atomic_exchange((u64 PBH_GLB*)(cur + ids[x]), KINF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+                    KINF
+                ? 1u
+                : 0u;
+  gone = block_sum<NT>(gone, sw);
+  if (threadIdx.x == 0) pt.cnt[blockIdx.x] = gone;
+}
+
 __global__ void k_absent(const u32* ids, u64 n, u64* cur) {
   for (u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (u64)gridDim.x * blockDim.x)
     cur[ids[x]] = KINF;
@@ -1548,6 +1563,37 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
     c0 += len;
   }
   return 0;
+}
+
+// Delete (Section 1.2) of a batch of ids: their current keys become absent,
+// which every later merge and every move into B_0 treat as a dead copy; B_0
+// is filtered at once (it holds only live elements), then Resolve(0) and the
+// schedule.
+int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count) {
+  HeapState* st = h->st;
+  if (count == 0) return 0;
+  if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
+  const u32 gi = grid_for(count);
+  hipLaunchKernelGGL(k_delete, dim3(gi), dim3(NT), 0, w->s, ids, count, h->cur, w->pt);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
+                     (u32*)nullptr, &w->box->newly, w->ctl);
+  if (int rc = launch_ok()) return rc;
+  const Lvl a0 = st->L[0];
+  if (a0.nB) {
+    Arr B = lbuf(h->g, 0, a0.bsel), O = lbuf(h->g, 0, a0.bsel ^ 1), X = lbuf(h->g, 0, 2);
+    u32 n0, n1, n2;
+    if (int rc = wpartition3(w, B, a0.nB, kv_inf(), kv_inf(), O, X, X, h->cur, &n0, &n1, &n2)) return rc;
+    st->L[0].bsel ^= 1;
+    st->L[0].nB = n0;
+    st->elems += (u64)a0.nB + n0;
+  } else if (int rc = fetch(w)) {
+    return rc;
+  }
+  st->live -= w->mail_h->newly;
+  fix_ell(st, h->g.q);
+  if (int rc = grow_if_needed(w, h)) return rc;
+  wdrive(w, h, DRIVE_AFTER);
+  return st->err;
 }
 
 // Batched ExtractMin: repeatedly the smallest min(k_left, |B_0|) elements of

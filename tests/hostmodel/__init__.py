@@ -37,6 +37,8 @@ def lib():
         L.hm_destroy.argtypes = [C.c_void_p]
         L.hm_update.restype = C.c_int
         L.hm_update.argtypes = [C.c_void_p, u64p, u32p, C.c_uint64]
+        L.hm_delete.restype = C.c_int
+        L.hm_delete.argtypes = [C.c_void_p, u32p, C.c_uint64]
         L.hm_extract.restype = C.c_int
         L.hm_extract.argtypes = [C.c_void_p, C.c_uint64, u64p, u32p, u64p]
         L.hm_levels.argtypes = [C.c_void_p, u32p, C.POINTER(C.c_int), u32p, u32p, u64p, u32p, u64p, u64p]
@@ -68,6 +70,12 @@ class HostHeap:
         rc = lib().hm_update(self.h, _p(keys, C.c_uint64), _p(ids, C.c_uint32), keys.shape[0])
         if rc:
             raise RuntimeError(f"hm_update rc={rc}")
+
+    def delete(self, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        rc = lib().hm_delete(self.h, _p(ids, C.c_uint32), ids.shape[0])
+        if rc:
+            raise RuntimeError(f"hm_delete rc={rc}")
 
     def extract_min(self, k):
         ko = np.zeros(max(k, 1), np.uint64)

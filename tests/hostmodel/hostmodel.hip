@@ -109,6 +109,30 @@ int hm_update(void* hp, const u64* keys, const u32* ids, u64 count) {
   }
 }
 
+int hm_delete(void* hp, const u32* ids, u64 count) {
+  HM* h = static_cast<HM*>(hp);
+  for (u64 i = 0; i < count; ++i)
+    if (ids[i] >= h->id_cap) return -1;
+  if (count == 0) return 0;
+  h->st.aux[1] = h->st.aux[3] = 0;
+  for (;;) {
+    PbhParams p{};
+    p.g = geom(h);
+    p.cur = h->cur.data();
+    p.id_cap = h->id_cap;
+    p.sched = h->sched;
+    p.idbits = ceil_log2(h->id_cap);
+    p.ids = ids;
+    p.count = count;
+    HostTeam t{&h->ts};
+    pbh_delete_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
+    if (h->st.err) return h->st.err;
+    if (h->st.aux[3] == 0) return 0;
+    if (h->q >= MAXL) return -2;
+    grow(h);
+  }
+}
+
 int hm_extract(void* hp, u64 k, u64* ko, u32* io, u64* count) {
   HM* h = static_cast<HM*>(hp);
   h->st.progress = 0;

@@ -34,6 +34,7 @@ def test_null_arguments_are_rejected():
     assert L.pbh_create(None, 10, 2) == pkg.PBH_EINVAL
     assert L.pbh_destroy(None) == pkg.PBH_OK
     assert L.pbh_bulk_update(None, None, None, 1) == pkg.PBH_EINVAL
+    assert L.pbh_delete(None, None, 1) == pkg.PBH_EINVAL
     n = C.c_uint64(0)
     assert L.pbh_extract_min(None, 1, None, None, C.byref(n)) == pkg.PBH_EINVAL
     assert L.sssp(None, None, None, 4, 3, 0, None) == pkg.PBH_EINVAL

@@ -23,6 +23,9 @@ def _script(cap, d, ops, engine=pkg.ENGINE_AUTO, schedule=0):
         if op[0] == "update":
             h.bulk_update(dev64(op[1]), dev32(op[2]))
             o.bulk_update(op[1], op[2])
+        elif op[0] == "delete":
+            h.delete(dev32(op[1]))
+            o.delete(op[1])
         else:
             n = h.extract_min(op[1], ko, io)
             ek, ei = o.extract_min(op[1])
@@ -38,6 +41,65 @@ def test_random_scripts(seed):
     cap = [7, 100, 2000][seed % 3]
     print(f"[heap] script seed={seed} d={d} cap={cap}", flush=True)
     _script(cap, d, W.random_script(50, cap, [d, 4 * d][seed % 2], [5, 10 ** 12][seed % 2], 900 + seed))
+
+
+@pytest.mark.parametrize("engine", [pkg.ENGINE_TEAM, pkg.ENGINE_WIDE])
+@pytest.mark.parametrize("seed", range(8))
+def test_random_scripts_with_deletes(engine, seed):
+    """pbh_delete (Section 1.2) mixed with bulk updates and batched extracts,
+    on both engines: every extract sequence and size equals the oracle's."""
+    d = [1, 3, 8, 32][seed % 4]
+    cap = [7, 100, 2000][seed % 3]
+    print(f"[heap] delete script engine={engine} seed={seed} d={d} cap={cap}", flush=True)
+    _script(cap, d, W.random_script(60, cap, [d, 4 * d][seed % 2], [5, 10 ** 12][seed % 2], 950 + seed,
+                                    deletes=True), engine=engine, schedule=seed % 2)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_wide_engine_deletes_multi_tile(seed):
+    """Deletes of thousands of ids at once on the device-wide engine, with
+    batches spanning many 2048-element tiles."""
+    cap, d = 60000, 4096
+    print(f"[heap] wide multi-tile deletes seed={seed}", flush=True)
+    h = _script(cap, d, W.random_script(30, cap, 3 * d, [1 << 40, 3000][seed], 60 + seed, deletes=True),
+                engine=pkg.ENGINE_WIDE, schedule=seed)
+    _check_levels(h, d)
+
+
+def test_delete_worked_example():
+    import json, os
+    ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pq_delete_worked_example.json")))
+    for engine in (pkg.ENGINE_TEAM, pkg.ENGINE_WIDE):
+        h = pkg.Heap(ex["id_capacity"], 2, engine)
+        ko = torch.empty(8, dtype=torch.int64, device=DEV)
+        io = torch.empty(8, dtype=torch.int32, device=DEV)
+        for st in ex["steps"]:
+            if st["op"] == "update":
+                p = np.array(st["pairs"], dtype=np.uint64).reshape(-1, 2)
+                h.bulk_update(dev64(p[:, 0]), dev32(p[:, 1].astype(np.uint32)))
+            elif st["op"] == "delete":
+                before = h.size()
+                h.delete(dev32(np.array(st["ids"], np.uint32)))
+                assert before - h.size() == st["removed"]
+            else:
+                n = h.extract_min(st["k"], ko, io)
+                got = [[int(a), int(b)] for a, b in zip(host64(ko[:n]), host32(io[:n]))]
+                assert got == st["expect"]
+        h.close()
+
+
+def test_invalid_delete_changes_nothing():
+    for engine in (pkg.ENGINE_TEAM, pkg.ENGINE_WIDE):
+        h = pkg.Heap(10, 2, engine)
+        h.bulk_update(dev64(np.array([5, 6], np.uint64)), dev32(np.array([3, 4], np.uint32)))
+        with pytest.raises(pkg.PBHError) as e:
+            h.delete(dev32(np.array([3, 10], np.uint32)))
+        assert e.value.code == pkg.PBH_EINVAL
+        assert h.size() == 2
+        ko = torch.empty(5, dtype=torch.int64, device=DEV)
+        io = torch.empty(5, dtype=torch.int32, device=DEV)
+        assert h.extract_min(5, ko, io) == 2
+        h.close()
 
 
 def test_worked_example():

@@ -11,7 +11,7 @@ import torch
 import oracle
 import paper_1908_09378_amd as pkg
 import workloads as W
-from gpu_util import DEV, dev32, host32, host64, run_sssp
+from gpu_util import DEV, dev32, dev64, host32, host64, run_sssp
 from oracle import mlp
 
 pytestmark = pytest.mark.gpu
@@ -84,6 +84,66 @@ def test_trace_labels_match_oracle():
     for r in range(m):
         ks = [int(x) for x in K[r] if x != np.uint64(0xFFFFFFFFFFFFFFFF)]
         assert ks == sorted(ks)
+
+
+def test_traced_batch_rerun_keeps_query_index():
+    """A traced batch whose heap slices are too small (heap_capacity = 16)
+    re-runs its queries one by one; their trace records must still name
+    their own query, and every label must equal the oracle's zero-waste
+    label against that query's distances (the graphs differ in n, so a
+    record naming the wrong query would read the wrong distance array)."""
+    gs = [W.grid4(40, 40, 1, 100, seed=31), W.ring_lattice(3000, 16, 1, 1000, seed=32),
+          W.grid8(30, 30, wmax=10000, seed=33)]
+    cap = 1 << 14
+    TK = 32
+    tf = torch.zeros(cap * 8, dtype=torch.float32, device=DEV)
+    tk = torch.zeros(cap * TK, dtype=torch.int64, device=DEV)
+    tv = torch.zeros(cap * TK, dtype=torch.int32, device=DEV)
+    tq = torch.full((cap,), -1, dtype=torch.int32, device=DEV)
+    cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+    qs, keep, dists = [], [], []
+    for g in gs:
+        off, tg, wt = dev64(g.offsets), dev32(g.targets), dev32(g.weights)
+        dist = torch.empty(g.n, dtype=torch.int64, device=DEV)
+        keep.append((off, tg, wt))
+        dists.append(dist)
+        qs.append((off, tg, wt, g.n, g.m, 0, dist))
+    print("[learn] traced batch with re-runs", flush=True)
+    pkg.sssp_batch(qs, trace=(tf, tk, tv, cnt, tq, 5), heap_capacity=16)
+    D = [oracle.dijkstra(g, 0) for g in gs]
+    for q, ref in zip(qs, D):
+        assert np.array_equal(host64(q[6]), ref)
+    m = min(int(cnt.item()), cap)
+    Q = host32(tq)[:m]
+    assert set(Q.tolist()) == {0, 1, 2}
+    lab = torch.empty(m, dtype=torch.float32, device=DEV)
+    pkg.mlp_trace_labels(tk, tv, tq, m, dists, lab)
+    K, V = host64(tk).reshape(-1, TK), host32(tv).reshape(-1, TK)
+    L = lab.cpu().numpy()
+    for r in range(m):
+        assert abs(L[r] - mlp.zero_waste_label(K[r], V[r], D[Q[r]])) < 1e-6
+    # a record naming a query past the list is rejected before any label is written
+    bad = tq.clone()
+    bad[0] = 3
+    lab.fill_(-7.0)
+    with pytest.raises(pkg.PBHError) as e:
+        pkg.mlp_trace_labels(tk, tv, bad, m, dists, lab)
+    assert e.value.code == pkg.PBH_EINVAL
+    assert bool((lab == -7.0).all())
+
+
+@pytest.mark.parametrize("kw", [dict(k_rule=1, k_fixed=64, k_max=64),
+                                dict(k_rule=3, k_max=256)])
+def test_speculative_rules_with_tiny_heap_capacity(kw):
+    """Rules that pull ahead re-insert vertices, so their insertions are
+    bounded by relaxations rather than by m: a run that starts with a heap
+    arena of 16 elements keeps adding levels until it fits, and stays exact."""
+    g = W.grid8(64, 64, wmax=10000, seed=35)
+    if kw["k_rule"] == 3:
+        kw = dict(kw, k_seq=dev32(np.array([256, 1, 200, 3], np.uint32)))
+    print(f"[learn] tiny heap capacity {kw.get('k_rule')}", flush=True)
+    got, st = run_sssp(pkg, g, 0, heap_capacity=16, **kw)
+    assert np.array_equal(got, oracle.dijkstra(g, 0))
 
 
 def test_training_reduces_loss():

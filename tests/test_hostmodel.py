@@ -76,6 +76,58 @@ def test_random_scripts_vs_oracle(seed):
         assert L["live"] == o.size()
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_random_scripts_with_deletes_vs_oracle(seed):
+    """Delete (Section 1.2) mixed with bulk updates and batched extracts:
+    extract sequences and sizes equal the oracle's after every operation, and
+    the level structure keeps its invariants (B_0 holds only live elements,
+    so a deleted id is never extracted)."""
+    d = [1, 2, 3, 4, 7, 16][seed % 6]
+    cap = [5, 40, 300, 1000][seed % 4]
+    maxb = [d, 3 * d, 60][seed % 3]
+    ops = W.random_script(70, cap, maxb, [3, 50, 10 ** 9][seed % 3], 700 + seed, deletes=True)
+    h = HostHeap(cap, d, seed % 2)
+    o = oracle.PQ(cap)
+    for op in ops:
+        if op[0] == "update":
+            h.bulk_update(op[1], op[2])
+            o.bulk_update(op[1], op[2])
+        elif op[0] == "delete":
+            h.delete(op[1])
+            o.delete(op[1])
+        else:
+            k1, v1 = h.extract_min(op[1])
+            k2, v2 = o.extract_min(op[1])
+            assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+        L = check_structure(h, o.cur(), d)
+        assert L["live"] == o.size()
+
+
+def test_delete_everything_then_reinsert():
+    """Deleting every id leaves dead copies in the deeper levels; the heap
+    reports size 0, extracts nothing, and ids inserted again afterwards
+    (some with their old keys) come out exactly once."""
+    n, d = 3000, 8
+    keys, ids = W.heap_init_pairs(n, key_bits=12, seed=4)
+    h = HostHeap(n, d)
+    o = oracle.PQ(n)
+    h.bulk_update(keys, ids)
+    o.bulk_update(keys, ids)
+    h.delete(ids[::2])
+    o.delete(ids[::2])
+    h.delete(np.arange(n, dtype=np.uint32))
+    o.delete(np.arange(n, dtype=np.uint32))
+    assert h.levels()["live"] == 0
+    assert h.extract_min(10)[0].shape[0] == 0
+    back = ids[: n // 3]
+    h.bulk_update(keys[: n // 3], back)
+    o.bulk_update(keys[: n // 3], back)
+    a = h.extract_min(n)
+    b = o.extract_min(n)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert h.levels()["ell"] == -1 or h.levels()["live"] == 0
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_decrease_key_workload_small(seed):
     """The standalone-heap workload shape at small scale: initial load in
