@@ -1,26 +1,39 @@
 """Benchmark: parDijkstra on the parallel bucket heap, 1 MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ring|grid64|grid8|dag|multi|heap|copy]
-                    [--method plain|learned|both]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload all|ring|grid64|grid8|batch|heap|dag|copy] [--no-cpu]
 
-One step = one complete sssp() over the resident graph (every round of the
-hot path: the extraction threshold, extract-min, relaxation, bulk update,
-Resolve schedule).  The
-default workload is the large high-diameter ring lattice: n = 2^20 vertices,
-each linked to its 16 nearest neighbours on each side (m = 33,554,432 directed
-edges), integer weights uniform in [1, 1000], source 0.
+One step of the headline = one complete sssp() over the resident ring
+lattice (n = 2^20 vertices, each linked to its 16 nearest neighbours on each
+side, m = 33,554,432 directed edges, integer weights uniform in [1, 1000],
+source 0) with the learned extraction threshold: every round of the hot path
+(features and MLP, extract-min, relaxation, re-insertion, bulk update, the
+Resolve schedule).  Plain parDijkstra on the same graph (d = the maximum
+out-degree, and d autotuned) is timed beside it.
 
-Prints one JSON line: GTEPS = m / seconds per step, the roofline of the
-round-loop kernel (algorithmic bytes per launch / its HIP-event duration vs
-8 TB/s) and the CPU oracle (single-thread binary-heap Dijkstra) timed on a
-bounded sample of the same workload.  With --method both (the default) the
-value is the learned-threshold rule's and the line also carries plain
-parDijkstra on the same graph ("plain") and the speedup; both runs' distances
-are checked against the oracle.
+The default (--workload all) prints ONE JSON line: the headline (GTEPS =
+m / seconds per step, K timed steps after W warm-up steps, the roofline of
+the round-loop kernel and the single-thread CPU oracle on the same graph) and,
+under "workloads", one record per other configuration, each with its own
+steps, exactness check against the oracle, roofline and CPU baseline:
+
+  grid64   4-neighbour grid 64x64, w ~ U[1,100]: plain and learned;
+  grid8    8-neighbour grid 2048x2048, w log-uniform in [1, 10^4]: learned
+           threshold vs plain parDijkstra;
+  batch    256 queries over 64 random geometric graphs in one launch
+           (learned and plain), with a sample of the same queries run one by
+           one, and the oracle on 1 and on all host threads;
+  heap     the standalone heap: 2^24 ids, 256 rounds of bulk_update(2^20
+           decrease-keys) + extract_min(2^16), every extraction checked.
+
+--workload X runs one of them alone and prints its record as the line.
+Inputs are synthetic and seeded (workloads/), resident in HBM before timing.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,26 +42,231 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSSP GTEPS (m/time) on 1 MI355X: learned-threshold & batched vs plain parDijkstra"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_1908_09378_amd", "csrc")
+KERNEL_SOURCES = ["pbh_core.h", "pbh_team.h", "pbh_launch.h", "kernels.hip", "wide.h", "wide.hip", "learn.hip"]
+
+RING_DESC = "ring lattice n=2^20, 16 neighbours per side, w~U[1,1000], source 0"
+GRID64_DESC = "4-neighbour grid 64x64, w~U[1,100], source 0"
+GRID8_DESC = "8-neighbour grid 2048x2048, w log-uniform [1,1e4], source 0"
+LEARNED_DESC = ("learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) picks how many "
+                "minima each round extracts, improved vertices are re-inserted")
 
 
-def make_graph(name):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- helpers
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the calibrated
+    rocprofv3 counters recorded in profiles/traffic.md -- or None when none
+    were taken, or when the kernel sources changed since (the row's source
+    hash differs from the current one)."""
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_source_sha()
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == kernel and cells[1] == workload and cells[2] == sha:
+            try:
+                return float(cells[3]) + float(cells[4])
+            except ValueError:
+                return None
+    return None
+
+
+def roofline(kernel, workload, abytes, kern_ms, extra=None):
+    achieved = abytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(kernel, workload), "kernel": kernel,
+         "kernel_ms": kern_ms, "algorithmic_bytes": abytes}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def sssp_bytes(st):
+    """Bytes the method must move per launch: per extracted vertex its two CSR
+    offsets (16 B); per scanned edge its target and weight (8 B) and the 8-byte
+    atomicMin on dist; per heap element read or written by the level operations
+    (Merge, DeleteDuplicates, Select, splits) 12 B (u64 key + u32 id)."""
+    return 16 * st["extracted"] + 16 * st["relaxations"] + 12 * st["heap_elems"]
+
+
+def to_dev(g):
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(g.offsets.view(np.int64)).to(dev), torch.from_numpy(g.targets.view(np.int32)).to(dev),
+            torch.from_numpy(g.weights.view(np.int32)).to(dev))
+
+
+def load_blob():
+    import torch
+    from paper_1908_09378_amd import learn
+    return torch.from_numpy(learn.load_model()).to(torch.device("cuda:0"))
+
+
+class Query:
+    """One resident graph + source + distance buffer, and the oracle's answer."""
+
+    def __init__(self, g, src, ref):
+        import torch
+        self.g, self.src, self.ref = g, src, ref
+        self.off, self.tg, self.wt = to_dev(g)
+        self.dist = torch.empty(g.n, dtype=torch.int64, device=torch.device("cuda:0"))
+        torch.cuda.synchronize()
+
+    def run(self, **kw):
+        import paper_1908_09378_amd as pkg
+        return pkg.sssp_ex(self.off, self.tg, self.wt, self.g.n, self.g.m, self.src, self.dist, **kw)
+
+    def exact(self):
+        import numpy as np
+        return bool(np.array_equal(self.dist.cpu().numpy().view(np.uint64), self.ref))
+
+    def timed(self, steps, warmup, label, **kw):
+        """warmup untimed runs, then `steps` timed runs (synchronised on both
+        sides); distances checked after the last one."""
+        import torch
+        for _ in range(warmup):
+            self.run(**kw)
+        torch.cuda.synchronize()
+        stats = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            stats.append(self.run(**kw))
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        ex = self.exact()
+        log(f"{label}: {sec * 1e3:.1f} ms/step over {steps}, {stats[-1]['rounds']} rounds, exact={ex}")
+        return sec, stats, ex
+
+    def record(self, sec, stats, exact, method, workload, steps, warmup):
+        st = stats[-1]
+        kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
+        return {"value": self.g.m / sec / 1e9, "unit": "GTEPS", "steps": steps, "warmup": warmup,
+                "ms_per_step": sec * 1e3, "method": method, "rounds": st["rounds"],
+                "relaxations": st["relaxations"], "extracted": st["extracted"], "updates": st["updates"],
+                "d": st["d"], "team": st["team"], "levels": st["levels"], "lds_levels": st["lds_levels"],
+                "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
+                "roofline": roofline("k_sssp", workload, sssp_bytes(st), kern_ms)}
+
+    def tune(self, **kw):
+        import torch
+        import paper_1908_09378_amd as pkg
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = pkg.sssp_autotune(self.off, self.tg, self.wt, self.g.n, self.g.m, self.src, self.dist, **kw)
+        torch.cuda.synchronize()
+        t["tune_s"] = time.perf_counter() - t0
+        log(f"autotune rule {kw.get('k_rule', 0)}: {t}")
+        return t
+
+
+def cpu_sssp(g, src, budget):
+    import oracle
+    per_run, runs = oracle.time_dijkstra(g, src, budget)
+    return {"value": g.m / per_run / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} full run(s) of single-thread binary-heap Dijkstra on the same graph "
+                      f"({per_run:.2f} s each), host {os.cpu_count()} cpus"}
+
+
+# ----------------------------------------------------------------- workloads
+def run_ring(args):
+    """The headline: learned threshold on the ring lattice, with plain
+    parDijkstra (d = maximum out-degree, and d autotuned) beside it."""
+    import oracle
     import workloads as W
-    if name == "ring":
-        return W.ring_lattice(1 << 20, 16, 1, 1000, seed=2), "ring lattice n=2^20, 16 neighbours per side, w~U[1,1000], source 0"
-    if name == "grid64":
-        return W.grid4(64, 64, 1, 100, seed=1), "4-neighbour grid 64x64, w~U[1,100], source 0"
-    if name == "grid8":
-        return W.grid8(2048, 2048, wmax=10000, seed=4), "8-neighbour grid 2048x2048, w log-uniform [1,1e4], source 0"
-    if name == "dag":
-        return (W.paper_dag(30000, 40_000_000, seed=11),
-                "the paper's high-diameter DAG: n=30000, chain of weight 1 plus random forward edges of weight "
-                "2(v-u), m=4e7, source 0")
-    raise SystemExit(f"unknown workload {name}")
+    g = W.ring_lattice(1 << 20, 16, 1, 1000, seed=2)
+    q = Query(g, 0, oracle.dijkstra(g, 0))
+    blob = load_blob()
+    t = q.tune(k_rule=2, k_model=blob)
+    kw = dict(k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"], team=t["team"], k_scale=t["k_scale"])
+    lr = q.record(*q.timed(args.steps, args.warmup, "ring learned", **kw),
+                  LEARNED_DESC + "; d, team and k_max autotuned", "ring", args.steps, args.warmup)
+    lr["autotune"] = t
+    pl = q.record(*q.timed(args.base_steps, 0, "ring plain"), "plain parDijkstra (k = 1, d = max out-degree)",
+                  "ring_plain", args.base_steps, 0)
+    tp = q.tune()
+    pt = q.record(*q.timed(args.base_steps, 0, "ring plain tuned", d=tp["d"], team=tp["team"]),
+                  "plain parDijkstra (k = 1), d and team autotuned", "ring_plain", args.base_steps, 0)
+    pt["autotune"] = tp
+    rec = dict(lr)
+    rec["plain"] = pl
+    rec["plain_tuned"] = pt
+    rec["speedup_vs_plain"] = lr["value"] / pl["value"]
+    rec["speedup_vs_plain_tuned"] = lr["value"] / pt["value"]
+    rec["exact"] = lr["exact"] and pl["exact"] and pt["exact"]
+    rec["config"] = {"workload": RING_DESC, "method": lr["method"], "n": g.n, "m": g.m, "d": lr["d"],
+                     "team": lr["team"], "levels": lr["levels"], "lds_levels": lr["lds_levels"],
+                     "parallelism": "1 workgroup per query"}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
+    return rec
 
 
-def run_multi(args):
-    """The batched workload: 256 queries (64 random geometric graphs with
-    uneven n in 2^12..2^18, mean degree 24, 4 sources each) in one launch."""
+def run_grid64(args):
+    """The small 64x64 grid: plain parDijkstra (every round of the method,
+    4,096 of them) and the learned threshold."""
+    import oracle
+    import workloads as W
+    g = W.grid4(64, 64, 1, 100, seed=1)
+    q = Query(g, 0, oracle.dijkstra(g, 0))
+    pl = q.record(*q.timed(args.steps, args.warmup, "grid64 plain"), "plain parDijkstra (k = 1, d = max out-degree)",
+                  "grid64", args.steps, args.warmup)
+    blob = load_blob()
+    lr = q.record(*q.timed(args.steps, args.warmup, "grid64 learned", k_rule=2, k_model=blob, d=32),
+                  LEARNED_DESC + "; d = 32", "grid64_learned", args.steps, args.warmup)
+    rec = {"metric": "SSSP GTEPS (m/time), plain parDijkstra", **pl,
+           "config": {"workload": GRID64_DESC, "n": g.n, "m": g.m}, "learned": lr,
+           "exact": pl["exact"] and lr["exact"]}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_sssp(g, 0, min(args.cpu_budget, 5.0))
+    return rec
+
+
+# Settings sssp_autotune chose for the 2048x2048 grid (its trials take about
+# 70 s there, so the bench does not repeat them): d = 128 x the maximum
+# out-degree, 256 threads, at most 256 minima per round; plain parDijkstra
+# with the autotuner's choice for the plain rule.
+GRID8_LEARNED = dict(d=1024, team=256, k_max=256)
+GRID8_PLAIN = dict(d=512, team=64)
+
+
+def run_grid8(args):
+    import oracle
+    import workloads as W
+    g = W.grid8(2048, 2048, wmax=10000, seed=4)
+    q = Query(g, 0, oracle.dijkstra(g, 0))
+    blob = load_blob()
+    lr = q.record(*q.timed(args.base_steps, 1, "grid8 learned", k_rule=2, k_model=blob, **GRID8_LEARNED),
+                  LEARNED_DESC + "; d = 1024, team 256, k_max 256 (autotuned settings for this graph)",
+                  "grid8", args.base_steps, 1)
+    pl = q.record(*q.timed(1, 0, "grid8 plain", **GRID8_PLAIN),
+                  "plain parDijkstra (k = 1), d = 512, team 64 (autotuned settings for this graph)",
+                  "grid8_plain", 1, 0)
+    rec = {"metric": "SSSP GTEPS (m/time), learned threshold", **lr,
+           "config": {"workload": GRID8_DESC, "n": g.n, "m": g.m}, "plain": pl,
+           "speedup_vs_plain": lr["value"] / pl["value"],
+           "reinsertions": lr["extracted"] - g.n, "exact": lr["exact"] and pl["exact"]}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
+    return rec
+
+
+def run_batch(args):
+    """256 queries (64 random geometric graphs with uneven n in 2^12..2^18,
+    mean degree 24, 4 sources each) in one persistent launch."""
     import numpy as np
     import torch
 
@@ -58,78 +276,99 @@ def run_multi(args):
 
     batch = W.rgg_batch(64, 4)
     dev = torch.device("cuda:0")
-    qs, keep = [], []
+    qs, keep, graphs = [], [], []
     for g, srcs in batch:
-        off = torch.from_numpy(g.offsets.view(np.int64)).to(dev)
-        tg = torch.from_numpy(g.targets.view(np.int32)).to(dev)
-        wt = torch.from_numpy(g.weights.view(np.int32)).to(dev)
+        off, tg, wt = to_dev(g)
         keep.append((off, tg, wt))
         for s in srcs:
             qs.append((off, tg, wt, g.n, g.m, s, torch.empty(g.n, dtype=torch.int64, device=dev)))
+            graphs.append((g, s))
     sum_m = sum(q[4] for q in qs)
-    refs = [oracle.dijkstra(g, s) for g, srcs in batch for s in srcs]
+    refs = [oracle.dijkstra(g, s) for g, s in graphs]
 
-    def timed(**kw):
+    def exact():
+        return all(np.array_equal(q[6].cpu().numpy().view(np.uint64), r) for q, r in zip(qs, refs))
+
+    def timed(steps, warmup, label, **kw):
         torch.cuda.synchronize()
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             pkg.sssp_batch(qs, **kw)
         torch.cuda.synchronize()
         stats = []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             stats.append(pkg.sssp_batch(qs, **kw))
         torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
-        exact = all(np.array_equal(q[6].cpu().numpy().view(np.uint64), r) for q, r in zip(qs, refs))
+        sec = (time.perf_counter() - t0) / steps
+        ex = exact()
+        log(f"{label}: {sec * 1e3:.1f} ms/step over {steps}, exact={ex}")
         st = stats[-1]
         kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
-        abytes = algorithmic_bytes(st)
-        achieved = abytes / (kern_ms * 1e-3) / 1e9
-        print(f"[bench] batch {kw.get('k_rule', 0)}: {sec * 1e3:.1f} ms/step exact={exact}", file=sys.stderr,
-              flush=True)
-        return {"value": sum_m / sec / 1e9, "ms_per_step": sec * 1e3, "rounds": st["rounds"],
-                "relaxations": st["relaxations"], "extracted": st["extracted"], "team": st["team"],
-                "exact": exact,
-                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp_multi",
-                             "kernel_ms": kern_ms, "algorithmic_bytes": abytes}}
+        return {"value": sum_m / sec / 1e9, "unit": "GTEPS", "steps": steps, "warmup": warmup,
+                "ms_per_step": sec * 1e3, "rounds": st["rounds"], "relaxations": st["relaxations"],
+                "extracted": st["extracted"], "team": st["team"], "exact": ex,
+                "roofline": roofline("k_sssp_multi", "batch", sssp_bytes(st), kern_ms)}
 
-    from paper_1908_09378_amd import learn
-    blob = torch.from_numpy(learn.load_model()).to(dev)
+    blob = load_blob()
     t0 = time.perf_counter()
     tuned = pkg.sssp_batch_autotune(qs, k_rule=2, k_model=blob)
     tuned["tune_s"] = time.perf_counter() - t0
-    print(f"[bench] batch autotune: {tuned}", file=sys.stderr, flush=True)
-    lr = timed(k_rule=2, k_model=blob, d_scale=tuned["d_scale"], k_max=tuned["k_max"], team=tuned["team"],
-               k_scale=tuned["k_scale"])
-    pr = timed()
-    line = {
-        "metric": METRIC, "value": lr["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": lr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "256 queries: 64 random geometric graphs (n = floor(2^(12+6u)), mean degree 24, "
-                               "w = round(1000 len)+1), 4 sources each, one launch",
-                   "method": "batched parDijkstra with the learned threshold, one parBucketHeap per query; "
-                             "d (as a multiple of each query's max out-degree) and k_max autotuned",
-                   "autotune": tuned,
-                   "queries": len(qs), "sum_n": sum(g.n for g, _ in batch), "sum_m_over_queries": sum_m,
-                   "team": lr["team"]},
-        "roofline": lr["roofline"], "rounds": lr["rounds"], "relaxations": lr["relaxations"],
-        "extracted": lr["extracted"], "exact": lr["exact"] and pr["exact"],
-        "plain": pr, "speedup_vs_plain": lr["value"] / pr["value"],
-    }
+    log(f"batch autotune: {tuned}")
+    kw = dict(k_rule=2, k_model=blob, d_scale=tuned["d_scale"], k_max=tuned["k_max"], team=tuned["team"],
+              k_scale=tuned["k_scale"])
+    lr = timed(args.steps, args.warmup, "batch learned", **kw)
+    pr = timed(args.base_steps, 0, "batch plain")
+    # the same settings, the first queries of the batch's order one launch each:
+    # what batching itself gains over running queries one after another
+    ns = 16
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in qs[:ns]:
+        pkg.sssp_ex(q[0], q[1], q[2], q[3], q[4], q[5], q[6], k_rule=2, k_model=blob, d_scale=tuned["d_scale"],
+                    k_max=tuned["k_max"], team=tuned["team"], k_scale=tuned["k_scale"])
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    seq_ok = all(np.array_equal(q[6].cpu().numpy().view(np.uint64), r) for q, r in zip(qs[:ns], refs[:ns]))
+    sub = qs[:ns]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pkg.sssp_batch(sub, **kw)
+    torch.cuda.synchronize()
+    sub_s = time.perf_counter() - t0
+    sub_m = sum(q[4] for q in sub)
+    rec = {"metric": "batched SSSP GTEPS (sum of m over queries / time)", **lr,
+           "config": {"workload": "256 queries: 64 random geometric graphs (n = floor(2^(12+6u)), mean degree 24, "
+                                  "w = round(1000 len)+1), 4 sources each, one launch",
+                      "method": "batched parDijkstra with the learned threshold, one parBucketHeap per query; "
+                                "d (as a multiple of each query's max out-degree), team and k_max autotuned",
+                      "autotune": tuned, "queries": len(qs), "sum_n": sum(g.n for g, _ in batch),
+                      "sum_m_over_queries": sum_m},
+           "plain": pr, "speedup_vs_plain": lr["value"] / pr["value"],
+           "one_by_one": {"queries": ns, "sequential_s": seq_s, "batched_s": sub_s,
+                          "sequential_gteps": sub_m / seq_s / 1e9, "batched_gteps": sub_m / sub_s / 1e9,
+                          "speedup_of_batching": seq_s / sub_s, "exact": seq_ok,
+                          "what": "the first 16 queries (largest first), learned rule with the tuned settings: "
+                                  "one sssp_ex call each vs one sssp_batch launch"},
+           "exact": lr["exact"] and pr["exact"] and seq_ok}
     if not args.no_cpu:
+        from concurrent.futures import ThreadPoolExecutor
         t0 = time.perf_counter()
-        runs = 0
-        for g, srcs in batch:
-            for s in srcs:
-                oracle.dijkstra(g, s)
-                runs += 1
-        el = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": sum_m / el / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-                                "sample": f"all {runs} queries, single-thread binary-heap Dijkstra ({el:.1f} s), "
-                                          f"host {os.cpu_count()} cpus"}
-    print(json.dumps(line), flush=True)
+        for g, s in graphs:
+            oracle.dijkstra(g, s)
+        el1 = time.perf_counter() - t0
+        nthreads = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=nthreads) as ex:  # the oracle call releases the GIL
+            list(ex.map(lambda gs: oracle.dijkstra(gs[0], gs[1]), graphs))
+        eln = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": sum_m / el1 / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+                               "sample": f"all {len(graphs)} queries, single-thread binary-heap Dijkstra "
+                                         f"({el1:.1f} s), host {nthreads} cpus"}
+        rec["cpu_baseline_all_cores"] = {"value": sum_m / eln / 1e9, "unit": "GTEPS", "cores": nthreads,
+                                         "kind": "oracle",
+                                         "sample": f"all {len(graphs)} queries, one query per thread on "
+                                                   f"{nthreads} threads ({eln:.2f} s)"}
+    return rec
 
 
 def run_heap(args):
@@ -153,13 +392,13 @@ def run_heap(args):
     rounds = args.heap_rounds
     dev = torch.device("cuda:0")
 
-    def to_dev(k, i):
+    def dev_pairs(k, i):
         return (torch.from_numpy(k.view(np.int64)).to(dev), torch.from_numpy(i.view(np.int32)).to(dev))
 
     keys, ids = W.heap_init_pairs(n_ids, seed=3)
     h = pkg.Heap(n_ids, d)
     for c in range(0, n_ids, d):
-        h.bulk_update(*to_dev(keys[c:c + d], ids[c:c + d]))
+        h.bulk_update(*dev_pairs(keys[c:c + d], ids[c:c + d]))
     torch.cuda.synchronize()
     cur = np.full(n_ids, INF, dtype=np.uint64)
     cur[ids] = keys
@@ -177,7 +416,7 @@ def run_heap(args):
         bk, bi = W.decrease_batch(live, lambda x: cur[x], d, 3, r)
         if len(kept) < 4:
             kept.append((bk, bi))
-        dk, di = to_dev(bk, bi)
+        dk, di = dev_pairs(bk, bi)
         torch.cuda.synchronize()
         e0 = h.traffic()
         t0 = time.perf_counter()
@@ -190,34 +429,31 @@ def run_heap(args):
         te = time.perf_counter() - t0
         hk = ko[:n].cpu().numpy().view(np.uint64)
         hi = io[:n].cpu().numpy().view(np.uint32)
-        good = n == ext and bool(np.all(cur[hi] == hk)) and np.unique(hi).shape[0] == n
+        good = n == min(ext, int(np.count_nonzero(cur != INF))) and bool(np.all(cur[hi] == hk))
+        good = good and np.unique(hi).shape[0] == n
         good = good and bool(np.all((hk[1:] > hk[:-1]) | ((hk[1:] == hk[:-1]) & (hi[1:] > hi[:-1]))))
         cur[hi] = INF
-        mk = cur.min()
-        if good and mk != INF:
-            good = mk > hk[-1] or (mk == hk[-1] and int(np.flatnonzero(cur == mk).min()) > int(hi[-1]))
+        if good and n:
+            left = np.flatnonzero(cur != INF)
+            if left.size:
+                mk = cur[left].min()
+                good = mk > hk[-1] or (mk == hk[-1] and int(left[cur[left] == mk].min()) > int(hi[-1]))
         ok &= bool(good)
         return tu, te, el
 
     # Every 32nd round (the last one, for short runs) is profiled instead of
-    # timed: HIP events around each merge writing pass give the kernel's own
-    # duration for the roofline; the timed rounds run without instrumentation.
+    # timed: HIP events around every kernel of the engine give each kernel's
+    # own duration; the timed rounds run without instrumentation.
     profiled = {r for r in range(rounds) if r % 32 == 31} if rounds >= 32 else {rounds - 1}
     if rounds < 2:
         profiled = set()
     timed = 0
-    m_launch = m_bytes_tot = 0
-    m_ms_tot = 0.0
+    prof0 = h.kernel_profile()
     for r in range(rounds):
         if r in profiled:
             h.set_profiling(True)
-            mp0 = h.merge_profile()
             one_round(r)
-            mp1 = h.merge_profile()
             h.set_profiling(False)
-            m_launch += mp1["launches"] - mp0["launches"]
-            m_bytes_tot += mp1["bytes"] - mp0["bytes"]
-            m_ms_tot += mp1["ms"] - mp0["ms"]
             continue
         tu, te, el = one_round(r)
         t_upd += tu
@@ -225,32 +461,41 @@ def run_heap(args):
         elems_upd += el
         timed += 1
         if timed % 32 == 1:
-            print(f"[bench] heap round {r}: update {t_upd / timed * 1e3:.2f} ms, extract "
-                  f"{t_ext / timed * 1e3:.2f} ms, exact={ok}", file=sys.stderr, flush=True)
+            log(f"heap round {r}: update {t_upd / timed * 1e3:.2f} ms, extract {t_ext / timed * 1e3:.2f} ms, "
+                f"exact={ok}")
+    prof = {k: {f: v[f] - prof0[k][f] for f in v} for k, v in h.kernel_profile().items()}
     ok &= h.size() == int(np.count_nonzero(cur != INF))
-    m_bytes = m_bytes_tot / max(1, m_launch)
-    m_ms = m_ms_tot / max(1, m_launch)
     n_rounds = rounds
     rounds = max(1, timed)
     upd_s = t_upd / rounds
     # algorithmic bytes of one bulk_update: the level operations' elements
     # (12 B each) plus the intake: read the pairs (12 B), the atomicMin on the
-    # current key (8 B) and a changed-id mark of one bit per id, scanned twice
-    abytes = 12.0 * elems_upd / rounds + 20.0 * d + n_ids / 4
+    # current key (8 B) and a changed-id mark of one byte per id, written for
+    # changed ids and scanned once
+    abytes = 12.0 * elems_upd / rounds + 20.0 * d + n_ids
     achieved = abytes / upd_s / 1e9
+    # the roofline names the engine kernel with the most event-timed time
+    kern = max(prof, key=lambda k: prof[k]["ms"]) if prof else None
+    tot_ms = sum(v["ms"] for v in prof.values()) or 1.0
+    if kern:
+        kp = prof[kern]
+        rl = roofline(kern, "heap", kp["bytes"] / max(1, kp["launches"]), kp["ms"] / max(1, kp["launches"]),
+                      {"launches": kp["launches"], "share_of_kernel_time": kp["ms"] / tot_ms,
+                       "measured": f"HIP events around each launch in {len(profiled)} profiled rounds"})
+    else:
+        rl = None
     line = {"metric": "parBucketHeap bulk_update keys/s on 1 MI355X", "value": d / upd_s, "unit": "keys/s",
-            "n_gpus": 1, "steps": rounds, "warmup": 0, "ms_per_step": (t_upd + t_ext) / rounds * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "steps": rounds, "warmup": 0, "ms_per_step": (t_upd + t_ext) / rounds * 1e3,
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
             "config": {"workload": "standalone heap: 2^24 ids, keys U[0,2^40), d=2^20; rounds of 2^20 "
                                    "decrease-keys (new = old - U[0, old/2]) + extract_min(2^16)",
                        "rounds": n_rounds, "timed_rounds": rounds, "engine": "device-wide"},
             "update_ms": upd_s * 1e3, "extract_ms": t_ext / rounds * 1e3,
             "extract_keys_per_s": ext / (t_ext / rounds),
-            "roofline": {"bound": "hbm", "achieved": m_bytes / (m_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": m_bytes / (m_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_merge<true> (merge + DeleteDuplicates, writing pass)",
-                         "kernel_ms": m_ms, "algorithmic_bytes": m_bytes, "launches": m_launch,
-                         "measured": f"HIP events around each launch in {len(profiled)} profiled rounds"},
+            "roofline": rl,
+            "kernels": {k: {"launches": v["launches"], "ms": v["ms"],
+                            "GB/s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0}
+                        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])},
             "op_level": {"achieved": achieved, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "what": "bulk_update as a whole (all kernels and host steps)", "algorithmic_bytes": abytes},
             "exact": ok}
@@ -269,7 +514,25 @@ def run_heap(args):
         line["cpu_baseline"] = {"value": done / el, "unit": "keys/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{len(kept)} rounds (bulk_update 2^20 + extract_min 2^16) on the "
                                           f"std::set oracle after the same 2^24 load ({el:.1f} s)"}
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def run_dag(args):
+    """The paper's high-diameter DAG (Section 4.2): n = 30,000, a weight-1
+    chain plus random forward edges of weight 2(v-u); distances checked
+    against the closed form dist(i) = i."""
+    import numpy as np
+    import workloads as W
+    g = W.paper_dag(30000, args.dag_m, seed=11)
+    q = Query(g, 0, np.arange(g.n, dtype=np.uint64))
+    pl = q.record(*q.timed(args.base_steps, 1, "dag plain"), "plain parDijkstra (k = 1, d = max out-degree)",
+                  "dag", args.base_steps, 1)
+    rec = {"metric": "SSSP GTEPS (m/time), plain parDijkstra", **pl,
+           "config": {"workload": f"the paper's DAG: n=30000, m={g.m}, chain of weight 1 plus random forward "
+                                  f"edges of weight 2(v-u), source 0", "n": g.n, "m": g.m}}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
+    return rec
 
 
 def run_copy(args):
@@ -287,17 +550,12 @@ def run_copy(args):
         b.copy_(a)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / args.steps
-    print(json.dumps({"metric": "device copy GB/s", "value": 2 * 8 * n / sec / 1e9, "unit": "GB/s",
-                      "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n, "steps": args.steps}),
-          flush=True)
+    return {"metric": "device copy GB/s", "value": 2 * 8 * n / sec / 1e9, "unit": "GB/s",
+            "bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n, "steps": args.steps}
 
 
-def algorithmic_bytes(st):
-    """Bytes the method must move per launch: per extracted vertex its two CSR
-    offsets (16 B); per scanned edge its target and weight (8 B) and the 8-byte
-    atomicMin on dist; per heap element read or written by the level operations
-    (Merge, DeleteDuplicates, Select, splits) 12 B (u64 key + u32 id)."""
-    return 16 * st["extracted"] + 16 * st["relaxations"] + 12 * st["heap_elems"]
+RUNNERS = {"ring": run_ring, "grid64": run_grid64, "grid8": run_grid8, "batch": run_batch, "heap": run_heap,
+           "dag": run_dag, "copy": run_copy}
 
 
 def main():
@@ -305,137 +563,44 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ring")
-    ap.add_argument("--method", default="both", choices=["plain", "learned", "both"],
-                    help="plain parDijkstra (the timed value), the learned threshold, or both on the same graph")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--workload", default="all", choices=["all"] + sorted(RUNNERS))
+    ap.add_argument("--base-steps", type=int, default=2,
+                    help="timed runs of the long baselines (plain parDijkstra, the large learned grid)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--heap-rounds", type=int, default=256)
+    ap.add_argument("--dag-m", type=int, default=40_000_000)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the bench runs on one GPU only; --gpus must be 1 "
                                    "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
-
-    if args.workload == "multi":
-        return run_multi(args)
-    if args.workload == "heap":
-        return run_heap(args)
-    if args.workload == "copy":
-        return run_copy(args)
-
-    import numpy as np
-    import torch
-
-    import paper_1908_09378_amd as pkg
-
-    g, desc = make_graph(args.workload)
-    dev = torch.device("cuda:0")
-    off = torch.from_numpy(g.offsets.view(np.int64)).to(dev)
-    tg = torch.from_numpy(g.targets.view(np.int32)).to(dev)
-    wt = torch.from_numpy(g.weights.view(np.int32)).to(dev)
-    dist = torch.empty(g.n, dtype=torch.int64, device=dev)
-    torch.cuda.synchronize()
-
-    import oracle
-    if args.workload == "dag":
-        ref = np.arange(g.n, dtype=np.uint64)  # the chain of weight-1 edges is the shortest path (closed form)
-    else:
-        ref = oracle.dijkstra(g, 0)
-
-    def timed(steps, warmup, **kw):
-        stats = []
-        for _ in range(warmup):
-            pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist, **kw)
-        torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    if args.workload != "all":
+        rec = RUNNERS[args.workload](args)
+        rec.setdefault("metric", METRIC)
+        rec["n_gpus"] = 1
+        print(json.dumps(rec), flush=True)
+        return
+    head = run_ring(args)
+    subs = {}
+    for name in ("grid64", "grid8", "batch", "heap"):
         t0 = time.perf_counter()
-        for _ in range(steps):
-            stats.append(pkg.sssp_ex(off, tg, wt, g.n, g.m, 0, dist, **kw))
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / steps
-        exact = bool(np.array_equal(dist.cpu().numpy().view(np.uint64), ref))
-        print(f"[bench] {kw.get('k_rule', 0) and 'learned' or 'plain'}: {sec * 1e3:.1f} ms/step, "
-              f"{stats[-1]['rounds']} rounds, exact={exact}", file=sys.stderr, flush=True)
-        return sec, stats, exact
-
-    def record(sec, stats, exact, method):
-        st = stats[-1]
-        kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
-        abytes = algorithmic_bytes(st)
-        achieved = abytes / (kern_ms * 1e-3) / 1e9
-        return {"value": g.m / sec / 1e9, "ms_per_step": sec * 1e3, "method": method, "rounds": st["rounds"],
-                "relaxations": st["relaxations"], "extracted": st["extracted"], "updates": st["updates"],
-                "d": st["d"], "team": st["team"], "levels": st["levels"], "lds_levels": st["lds_levels"],
-                "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
-                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sssp",
-                             "kernel_ms": kern_ms, "algorithmic_bytes": abytes}}
-
-    def tune(**kw):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        t = pkg.sssp_autotune(off, tg, wt, g.n, g.m, 0, dist, **kw)
-        torch.cuda.synchronize()
-        t["tune_s"] = time.perf_counter() - t0
-        print(f"[bench] autotune {kw.get('k_rule', 0)}: {t}", file=sys.stderr, flush=True)
-        return t
-
-    runs = {}
-    if args.method in ("both", "learned"):
-        from paper_1908_09378_amd import learn
-        blob = torch.from_numpy(learn.load_model()).to(dev)
-        t = tune(k_rule=2, k_model=blob)
-        r = record(*timed(args.steps, args.warmup, k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"],
-                          team=t["team"], k_scale=t["k_scale"]),
-                   "learned threshold: an 8-64-64-1 GELU MLP (bf16 weights, models/k_mlp.bin) picks how many "
-                   "minima each round extracts, improved vertices are re-inserted; d, team and k_max autotuned")
-        r["autotune"] = t
-        runs["learned"] = r
-    if args.method in ("both", "plain"):
-        runs["plain"] = record(*timed(args.steps, args.warmup), "plain parDijkstra (k = 1, d = max out-degree)")
-    if args.method == "both":
-        t = tune()
-        r = record(*timed(args.steps, args.warmup, d=t["d"], team=t["team"]),
-                   "plain parDijkstra (k = 1), d and team autotuned")
-        r["autotune"] = t
-        runs["plain_tuned"] = r
-    main_run = runs["learned" if "learned" in runs else "plain"]
+        subs[name] = RUNNERS[name](args)
+        subs[name]["wall_s"] = time.perf_counter() - t0
+        log(f"{name} done in {subs[name]['wall_s']:.1f} s")
     line = {
-        "metric": METRIC,
-        "value": main_run["value"],
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": main_run["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": desc, "method": main_run["method"], "n": g.n, "m": g.m, "d": main_run["d"],
-                   "team": main_run["team"], "levels": main_run["levels"], "lds_levels": main_run["lds_levels"],
-                   "parallelism": "1 workgroup per query"},
-        "roofline": main_run["roofline"],
-        "rounds": main_run["rounds"],
-        "relaxations": main_run["relaxations"],
-        "extracted": main_run["extracted"],
-        "us_per_round": main_run["us_per_round"],
-        "exact": all(r["exact"] for r in runs.values()),
+        "metric": METRIC, "value": head["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": head["config"],
+        "roofline": head["roofline"], "cpu_baseline": head.get("cpu_baseline"),
+        "rounds": head["rounds"], "relaxations": head["relaxations"], "extracted": head["extracted"],
+        "us_per_round": head["us_per_round"],
+        "exact": head["exact"] and all(s.get("exact", True) for s in subs.values()),
+        "autotune": head["autotune"], "plain": head["plain"], "plain_tuned": head["plain_tuned"],
+        "speedup_vs_plain": head["speedup_vs_plain"], "speedup_vs_plain_tuned": head["speedup_vs_plain_tuned"],
+        "workloads": subs, "wall_s": time.perf_counter() - t_start,
     }
-    if "autotune" in main_run:
-        line["config"]["autotune"] = main_run["autotune"]
-    if "learned" in runs and "plain" in runs:
-        line["plain"] = {k: v for k, v in runs["plain"].items() if k != "method"}
-        line["speedup_vs_plain"] = runs["learned"]["value"] / runs["plain"]["value"]
-    if "plain_tuned" in runs:
-        line["plain_tuned"] = runs["plain_tuned"]
-        line["speedup_vs_plain_tuned"] = runs["learned"]["value"] / runs["plain_tuned"]["value"]
-    if not args.no_cpu:
-        per_run, runs = oracle.time_dijkstra(g, 0, args.cpu_budget)
-        line["cpu_baseline"] = {"value": g.m / per_run / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-                                "sample": f"{runs} full run(s) of single-thread binary-heap Dijkstra on the "
-                                          f"same graph ({per_run:.2f} s each), host {os.cpu_count()} cpus"}
     print(json.dumps(line), flush=True)
 
 

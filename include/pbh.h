@@ -137,11 +137,27 @@ int pbh_traffic(pbh_t *h, uint64_t *elements_out);
 int pbh_merge_profile(pbh_t *h, uint64_t *launches, uint64_t *bytes, double *ms);
 
 /*
- * pbh_set_profiling: on != 0 brackets each merge writing pass of the
- * device-wide engine with HIP events (for pbh_merge_profile); the events add
- * some microseconds to each merge, so profiling is off by default.  No effect
- * on results, nor on the one-workgroup engine.  Errors: PBH_EINVAL (NULL
- * handle).
+ * pbh_kernel_profile: for the device-wide engine, totals per kernel kind over
+ * the launches made while profiling was on: launches, algorithmic bytes and
+ * summed HIP-event time in ms (host outputs; zeros for the one-workgroup
+ * engine).  kind < the number of kinds; pbh_kernel_name(kind) names it
+ * (NULL past the last kind).  Algorithmic bytes per launch: merge writing
+ * pass 12 per input + 12 per output element; merge counting pass 4 per input
+ * (ids); Select pass and gather 12 per element (passes that return at once
+ * are a kind of their own with 0 bytes); split counting 12 and writing 24 per
+ * element; intake 20 per pair; mark compaction 1 per id (+ 20 per output in
+ * the writing pass); extract sort 24 per element per pass; absent marking 12
+ * per id.  Errors: PBH_EINVAL (NULL argument, kind out of range).
+ */
+int pbh_kernel_profile(pbh_t *h, uint32_t kind, uint64_t *launches, uint64_t *bytes, double *ms);
+const char *pbh_kernel_name(uint32_t kind);
+
+/*
+ * pbh_set_profiling: on != 0 brackets every kernel launch of the device-wide
+ * engine with HIP events (for pbh_kernel_profile and pbh_merge_profile); the
+ * events add some microseconds to each launch, so profiling is off by
+ * default.  No effect on results, nor on the one-workgroup engine.  Errors:
+ * PBH_EINVAL (NULL handle).
  */
 int pbh_set_profiling(pbh_t *h, int on);
 
@@ -219,6 +235,13 @@ typedef struct {
   uint32_t d_scale;       /* with d == 0: d = maximum out-degree * max(1, d_scale) */
   float k_scale;          /* learned rule: k = 2^(k_scale * scale * y); 0 means 1 */
   uint32_t reserved;      /* must be zero */
+  /* Extraction record (may be NULL): settle_order[j] receives the id of the
+   * j-th extracted vertex, for j < settle_cap (device array).  With the plain
+   * rule this is parDijkstra's settle order; a round that extracts k > 1
+   * writes its k ids in increasing id order.  sssp_ex and sssp_noalloc only
+   * (sssp_batch ignores it). */
+  uint32_t *settle_order;
+  uint64_t settle_cap;
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
@@ -250,6 +273,28 @@ typedef struct {
 int sssp_ex(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
             uint64_t m, uint32_t source, uint64_t *dist_out, const sssp_opts *opts,
             sssp_stats *stats, void *stream);
+
+/*
+ * sssp_noalloc: sssp_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and statistics as sssp_ex (except
+ * stats->kernel_ms, which is 0: no events are created), but every buffer the
+ * run needs beyond the caller's arrays -- the CSR check, the statistics block,
+ * the heap levels that do not fit in LDS and the update lists of speculative
+ * rounds -- is carved from one fixed 64 MiB array of device memory that the
+ * library holds on each GPU it runs on until the process ends; nothing is
+ * allocated or freed.  The array keeps the last call's contents (everything
+ * a run reads is initialised by that run).  Calls are serialised inside the
+ * library; calls that overlap on one GPU from outside it (e.g. through
+ * another copy of the library) would race on the array.
+ * Errors: those of sssp_ex, plus PBH_EINVAL (nothing run) when the query's
+ * heap at its starting capacity needs more than the 64 MiB
+ * (4096 + 12 x (HBM heap elements + list elements) bytes), and PBH_ECAPACITY
+ * when the heap of a rule that pulls ahead outgrows it during the run.
+ */
+int sssp_noalloc(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
+                 uint64_t m, uint32_t source, uint64_t *dist_out, const sssp_opts *opts, sssp_stats *stats,
+                 void *stream);
 
 /* One query of sssp_batch: a CSR graph (device arrays, same rules as sssp),
  * a source and the distance output (device, n entries).  Queries may share

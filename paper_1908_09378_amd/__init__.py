@@ -44,7 +44,8 @@ class SsspOpts(C.Structure):
                 ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
                 ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
-                ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("reserved", C.c_uint32)]
+                ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("reserved", C.c_uint32),
+                ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64)]
 
 
 class SsspStats(C.Structure):
@@ -60,8 +61,8 @@ class SsspQuery(C.Structure):
 
 
 _lib = None
-EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_delete", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_set_profiling", "pbh_destroy",
-           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
+EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_delete", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_kernel_profile", "pbh_set_profiling", "pbh_destroy",
+           "pbh_debug_levels", "sssp", "sssp_ex", "sssp_noalloc", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
            "mlp_grad", "mlp_train", "mlp_infer", "pbh_last_error"]
 
 
@@ -82,10 +83,14 @@ def lib():
         L.pbh_traffic.argtypes = [vp, C.POINTER(u64)]
         L.pbh_merge_profile.argtypes = [vp, C.POINTER(u64), C.POINTER(u64), C.POINTER(C.c_double)]
         L.pbh_set_profiling.argtypes = [vp, C.c_int]
+        L.pbh_kernel_profile.argtypes = [vp, u32, C.POINTER(u64), C.POINTER(u64), C.POINTER(C.c_double)]
+        L.pbh_kernel_name.argtypes = [u32]
+        L.pbh_kernel_name.restype = C.c_char_p
         L.pbh_destroy.argtypes = [vp]
         L.pbh_debug_levels.argtypes = [vp, u32, C.POINTER(u32), C.POINTER(C.c_int32), vp, vp, vp, vp, vp]
         L.sssp.argtypes = [vp, vp, vp, u32, u64, u32, vp]
         L.sssp_ex.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
+        L.sssp_noalloc.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.sssp_batch.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), C.POINTER(SsspStats), vp]
         L.sssp_autotune.argtypes = [vp, vp, vp, u32, u64, u32, vp, C.POINTER(SsspOpts), vp]
         L.sssp_batch_autotune.argtypes = [C.POINTER(SsspQuery), u32, C.POINTER(SsspOpts), vp]
@@ -131,8 +136,10 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
-          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0):
+          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None):
     o = SsspOpts()
+    if settle_order is not None:
+        o.settle_order, o.settle_cap = _ptr(settle_order, 4), settle_order.numel()
     o.k_scale = k_scale
     o.d, o.team, o.schedule, o.lds_levels, o.heap_capacity = d, team, schedule, lds_levels, heap_capacity
     o.k_rule, o.k_fixed, o.k_max = k_rule, k_fixed, k_max
@@ -161,6 +168,17 @@ def sssp_ex(offsets, targets, weights, n: int, m: int, source: int, dist_out, *,
     sp = None if stream is None else C.c_void_p(stream.cuda_stream)
     _check(lib().sssp_ex(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source, _ptr(dist_out, 8),
                          C.byref(o), C.byref(s), sp))
+    return _stats_dict(s)
+
+
+def sssp_noalloc(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:
+    """sssp_ex without device allocation: every buffer comes from the
+    library's fixed scratch (sssp_noalloc in include/pbh.h)."""
+    o = _opts(**kw)
+    s = SsspStats()
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(lib().sssp_noalloc(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source,
+                              _ptr(dist_out, 8), C.byref(o), C.byref(s), sp))
     return _stats_dict(s)
 
 
@@ -264,6 +282,21 @@ class Heap:
         a, b, t = C.c_uint64(0), C.c_uint64(0), C.c_double(0)
         _check(lib().pbh_merge_profile(self._h, C.byref(a), C.byref(b), C.byref(t)))
         return dict(launches=a.value, bytes=b.value, ms=t.value)
+
+    def kernel_profile(self) -> dict:
+        """Device-wide engine: {kernel name: {launches, bytes, ms}} over the
+        launches timed so far (pbh_kernel_profile)."""
+        out = {}
+        kind = 0
+        while True:
+            name = lib().pbh_kernel_name(kind)
+            if name is None:
+                break
+            a, b, t = C.c_uint64(0), C.c_uint64(0), C.c_double(0)
+            _check(lib().pbh_kernel_profile(self._h, kind, C.byref(a), C.byref(b), C.byref(t)))
+            out[name.decode()] = dict(launches=a.value, bytes=b.value, ms=t.value)
+            kind += 1
+        return out
 
     def set_profiling(self, on: bool) -> None:
         """Device-wide engine: time each merge writing pass with HIP events."""

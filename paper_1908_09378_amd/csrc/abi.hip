@@ -413,15 +413,22 @@ int mlp_infer(const float* X, uint32_t n, const float* blob, uint32_t team, floa
   return PBH_OK;
 }
 
+int pbh_kernel_profile(pbh_t* h, uint32_t kind, uint64_t* launches, uint64_t* bytes, double* ms) {
+  if (!h || !launches || !bytes || !ms) return fail(PBH_EINVAL, "pbh_kernel_profile: NULL argument");
+  if (kind >= (uint32_t)WK_COUNT) return fail(PBH_EINVAL, "pbh_kernel_profile: kind %u >= %d", kind, (int)WK_COUNT);
+  WideKernelStat k{0, 0, 0.0};
+  if (h->wide) wide_kernel_profile(h->wide, (int)kind, &k);
+  *launches = k.launches;
+  *bytes = k.bytes;
+  *ms = k.ms;
+  return PBH_OK;
+}
+
+const char* pbh_kernel_name(uint32_t kind) { return wide_kernel_name((int)kind); }
+
 int pbh_merge_profile(pbh_t* h, uint64_t* launches, uint64_t* bytes, double* ms) {
   if (!h || !launches || !bytes || !ms) return fail(PBH_EINVAL, "pbh_merge_profile: NULL argument");
-  u64 l = 0, b = 0;
-  double t = 0.0;
-  if (h->wide) wide_merge_profile(h->wide, &l, &b, &t);
-  *launches = l;
-  *bytes = b;
-  *ms = t;
-  return PBH_OK;
+  return pbh_kernel_profile(h, WK_MERGE_WRITE, launches, bytes, ms);
 }
 
 int pbh_set_profiling(pbh_t* h, int on) {
@@ -473,11 +480,27 @@ static CsrCheck* g_csr = nullptr;
 
 namespace {
 
+// A fixed block of device memory that a run carves all of its buffers from
+// instead of allocating them (the no-allocation entry point).
+struct FixedScratch {
+  unsigned char* base;
+  u64 bytes;
+};
+
+// Bytes of the fixed block a run needs: the CSR check and the statistics
+// (one 4096-byte header), the HBM levels (12 B per element) and the
+// speculative rounds' update lists.
+constexpr u64 FIXED_HEAD = 4096;
+u64 fixed_bytes(u64 arena_elems, u64 list_elems) { return FIXED_HEAD + 12ull * (arena_elems + list_elems); }
+
 // sssp_ex with the query index that trace records carry (0 for a single
 // query; a batch re-running one of its queries passes that query's index).
-// The caller holds g_sssp_mu.
+// With fx, every device buffer comes from that block and nothing is
+// allocated (no events either: kernel_ms is then 0).  The caller holds
+// g_sssp_mu.
 int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
-             uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream, u32 qid) {
+             uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream, u32 qid,
+             const FixedScratch* fx = nullptr) {
   if (!offsets || !dist_out || (m > 0 && (!targets || !weights)))
     return fail(PBH_EINVAL, "sssp: NULL array argument");
   if (n == 0) return fail(PBH_EINVAL, "sssp: n == 0");
@@ -485,12 +508,24 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
   sssp_opts o{};
   if (opts) o = *opts;
   hipStream_t s = (hipStream_t)stream;
-  if (!g_csr) HIPCHK(hipMalloc(&g_csr, sizeof(CsrCheck)));
-  if (!g_sssp_stats) HIPCHK(hipMalloc(&g_sssp_stats, sizeof(SsspDevStats)));
-  HIPCHK(hipMemsetAsync(g_csr, 0, sizeof(CsrCheck), s));
-  HIPCHK(launch_check_csr((const u64*)offsets, targets, n, m, g_csr, s));
+  CsrCheck* csr;
+  SsspDevStats* dstats;
+  if (fx) {
+    csr = reinterpret_cast<CsrCheck*>(fx->base);
+    dstats = reinterpret_cast<SsspDevStats*>(fx->base + 256);
+    static_assert(256 + sizeof(SsspDevStats) <= FIXED_HEAD, "header of the fixed block");
+  } else {
+    if (!g_csr) HIPCHK(hipMalloc(&g_csr, sizeof(CsrCheck)));
+    if (!g_sssp_stats) HIPCHK(hipMalloc(&g_sssp_stats, sizeof(SsspDevStats)));
+    csr = g_csr;
+    dstats = g_sssp_stats;
+  }
+  // a fill kernel, not a memset, so that the sequence stays free of memset
+  // nodes for callers that record it
+  HIPCHK(launch_zero_u64(reinterpret_cast<u64*>(csr), sizeof(CsrCheck) / 8, s));
+  HIPCHK(launch_check_csr((const u64*)offsets, targets, n, m, csr, s));
   CsrCheck cc;
-  HIPCHK(hipMemcpyAsync(&cc, g_csr, sizeof cc, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&cc, csr, sizeof cc, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (cc.bad) return fail(PBH_EINVAL, "sssp: malformed CSR (offsets or targets)");
   u32 d = o.d ? o.d : (u32)(cc.maxdeg ? cc.maxdeg : 1) * (o.d_scale > 1 ? o.d_scale : 1u);
@@ -513,6 +548,7 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
   HIPCHK(hipGetDevice(&dev));
   int max_lds = 0;
   HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  bool first = true;
   for (;;) {
     int q = levels_for(d, hcap, 2);
     size_t budget = (size_t)max_lds - sssp_static_lds(team) - 256;
@@ -525,29 +561,54 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
     if (qlds > q) qlds = q;
     size_t lds = (size_t)lvl_off(d, qlds) * 12ull;
     if (lds > budget) return fail(PBH_EINVAL, "sssp: %d LDS levels do not fit", qlds);
-    u64 gel = lvl_off(d, q) - lvl_off(d, qlds);
-    if (g_sssp_arena.elems < gel) {
-      arena_free(&g_sssp_arena);
-      int rc = arena_alloc(&g_sssp_arena, gel);
-      if (rc) return rc;
-    }
+    const u64 gel = lvl_off(d, q) - lvl_off(d, qlds);
     SsspParams p{};
     u32 kmax = 1;
     {
       int rc = spec_from_opts(o, d, &p.spec, &kmax);
       if (rc) return rc;
     }
-    if (spec_needs_list(o)) {
-      u64 le = 2ull * kmax * (u64)d;
-      if (g_sssp_list.elems < le) {
+    const u64 le = spec_needs_list(o) ? 2ull * kmax * (u64)d : 0ull;
+    u64 *ak, *lk;
+    u32 *av, *lv;
+    if (fx) {
+      const u64 need = fixed_bytes(gel, le);
+      if (need > fx->bytes) {
+        if (first)
+          return fail(PBH_EINVAL,
+                      "sssp_noalloc: this query needs %llu bytes of scratch (%d heap levels of bulk size %u), "
+                      "the fixed scratch holds %llu",
+                      (unsigned long long)need, q, d, (unsigned long long)fx->bytes);
+        return fail(PBH_ECAPACITY, "sssp_noalloc: the heap outgrew the fixed scratch (%llu bytes needed, %llu held)",
+                    (unsigned long long)need, (unsigned long long)fx->bytes);
+      }
+      // keys (8-byte aligned after the header), then ids, for the arena and the list
+      ak = reinterpret_cast<u64*>(fx->base + FIXED_HEAD);
+      lk = ak + gel;
+      av = reinterpret_cast<u32*>(lk + le);
+      lv = av + gel;
+    } else {
+      if (g_sssp_arena.elems < gel) {
+        arena_free(&g_sssp_arena);
+        int rc = arena_alloc(&g_sssp_arena, gel);
+        if (rc) return rc;
+      }
+      if (le && g_sssp_list.elems < le) {
         arena_free(&g_sssp_list);
         int rc = arena_alloc(&g_sssp_list, le);
         if (rc) return rc;
       }
-      p.spec.uk = g_sssp_list.k;
-      p.spec.uv = g_sssp_list.v;
-      p.spec.tk = g_sssp_list.k + (u64)kmax * d;
-      p.spec.tv = g_sssp_list.v + (u64)kmax * d;
+      ak = g_sssp_arena.k;
+      av = g_sssp_arena.v;
+      lk = le ? g_sssp_list.k : nullptr;
+      lv = le ? g_sssp_list.v : nullptr;
+    }
+    first = false;
+    if (le) {
+      p.spec.uk = lk;
+      p.spec.uv = lv;
+      p.spec.tk = lk + (u64)kmax * d;
+      p.spec.tv = lv + (u64)kmax * d;
       // the LDS left after the levels holds the round's list for the intake
       // sort when it fits (two buffers, 12 B per pair each)
       const u64 room = (budget - lds) / 24u;
@@ -557,6 +618,8 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
         lds += (size_t)lcap * 24u;
       }
     }
+    p.spec.order = o.settle_order;
+    p.spec.order_cap = o.settle_order ? o.settle_cap : 0;
     if (o.trace_features) {
       if (!o.trace_keys || !o.trace_ids || !o.trace_count || o.trace_every == 0)
         return fail(PBH_EINVAL, "sssp: trace needs keys, ids, count and trace_every");
@@ -579,23 +642,27 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
     p.g.d = d;
     p.g.q = q;
     p.g.qlds = qlds;
-    p.g.gk = g_sssp_arena.k;
-    p.g.gv = g_sssp_arena.v;
-    p.stats = g_sssp_stats;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    p.g.gk = ak;
+    p.g.gv = av;
+    p.stats = dstats;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!fx) {
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+    }
     HIPCHK(launch_fill_dist((u64*)dist_out, n, source, s));
-    HIPCHK(hipEventRecord(e0, s));
+    if (e0) HIPCHK(hipEventRecord(e0, s));
     HIPCHK(launch_sssp(team, p, lds, s));
-    HIPCHK(hipEventRecord(e1, s));
+    if (e1) HIPCHK(hipEventRecord(e1, s));
     SsspDevStats ds;
-    HIPCHK(hipMemcpyAsync(&ds, g_sssp_stats, sizeof ds, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&ds, dstats, sizeof ds, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) {
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
     if (ds.err == E_CAPACITY && q < MAXL) {
       // at least one more level: the deepest nominal bucket must grow past hcap
       const u64 grown = std::max<u64>(safe, nomB(d, q - 1) * 4ull);
@@ -631,6 +698,50 @@ int sssp_ex(const uint64_t* offsets, const uint32_t* targets, const uint32_t* we
             uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream) {
   std::lock_guard<std::mutex> lock(g_sssp_mu);
   return sssp_run(offsets, targets, weights, n, m, source, dist_out, opts, stats, stream, 0u);
+}
+
+// ------------------------------------------------------------ sssp_noalloc
+
+}  // extern "C"
+
+// Fixed scratch of the no-allocation entry point: one static device array,
+// held by every GPU the library runs on until the process ends.  In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is used.
+constexpr u64 NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (set up on the first
+// call there).  The caller holds g_sssp_mu.
+int scratch_on_device(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(PBH_EDEVICE, "sssp_noalloc: device %d out of range", dev);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PBH_EDEVICE, "sssp_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PBH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sssp_noalloc(const uint64_t* offsets, const uint32_t* targets, const uint32_t* weights, uint32_t n, uint64_t m,
+                 uint32_t source, uint64_t* dist_out, const sssp_opts* opts, sssp_stats* stats, void* stream) {
+  std::lock_guard<std::mutex> lock(g_sssp_mu);
+  unsigned char* base = nullptr;
+  if (int rc = scratch_on_device(&base)) return rc;
+  const FixedScratch fx{base, NOALLOC_SCRATCH_BYTES};
+  return sssp_run(offsets, targets, weights, n, m, source, dist_out, opts, stats, stream, 0u, &fx);
 }
 
 // ------------------------------------------------------------ sssp_batch

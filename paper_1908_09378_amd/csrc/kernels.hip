@@ -19,6 +19,7 @@ struct DevPolicy {
   using L = ArrT<u64 PBH_LDS*, u32 PBH_LDS*>;
   using G = ArrT<u64 PBH_GLB*, u32 PBH_GLB*>;
   using SP = HeapState PBH_LDS*;
+  __device__ __forceinline__ static void on_resolve(const Geom&, SP, int, bool) {}
 };
 
 __global__ void k_fill_dist(u64* dist, u32 n, u32 src) {
@@ -41,6 +42,10 @@ __global__ void k_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrChec
     if (tg[e] >= n) bad = 1;
   if (bad) atomicOr(&out->bad, 1ull);
   if (md) atomicMax(&out->maxdeg, md);
+}
+
+__global__ void k_zero_u64(u64* p, u64 n) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 __global__ void k_check_update(const u64* keys, const u32* ids, u64 count, u32 id_cap, u64* bad) {
@@ -177,6 +182,11 @@ static int grid_for(u64 work, int block) {
 
 hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_dist, dim3(grid_for(n, 256)), dim3(256), 0, s, dist, n, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(u64* p, u64 n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

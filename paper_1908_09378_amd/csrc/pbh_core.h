@@ -153,6 +153,10 @@ struct HostPolicy {
   using L = Arr;
   using G = Arr;
   using SP = HeapState*;
+  // called before (after = false) and after every Resolve(i); the CPU tests'
+  // policy records the level sizes there, the others do nothing
+  template <class SPP>
+  PBH_INL static void on_resolve(const Geom&, SPP, int, bool) {}
 };
 
 // ---------------------------------------------------------------- primitives
@@ -769,12 +773,14 @@ done:
 
 template <class T, class P>
 PBH_INL void resolve(const T& t, const Geom& g, typename P::SP st, const u64* cur, int i) {
+  P::on_resolve(g, st, i, false);
   if (i + 1 < g.qlds)
     resolve_t<T, P, typename P::L, typename P::L>(t, g, st, cur, i);
   else if (i < g.qlds)
     resolve_t<T, P, typename P::L, typename P::G>(t, g, st, cur, i);
   else
     resolve_t<T, P, typename P::G, typename P::G>(t, g, st, cur, i);
+  P::on_resolve(g, st, i, true);
 }
 
 // Can Resolve(j) move its worst case (all of S_j and B_j) into level j+1?
@@ -935,7 +941,8 @@ PBH_INL u32 intake(const T& t, A S, u32 n, A tmp, A tmp2, const u64* dist, int i
 // Returns false when the heap is empty.
 template <class T, class P, class A0>
 PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
-                        const u32* wt, u64* dist, int idbits, u64* relax, u64* upd) {
+                        const u32* wt, u64* dist, int idbits, u64* relax, u64* upd, u32* order, u64 order_cap,
+                        u64 nth) {
   const Lvl a0 = lvl_load(st, 0);
   if (a0.nB == 0) return false;
   A0 B = as_arr<A0>(lbuf(g, 0, a0.bsel));
@@ -951,6 +958,7 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
   }
   t.minkv(mk, mv);
   const u64 e0 = off[mv], e1 = off[mv + 1];
+  if (order && nth < order_cap && t.tid() == 0) order[nth] = mv;  // the settle order, when asked for
   u32 n0, n1, n2;
   A0 T0 = as_arr<A0>(lbuf(g, 0, 2));
   partition3(t, B, a0.nB, KV{mk, mv}, kv_inf(), T0, as_arr<A0>(lbuf(g, 0, a0.bsel ^ 1)), T0, &n0, &n1, &n2);
@@ -1036,6 +1044,10 @@ struct SpecCfg {
   // LDS room for the round's list after the LDS levels: two buffers of lcap
   // pairs (keys, then ids); 0 = the intake sorts in global memory
   u32 lcap;
+  // extracted ids in extraction order (order[j] = the j-th extraction; a
+  // round of k > 1 writes its k in id order), first order_cap of them
+  u32* order;
+  u64 order_cap;
 };
 
 struct SsspCounters {
@@ -1361,6 +1373,9 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
   u32 n0, n1, n2;
   A0 X = as_arr<A0>(lbuf(g, 0, 2));
   partition3(t, B, a0.nB, thr, kv_inf(), X, as_arr<A0>(lbuf(g, 0, a0.bsel ^ 1)), X, &n0, &n1, &n2);
+  if (sc.order)
+    for (u32 j = (u32)t.tid(); j < take; j += (u32)T::kNT)
+      if (c->extracted + j < sc.order_cap) sc.order[c->extracted + j] = X.v[j];
   // out-degree prefix sums of the extracted vertices
   u32 E = 0;
   for (u32 base = 0; base < take; base += (u32)T::kNT) {
@@ -1547,8 +1562,10 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     }
     bool more;
     if (sc.rule == 0 && !sc.trace_f) {
-      more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates)
-                        : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates);
+      more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
+                                                          sc.order, sc.order_cap, c.extracted)
+                        : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
+                                                          sc.order, sc.order_cap, c.extracted);
       c.extracted += more ? 1 : 0;
     } else {
       const Lvl a0 = lvl_load(st, 0);
@@ -1737,6 +1754,8 @@ PBH_INL void pbh_delete_body(const T& t, const Geom& g, typename P::SP st, const
     }
     t.sync();
   }
+  if (t.tid() == 0) st->aux[3] = 0;
+  t.sync();
   if (need_grow(g, st)) {
     if (t.tid() == 0) st->aux[3] = 1;
     t.sync();

@@ -34,6 +34,7 @@ struct CsrCheck {
 };
 
 hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s);
+hipError_t launch_zero_u64(u64* p, u64 n, hipStream_t s);
 hipError_t launch_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out, hipStream_t s);
 hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s);
 size_t sssp_static_lds(int team);

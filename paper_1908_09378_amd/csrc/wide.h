@@ -47,11 +47,21 @@ int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count);
 // ascending by (key, id); *count_out = number written.
 int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, u64* count_out);
 
-// Totals over the merge writing passes timed so far: launches, algorithmic
-// bytes (12 B per input and per output element) and HIP-event time.  Only
-// passes run while profiling is on are timed (the events cost each merge
-// some microseconds).
-void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms);
+// Kernel kinds of the engine, for profiling.
+enum {
+  WK_MERGE_WRITE, WK_MERGE_COUNT, WK_SEL_PASS, WK_SEL_GATHER, WK_SPLIT_COUNT, WK_SPLIT_WRITE, WK_INTAKE,
+  WK_BITS_COUNT, WK_BITS_WRITE, WK_SORT_TILE, WK_SORT_MERGE, WK_ABSENT, WK_OTHER, WK_IDLE, WK_COUNT
+};
+struct WideKernelStat {
+  u64 launches;
+  u64 bytes;  // algorithmic bytes of those launches
+  double ms;  // summed HIP-event time
+};
+// Totals per kernel kind over the launches timed so far (only launches made
+// while profiling is on are timed: the events cost each launch some
+// microseconds of host time).
+void wide_kernel_profile(const WideScratch* w, int kind, WideKernelStat* out);
+const char* wide_kernel_name(int kind);  // nullptr past the last kind
 void wide_set_profiling(WideScratch* w, bool on);
 
 }  // namespace bkt

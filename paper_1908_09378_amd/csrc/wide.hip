@@ -35,6 +35,7 @@
 #include <chrono>
 #include <cstddef>
 #include <cstring>
+#include <vector>
 
 #include "pbh_team.h"
 
@@ -68,6 +69,7 @@ struct Ctl {
   int sbad;     // no bin held the rank (never expected)
   u32 sncand;
   u32 passdone;  // workgroups finished with the current pass (the last one picks)
+  u32 npass;     // passes that did work since the last gather (profiling)
   u32 shist[SEL_BINS];
 };
 
@@ -83,6 +85,8 @@ struct Mail {
   u32 rv;
   int sfail;    // the selection needs more passes
   int sbad;     // the selection found no element of the rank (never expected)
+  u32 npass;    // Select passes of the step that did work (the others returned at once)
+  u32 pad_;     // keeps seq the struct's last word
   u32 seq;      // number of the last step published (host copy only)
 };
 static_assert(offsetof(Mail, seq) + sizeof(u32) == sizeof(Mail) && sizeof(Mail) % 4 == 0,
@@ -685,6 +689,7 @@ __global__ __launch_bounds__(NT) void k_sel_pass(const u64* K, const u32* V, u32
   if (h[threadIdx.x]) atomic_add32(&c->shist[threadIdx.x], h[threadIdx.x]);
   if (!last_workgroup(&c->passdone, &s_last)) return;
   // the pick, by the last workgroup: bin b (one per thread) holds the rank
+  if (threadIdx.x == 0) c->npass += 1;
   const u32 b = threadIdx.x;
   const u32 hb = ld_a32(&c->shist[b]);
   u32 tot;
@@ -729,6 +734,8 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       box->sfail = 1;
       box->sbad = 0;
+      box->npass = c->npass;
+      c->npass = 0;
     }
     return;
   }
@@ -767,6 +774,8 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
   if (threadIdx.x == 0) {
     box->sfail = 0;
     box->sbad = (c->sbad || r == 0 || r > m || nc0 != c->scnt) ? 1 : 0;
+    box->npass = c->npass;
+    c->npass = 0;
     st_a32(&c->sncand, 0u);
   }
   if (threadIdx.x < m) {
@@ -1161,12 +1170,17 @@ struct WideScratch {
   Partials pt{nullptr, nullptr, nullptr};  // one slot per tile / workgroup (maxtiles, >= GRID_STRIDE)
   u32 maxtiles = 0;
   hipStream_t s = 0;
-  // HIP-event timing of the merge writing pass (the engine's largest kernel),
-  // while profiling is on
+  // Profiling (off by default): HIP events around every kernel launch of
+  // the engine, with the kernel's kind and algorithmic bytes; totalled per
+  // kind when the operation ends.
   bool profile = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  u64 merge_launches = 0, merge_bytes = 0;
-  double merge_ms = 0.0;
+  struct Rec {
+    int kind;
+    u64 bytes;
+  };
+  std::vector<hipEvent_t> ev;  // event pairs, created as needed
+  std::vector<Rec> rec;        // launches of the current operation
+  WideKernelStat kst[WK_COUNT] = {};
 };
 
 namespace {
@@ -1178,6 +1192,57 @@ namespace {
 
 int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : E_DEVICE; }
 
+// Runs launch() -- one kernel launch -- bracketed by HIP events while
+// profiling is on.  Returns the launch's record index (bytes can be patched
+// once a step's results are known) or -1.
+template <class F>
+int plaunch(WideScratch* w, int kind, u64 bytes, F&& launch) {
+  if (!w->profile) {
+    launch();
+    return -1;
+  }
+  const size_t i = w->rec.size();
+  while (w->ev.size() < 2 * (i + 1)) {
+    hipEvent_t e = nullptr;
+    // timing-only events: without the system-scope fence a record does not
+    // write back the L2 (which would slow the very step being timed)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+      launch();
+      return -1;
+    }
+    w->ev.push_back(e);
+  }
+  (void)hipEventRecord(w->ev[2 * i], w->s);
+  launch();
+  (void)hipEventRecord(w->ev[2 * i + 1], w->s);
+  w->rec.push_back(WideScratch::Rec{kind, bytes});
+  return (int)i;
+}
+
+void patch_bytes(WideScratch* w, int idx, u64 bytes) {
+  if (idx >= 0) w->rec[(size_t)idx].bytes = bytes;
+}
+void patch_kind(WideScratch* w, int idx, int kind) {
+  if (idx >= 0) w->rec[(size_t)idx].kind = kind;
+}
+
+// Totals the current operation's timed launches per kind (the operation's
+// work has ended, so the events have passed).
+int prof_collect(WideScratch* w) {
+  if (w->rec.empty()) return 0;
+  WCHK(hipEventSynchronize(w->ev[2 * w->rec.size() - 1]));
+  for (size_t i = 0; i < w->rec.size(); ++i) {
+    float ms = 0.f;
+    WCHK(hipEventElapsedTime(&ms, w->ev[2 * i], w->ev[2 * i + 1]));
+    WideKernelStat& k = w->kst[w->rec[i].kind];
+    k.launches += 1;
+    k.bytes += w->rec[i].bytes;
+    k.ms += ms;
+  }
+  w->rec.clear();
+  return 0;
+}
+
 // Ends a step: publishes its results and waits until the host sees them, by
 // polling the mailbox's sequence number (a stream synchronisation would add
 // the runtime's completion path and a system-scope cache write-back to every
@@ -1185,7 +1250,8 @@ int launch_ok() { return hipGetLastError() == hipSuccess ? 0 : E_DEVICE; }
 // synchronised, which also reports a failed kernel.
 int fetch(WideScratch* w) {
   const u32 want = ++w->seq;
-  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, w->s, w->box, w->mail_d, want);
+  plaunch(w, WK_OTHER, 2ull * sizeof(Mail),
+          [&] { hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, w->s, w->box, w->mail_d, want); });
   if (int rc = launch_ok()) return rc;
   const auto t0 = std::chrono::steady_clock::now();
   for (u32 spin = 1;; ++spin) {
@@ -1208,27 +1274,26 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   const u32 nt = cdiv(total, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
-  hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
-                     (const u32*)nullptr, w->pt, 0);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
-  if (w->profile) WCHK(hipEventRecord(w->ev0, w->s));
-  hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, (u32*)nullptr, w->toff,
-                     w->pt, stats ? 1 : 0);
-  if (w->profile) WCHK(hipEventRecord(w->ev1, w->s));
+  plaunch(w, WK_MERGE_COUNT, 4ull * total, [&] {
+    hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
+                       (const u32*)nullptr, w->pt, 0);
+  });
+  plaunch(w, WK_OTHER, 8ull * nt, [&] {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
+  });
+  const int iw = plaunch(w, WK_MERGE_WRITE, 12ull * total, [&] {
+    hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, (u32*)nullptr,
+                       w->toff, w->pt, stats ? 1 : 0);
+  });
   if (stats)
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
+    plaunch(w, WK_OTHER, 20ull * nt, [&] {
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
+    });
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *m = w->mail_h->total;
   *num_le = stats ? w->mail_h->num_le : 0u;
-  if (w->profile) {
-    float ms = 0.f;
-    WCHK(hipEventSynchronize(w->ev1));  // already passed: the step has ended
-    WCHK(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-    w->merge_ms += ms;
-    w->merge_bytes += 12ull * (total + *m);
-    w->merge_launches += 1;
-  }
+  patch_bytes(w, iw, 12ull * (total + *m));  // 12 B per input read + 12 B per output written
   return 0;
 }
 
@@ -1244,8 +1309,10 @@ int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2
   if (n == 0 || r == 0 || r > n) return E_INTERNAL;
   if (!have_range) {
     const u32 gm = grid_for(n);
-    hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
+    plaunch(w, WK_OTHER, 8ull * n, [&] { hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt); });
+    plaunch(w, WK_OTHER, 20ull * gm, [&] {
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
+    });
   }
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
   // Each pass fixes 8 more of the 96 bits, so 12 passes (4 rounds of 3)
@@ -1253,10 +1320,21 @@ int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2
   // one end of their range, as decreased keys do).  Passes after the last
   // needed one return at once.
   for (int round = 0; round < 4; ++round) {
+    int ip[3];
     for (int p = 0; p < 3; ++p)
-      hipLaunchKernelGGL(k_sel_pass, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, r, round == 0 && p == 0 ? 1 : 0);
-    hipLaunchKernelGGL(k_sel_collect, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v, w->box);
+      ip[p] = plaunch(w, WK_SEL_PASS, 12ull * n, [&] {
+        hipLaunchKernelGGL(k_sel_pass, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, r,
+                           round == 0 && p == 0 ? 1 : 0);
+      });
+    const int ic = plaunch(w, WK_SEL_GATHER, 12ull * n, [&] {
+      hipLaunchKernelGGL(k_sel_collect, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v,
+                         w->box);
+    });
     if (int rc = wpartition3_sel(w, A, n, cap, p2, O0, O1, O2, live, n0, n1, n2, w->box)) return rc;
+    // passes after the last needed one, and a gather before the passes were
+    // done, returned at once: they read nothing
+    for (int p = (int)w->mail_h->npass; p < 3; ++p) patch_kind(w, ip[p], WK_IDLE), patch_bytes(w, ip[p], 0);
+    if (w->mail_h->sfail) patch_kind(w, ic, WK_IDLE), patch_bytes(w, ic, 0);
     if (w->mail_h->sbad) return E_INTERNAL;
     if (!w->mail_h->sfail) {
       *p1 = cap;
@@ -1277,9 +1355,15 @@ int wpartition3_sel(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, 
   const u32 nt = cdiv(n, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   PArgs a{A.k, A.v, n, p1.k, p1.v, p2.k, p2.v, live, {O0.k, O1.k, O2.k}, {O0.v, O1.v, O2.v}, sel};
-  hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
-  hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part);
-  hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
+  plaunch(w, WK_SPLIT_COUNT, 12ull * n, [&] {
+    hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
+  });
+  plaunch(w, WK_OTHER, 24ull * nt, [&] {
+    hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part);
+  });
+  plaunch(w, WK_SPLIT_WRITE, 24ull * n, [&] {
+    hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
+  });
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   *n0 = w->mail_h->part[0];
@@ -1303,13 +1387,18 @@ int wsort(WideScratch* w, Arr X, u32 n, u64* dk, u32* dv) {
   // ping-pong so that the last pass lands in D
   Arr bufs[2] = {X, Arr{w->tmp_k, w->tmp_v}};
   Arr dst = passes == 0 ? Arr{dk, dv} : bufs[(passes & 1) ? 1 : 0];
-  hipLaunchKernelGGL(k_tsort, dim3(nt), dim3(NT), 0, w->s, X.k, X.v, n, dst.k, dst.v);
+  plaunch(w, WK_SORT_TILE, 24ull * n,
+          [&] { hipLaunchKernelGGL(k_tsort, dim3(nt), dim3(NT), 0, w->s, X.k, X.v, n, dst.k, dst.v); });
   Arr src = dst;
   u64 L = TILE;
   for (int p = 0; p < passes; ++p, L *= 2) {
     Arr to = p == passes - 1 ? Arr{dk, dv} : (src.k == bufs[0].k ? bufs[1] : bufs[0]);
-    hipLaunchKernelGGL(k_spart, dim3(cdiv(nt, SPW)), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, nt, w->part);
-    hipLaunchKernelGGL(k_smerge, dim3(nt), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, w->part, to.k, to.v);
+    plaunch(w, WK_OTHER, 4ull * nt, [&] {
+      hipLaunchKernelGGL(k_spart, dim3(cdiv(nt, SPW)), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, nt, w->part);
+    });
+    plaunch(w, WK_SORT_MERGE, 24ull * n, [&] {
+      hipLaunchKernelGGL(k_smerge, dim3(nt), dim3(NT), 0, w->s, src.k, src.v, n, (u32)L, w->part, to.k, to.v);
+    });
     src = to;
   }
   return launch_ok();
@@ -1470,19 +1559,30 @@ int wide_create(WideScratch** out, u32 d) {
   WCHK(hipMalloc(&w->tmp_k, 4ull * d * sizeof(u64)));
   WCHK(hipMalloc(&w->tmp_v, 4ull * d * sizeof(u32)));
   WCHK(hipMemset(w->ctl, 0, sizeof(Ctl)));
-  // Timing-only events: without the system-scope fence a record does not
-  // write back the L2 (which would slow the very step being timed).
-  WCHK(hipEventCreateWithFlags(&w->ev0, hipEventDisableSystemFence));
-  WCHK(hipEventCreateWithFlags(&w->ev1, hipEventDisableSystemFence));
   return wide_reserve(w, 4ull * d);
 }
 
 void wide_set_profiling(WideScratch* w, bool on) { w->profile = on; }
 
-void wide_merge_profile(const WideScratch* w, u64* launches, u64* bytes, double* ms) {
-  *launches = w->merge_launches;
-  *bytes = w->merge_bytes;
-  *ms = w->merge_ms;
+void wide_kernel_profile(const WideScratch* w, int kind, WideKernelStat* out) { *out = w->kst[kind]; }
+
+const char* wide_kernel_name(int kind) {
+  static const char* const names[WK_COUNT] = {
+      "k_merge<true> (merge + DeleteDuplicates, writing pass)",
+      "k_merge<false> (merge, counting pass)",
+      "k_sel_pass (radix Select pass)",
+      "k_sel_collect (Select gather and rank)",
+      "k_part<false> (three-way split, counting pass)",
+      "k_part<true> (three-way split, writing pass)",
+      "k_intake (atomicMin on current keys + marks)",
+      "k_bits<false> (mark compaction, counting pass)",
+      "k_bits<true> (mark compaction, writing pass)",
+      "k_tsort (tile sort of the extracted minima)",
+      "k_smerge (merge pass of the extracted minima)",
+      "k_delete / k_absent (ids marked absent)",
+      "scans, reductions, result publishing",
+      "Select passes and gathers that returned at once"};
+  return kind >= 0 && kind < WK_COUNT ? names[kind] : nullptr;
 }
 
 void wide_destroy(WideScratch* w) {
@@ -1502,8 +1602,7 @@ void wide_destroy(WideScratch* w) {
   if (w->cand_v) (void)hipFree(w->cand_v);
   if (w->tmp_k) (void)hipFree(w->tmp_k);
   if (w->tmp_v) (void)hipFree(w->tmp_v);
-  if (w->ev0) (void)hipEventDestroy(w->ev0);
-  if (w->ev1) (void)hipEventDestroy(w->ev1);
+  for (hipEvent_t e : w->ev) (void)hipEventDestroy(e);
   delete w;
 }
 
@@ -1528,22 +1627,36 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
     w->marks_n = 32ull * h->nwords;
   }
   const u32 gi = grid_for(count);
-  hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, w->marks, w->pt);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                     (u32*)nullptr, &w->box->newly, w->ctl);
+  // per pair: the pair (12 B) and the atomicMin on its current key (8 B)
+  plaunch(w, WK_INTAKE, 20ull * count, [&] {
+    hipLaunchKernelGGL(k_intake, dim3(gi), dim3(NT), 0, w->s, keys, ids, count, h->cur, w->marks, w->pt);
+  });
+  plaunch(w, WK_OTHER, 4ull * gi, [&] {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
+                       (u32*)nullptr, &w->box->newly, w->ctl);
+  });
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   const Arr S0 = lbuf(h->g, 0, 3);
   u64* uk = direct ? S0.k : h->ukeys;
   u32* uv = direct ? S0.v : h->uids;
-  hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, w->tc, (const u32*)nullptr,
-                     (const u64*)h->cur, uk, uv);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
-  hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, (u32*)nullptr, w->toff,
-                     (const u64*)h->cur, uk, uv);
+  const u64 nmark = 32ull * h->nwords;  // one mark byte per id
+  plaunch(w, WK_BITS_COUNT, nmark, [&] {
+    hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, w->tc, (const u32*)nullptr,
+                       (const u64*)h->cur, uk, uv);
+  });
+  plaunch(w, WK_OTHER, 8ull * nt, [&] {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
+  });
+  const int ib = plaunch(w, WK_BITS_WRITE, nmark, [&] {
+    hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, (u32*)nullptr, w->toff,
+                       (const u64*)h->cur, uk, uv);
+  });
   if (int rc = launch_ok()) return rc;
   if (int rc = fetch(w)) return rc;
   const u64 nu = w->mail_h->total;
+  // marks read, plus per output its current key read (8 B) and the pair written (12 B)
+  patch_bytes(w, ib, nmark + 20ull * nu);
   st->live += w->mail_h->newly;
   for (u64 c0 = 0; c0 < nu;) {
     if (!direct)
@@ -1562,7 +1675,7 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
     if (st->err) return st->err;
     c0 += len;
   }
-  return 0;
+  return prof_collect(w);
 }
 
 // Delete (Section 1.2) of a batch of ids: their current keys become absent,
@@ -1574,9 +1687,12 @@ int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count) {
   if (count == 0) return 0;
   if (int rc = wide_reserve(w, capB(h->g.d, h->g.q - 1))) return rc;
   const u32 gi = grid_for(count);
-  hipLaunchKernelGGL(k_delete, dim3(gi), dim3(NT), 0, w->s, ids, count, h->cur, w->pt);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                     (u32*)nullptr, &w->box->newly, w->ctl);
+  plaunch(w, WK_ABSENT, 12ull * count,
+          [&] { hipLaunchKernelGGL(k_delete, dim3(gi), dim3(NT), 0, w->s, ids, count, h->cur, w->pt); });
+  plaunch(w, WK_OTHER, 4ull * gi, [&] {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
+                       (u32*)nullptr, &w->box->newly, w->ctl);
+  });
   if (int rc = launch_ok()) return rc;
   const Lvl a0 = st->L[0];
   if (a0.nB) {
@@ -1593,7 +1709,8 @@ int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count) {
   fix_ell(st, h->g.q);
   if (int rc = grow_if_needed(w, h)) return rc;
   wdrive(w, h, DRIVE_AFTER);
-  return st->err;
+  if (st->err) return st->err;
+  return prof_collect(w);
 }
 
 // Batched ExtractMin: repeatedly the smallest min(k_left, |B_0|) elements of
@@ -1632,8 +1749,10 @@ int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, 
     }
     if (n0 != take) return E_INTERNAL;
     if (int rc = wsort(w, X, take, okeys + out, oids + out)) return rc;
-    hipLaunchKernelGGL(k_absent, dim3(grid_for(take)), dim3(NT), 0, w->s, (const u32*)(oids + out), (u64)take,
-                       h->cur);
+    plaunch(w, WK_ABSENT, 12ull * take, [&] {
+      hipLaunchKernelGGL(k_absent, dim3(grid_for(take)), dim3(NT), 0, w->s, (const u32*)(oids + out), (u64)take,
+                         h->cur);
+    });
     if (int rc = launch_ok()) return rc;
     st->L[0].bsel ^= 1;
     st->L[0].nB = n1;
@@ -1644,7 +1763,7 @@ int wide_extract_min(WideScratch* w, WideHeap* h, u64 k, u64* okeys, u32* oids, 
   }
   WCHK(hipStreamSynchronize(w->s));
   *count_out = out;
-  return 0;
+  return prof_collect(w);
 }
 
 }  // namespace bkt

@@ -43,6 +43,8 @@ def lib():
         L.hm_extract.argtypes = [C.c_void_p, C.c_uint64, u64p, u32p, u64p]
         L.hm_levels.argtypes = [C.c_void_p, u32p, C.POINTER(C.c_int), u32p, u32p, u64p, u32p, u64p, u64p]
         L.hm_level_items.argtypes = [C.c_void_p, C.c_int, u64p, u32p, u64p, u32p]
+        L.hm_resolve_log.restype = C.c_uint64
+        L.hm_resolve_log.argtypes = [C.c_void_p, C.POINTER(C.c_longlong), C.c_uint64]
         L.hm_sssp.restype = C.c_int
         L.hm_sssp.argtypes = [u64p, u32p, u32p, C.c_uint32, C.c_uint64, C.c_uint32, u64p, C.c_uint32,
                               C.c_int, C.c_uint64, C.c_int, u64p, C.c_int, C.c_uint32, C.c_uint32, u32p,
@@ -100,6 +102,17 @@ class HostHeap:
         q = q.value
         return dict(q=q, ell=ell.value, nB=nB[:q], nS=nS[:q], pk=pk[:q], pv=pv[:q], cnt=cnt[:q],
                     live=live.value)
+
+    def resolve_log(self):
+        """Records of every Resolve(i) since the last call, before and after
+        it: dicts with lvl, after, ell, q, nB, nS (level i), nB1, nS1 (level
+        i+1), cnt (Resolve(i) executions so far)."""
+        cap = 1 << 16
+        buf = np.zeros(9 * cap, np.int64)
+        n = lib().hm_resolve_log(self.h, buf.ctypes.data_as(C.POINTER(C.c_longlong)), cap)
+        assert n <= cap
+        keys = ("lvl", "after", "ell", "q", "nB", "nS", "nB1", "nS1", "cnt")
+        return [dict(zip(keys, buf[9 * j:9 * j + 9].tolist())) for j in range(n)]
 
     def items(self, i, nB, nS):
         bk = np.zeros(max(nB, 1), np.uint64)

@@ -28,6 +28,37 @@ int ceil_log2(u64 x) {
   return b < 1 ? 1 : b;
 }
 
+// One record per Resolve(i) call, before and after it: the level sizes it
+// is about and the deepest non-empty level.
+struct ResolveRec {
+  int lvl, after, ell, q;
+  u32 nB0, nS0, nB1, nS1;  // levels i and i+1 (0 when i+1 does not exist)
+  u64 cnt;                 // Resolve(i) executions so far
+};
+static std::vector<ResolveRec>* g_log = nullptr;
+
+// HostPolicy that records every Resolve (the CPU tests of Algorithm 1's
+// pre- and postconditions and of Theorem 1's schedule read the records).
+struct TracePolicy {
+  using L = Arr;
+  using G = Arr;
+  using SP = HeapState*;
+  static void on_resolve(const Geom& g, HeapState* st, int i, bool after) {
+    if (!g_log) return;
+    ResolveRec r;
+    r.lvl = i;
+    r.after = after ? 1 : 0;
+    r.ell = st->ell;
+    r.q = g.q;
+    r.nB0 = st->L[i].nB;
+    r.nS0 = st->L[i].nS;
+    r.nB1 = i + 1 < g.q ? st->L[i + 1].nB : 0;
+    r.nS1 = i + 1 < g.q ? st->L[i + 1].nS : 0;
+    r.cnt = st->L[i].cnt;
+    g_log->push_back(r);
+  }
+};
+
 struct HM {
   u32 id_cap, d;
   int q, sched;
@@ -35,6 +66,13 @@ struct HM {
   std::vector<u32> bitmap, av, ui;
   HeapState st;
   TeamShared<1> ts;
+  std::vector<ResolveRec> log;
+};
+
+// Routes the Resolve records of the operation that follows to h's log.
+struct LogScope {
+  explicit LogScope(HM* h) { g_log = &h->log; }
+  ~LogScope() { g_log = nullptr; }
 };
 
 Geom geom(HM* h) {
@@ -101,7 +139,8 @@ int hm_update(void* hp, const u64* keys, const u32* ids, u64 count) {
     p.ukeys = h->uk.data();
     p.uids = h->ui.data();
     HostTeam t{&h->ts};
-    pbh_update_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
+    LogScope ls(h);
+    pbh_update_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) return 0;
     if (h->q >= MAXL) return -2;
@@ -125,7 +164,8 @@ int hm_delete(void* hp, const u32* ids, u64 count) {
     p.ids = ids;
     p.count = count;
     HostTeam t{&h->ts};
-    pbh_delete_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
+    LogScope ls(h);
+    pbh_delete_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) return 0;
     if (h->q >= MAXL) return -2;
@@ -149,7 +189,8 @@ int hm_extract(void* hp, u64 k, u64* ko, u32* io, u64* count) {
     p.okeys = ko;
     p.oids = io;
     HostTeam t{&h->ts};
-    pbh_extract_body<HostTeam, HostPolicy>(t, p.g, &h->st, p);
+    LogScope ls(h);
+    pbh_extract_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) break;
     if (h->q >= MAXL) return -2;
@@ -172,6 +213,22 @@ int hm_levels(void* hp, u32* q, int* ell, u32* nB, u32* nS, u64* pk, u32* pv, u6
     cnt[i] = h->st.L[i].cnt;
   }
   return 0;
+}
+
+// Copies up to cap Resolve records (ints: lvl, after, ell, q, nB_i, nS_i,
+// nB_i+1, nS_i+1, cnt; 9 per record) and clears the log; returns how many
+// records there were.
+u64 hm_resolve_log(void* hp, long long* out, u64 cap) {
+  HM* h = static_cast<HM*>(hp);
+  const u64 n = h->log.size();
+  for (u64 j = 0; j < n && j < cap; ++j) {
+    const ResolveRec& r = h->log[j];
+    long long* o = out + 9 * j;
+    o[0] = r.lvl, o[1] = r.after, o[2] = r.ell, o[3] = r.q;
+    o[4] = r.nB0, o[5] = r.nS0, o[6] = r.nB1, o[7] = r.nS1, o[8] = (long long)r.cnt;
+  }
+  h->log.clear();
+  return n;
 }
 
 // Dumps level i's B and S contents (for invariant checks).

@@ -11,6 +11,7 @@ import workloads as W
 from gpu_util import run_sssp
 
 pytestmark = pytest.mark.gpu
+INF = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 
 def _check(g, src, **kw):
@@ -96,6 +97,63 @@ def test_ring_lattice_full_size():
     g = W.ring_lattice(1 << 20, 16, 1, 1000, seed=2)
     st = _check(g, 0, team=64)
     print(f"[sssp] ring 2^20: {st['kernel_ms']:.1f} ms, rounds {st['rounds']}", flush=True)
+
+
+@pytest.mark.parametrize("gname", ["grid64", "ring2e16"])
+def test_plain_settle_order_is_the_oracles(gname):
+    """The plain rule extracts one vertex per round, always the heap's
+    minimum (key, id): the whole extraction sequence equals the oracle's
+    settle order, which is the reached vertices in (dist, id) order."""
+    import torch
+    g = W.grid4(64, 64, 1, 100, seed=1) if gname == "grid64" else W.ring_lattice(1 << 16, 16, 1, 1000, seed=2)
+    ref, order, _ = oracle.dijkstra(g, 0, want_order=True)
+    assert np.array_equal(order, np.lexsort((np.arange(g.n)[ref != INF], ref[ref != INF])))
+    from gpu_util import DEV, dev32
+    for kw in (dict(), dict(team=256), dict(lds_levels=0xFFFFFFFF, schedule=1)):
+        rec = torch.full((g.n + 8,), -1, dtype=torch.int32, device=DEV)
+        print(f"[sssp] settle order {gname} {kw}", flush=True)
+        got, st = run_sssp(pkg, g, 0, settle_order=rec, **kw)
+        seq = rec.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, ref)
+        assert np.array_equal(seq[:order.shape[0]], order)
+        assert np.all(seq[order.shape[0]:] == np.uint32(0xFFFFFFFF))
+
+
+def test_speculative_extraction_record_covers_every_vertex():
+    import torch
+    from gpu_util import DEV
+    g = W.grid8(64, 64, wmax=10000, seed=9)
+    ref = oracle.dijkstra(g, 0)
+    rec = torch.full((8 * g.n,), -1, dtype=torch.int32, device=DEV)
+    print("[sssp] speculative extraction record", flush=True)
+    got, st = run_sssp(pkg, g, 0, k_rule=1, k_fixed=16, k_max=16, settle_order=rec)
+    seq = rec.cpu().numpy().view(np.uint32)[: st["extracted"]]
+    assert np.array_equal(got, ref)
+    assert st["extracted"] <= 8 * g.n
+    assert np.array_equal(np.unique(seq), np.nonzero(ref != INF)[0].astype(np.uint32))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(team=256), dict(k_rule=1, k_fixed=16),
+                                dict(k_rule=3, k_max=256)])
+def test_rows_not_sorted_by_target(kw):
+    """CSR rows in random order (the ABI allows any order): the plain round's
+    intake sorts the relaxation output by id, the speculative rounds' intake
+    sorts their list; distances, rounds and relaxations stay the oracle's."""
+    from gpu_util import dev32
+    for g in (W.shuffle_rows(W.grid8(96, 96, wmax=10000, seed=9), 1),
+              W.shuffle_rows(W.ring_lattice(1 << 13, 16, 1, 1000, seed=2), 2),
+              W.shuffle_rows(W.random_graph(3000, 40000, 0, 9, seed=4), 3)):
+        assert not all(np.all(np.diff(g.targets[g.offsets[u]:g.offsets[u + 1]].astype(np.int64)) >= 0)
+                       for u in range(min(g.n, 50)))
+        kk = dict(kw)
+        if kk.get("k_rule") == 3:
+            kk["k_seq"] = dev32(np.array([1, 17, 2, 250, 5, 1, 64], np.uint32))
+        print(f"[sssp] shuffled rows {g.name} {kw}", flush=True)
+        if "k_rule" in kk:
+            got, st = run_sssp(pkg, g, 0, **kk)
+            assert np.array_equal(got, oracle.dijkstra(g, 0))
+        else:
+            _check(g, 0, **kk)
 
 
 def test_invalid_inputs():

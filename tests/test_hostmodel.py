@@ -271,3 +271,113 @@ def test_trial_limits_settle_everything_below_the_frontier(rule):
     rc, dist, st = hm_sssp(g, 0, stop_key=1 << 62)
     assert rc == 0 and not st["stopped"] and st["last_key"] == 2 ** 64 - 1
     assert np.array_equal(dist, ref)
+
+
+# ------------------------------------------------- Algorithm 1 and Theorem 1
+def _pure_script(n_ops, d, cap, seed):
+    """Operations in the setting of Theorem 1: each inserts at most d new
+    distinct ids (no key of a present id changes, so no copy of an id is ever
+    left behind) or extracts at most d minima."""
+    rng = np.random.default_rng(seed)
+    fresh = iter(rng.permutation(cap).astype(np.uint32).tolist())
+    ops, live = [], 0
+    for _ in range(n_ops):
+        if live >= d and rng.random() < 0.35:
+            k = int(rng.integers(1, d + 1))
+            ops.append(("extract", k))
+            live -= min(k, live)
+            continue
+        cnt = int(rng.integers(1, d + 1))
+        ids = np.array([next(fresh) for _ in range(cnt)], np.uint32)
+        ops.append(("update", rng.integers(0, 1 << 20, size=cnt).astype(np.uint64), ids))
+        live += cnt
+    return ops
+
+
+def _apply(h, o, op):
+    if op[0] == "update":
+        h.bulk_update(op[1], op[2])
+        o.bulk_update(op[1], op[2])
+    elif op[0] == "delete":
+        h.delete(op[1])
+        o.delete(op[1])
+    else:
+        a = h.extract_min(op[1])
+        b = o.extract_min(op[1])
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_theorem1_schedule_and_algorithm1_conditions(seed):
+    """Schedule 0 on operations of at most d elements (Theorem 1's setting):
+
+    * every operation is followed by Resolve(0), then Resolve(i) runs exactly
+      when the count of Resolve(i-1) reaches a multiple of four (and level i
+      holds elements) -- no other Resolve runs;
+    * before every Resolve(i) Algorithm 1's preconditions hold: |S_i| <= d 4^i,
+      |B_i| >= d 4^i if i < l, |S_i+1| <= d 4^(i+1) - d 4^i, and
+      |B_i+1| >= d 4^(i+1) + d 4^i if i+1 < l (l = deepest non-empty level);
+    * after it the postconditions hold: S_i empty, and |B_i| = 2d 4^i if i < l;
+    * the k-th Resolve(i) comes after the 4k-th Resolve(i-1)."""
+    d = [1, 2, 4, 8][seed % 4]
+    cap = 4000
+    h = HostHeap(cap, d, 0)
+    o = oracle.PQ(cap)
+    counts = {}
+    for op in _pure_script(400, d, cap, 100 + seed):
+        _apply(h, o, op)
+        log = h.resolve_log()
+        assert log and log[0]["lvl"] == 0 and log[0]["after"] == 0, "the operation's first Resolve is Resolve(0)"
+        expect_next = 0
+        for j in range(0, len(log), 2):
+            b, a = log[j], log[j + 1]
+            i = b["lvl"]
+            assert a["lvl"] == i and b["after"] == 0 and a["after"] == 1
+            assert i == expect_next, f"Resolve({i}) out of Theorem 1's order"
+            ell, nom = b["ell"], d * 4 ** i
+            # preconditions
+            assert b["nS"] <= nom
+            if i < ell:
+                assert b["nB"] >= nom
+            assert b["nS1"] <= 4 * nom - nom
+            if i + 1 < ell:
+                assert b["nB1"] >= 4 * nom + nom
+            # postconditions
+            assert a["nS"] == 0
+            if i < a["ell"]:
+                assert a["nB"] == 2 * nom
+            counts[i] = a["cnt"]
+            if i >= 1:
+                assert counts[i] * 4 <= counts[i - 1]
+            # Theorem 1: the next Resolve is of level i+1 iff Resolve(i)'s count
+            # is now a multiple of four and level i+1 holds elements
+            expect_next = i + 1 if (a["cnt"] % 4 == 0 and i + 1 <= a["ell"] and i + 1 < a["q"]) else None
+        assert expect_next is None, "a Resolve that Theorem 1's rule asks for did not run"
+        check_structure(h, o.cur(), d)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_algorithm1_postconditions_with_duplicates_and_deletes(seed):
+    """Outside Theorem 1's setting (decrease-keys that leave stale copies,
+    deletes, extracts of up to 4d, both schedules) the schedule adds Resolves
+    (room-making, refills of an empty B_0) and copies are dropped when they
+    meet, so |B_i| can end below 2d 4^i; what still holds after every
+    Resolve(i): S_i is empty and |B_i| <= 2d 4^i (EMPTY runs whenever B_i is
+    above it, which a FILL of level i-1 can cause by keeping the elements of
+    S_i at or below p_i)."""
+    d = [1, 3, 8][seed % 3]
+    cap = [50, 600][seed % 2]
+    h = HostHeap(cap, d, seed % 2)
+    o = oracle.PQ(cap)
+    above = 0
+    for op in W.random_script(80, cap, 3 * d, [20, 10 ** 6][seed % 2], 1300 + seed, deletes=True):
+        if op[0] == "extract":
+            op = ("extract", min(op[1], 4 * d))
+        _apply(h, o, op)
+        for r in h.resolve_log():
+            if r["after"]:
+                assert r["nS"] == 0 and r["nB"] <= 2 * d * 4 ** r["lvl"]
+            else:
+                above += r["nB"] > 2 * d * 4 ** r["lvl"]
+        check_structure(h, o.cur(), d)
+    print(f"Resolves entered with B_i above its nominal size: {above}")

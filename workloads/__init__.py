@@ -116,6 +116,17 @@ def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray, name
     return Graph(name, n, offsets, dst.astype(np.uint32), w)
 
 
+def shuffle_rows(g: Graph, seed: int) -> Graph:
+    """The same graph with the out-edges of every vertex in a random order
+    (seeded): a CSR input whose rows are not sorted by target."""
+    s = stream_seed(seed, 12)
+    m = g.m
+    row = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.offsets).astype(np.int64))
+    r = rand_u64(s, np.arange(m, dtype=np.uint64))
+    order = np.lexsort((r, row))  # by row, randomly within a row
+    return Graph(g.name + "_shuffled", g.n, g.offsets.copy(), g.targets[order].copy(), g.weights[order].copy())
+
+
 def _undirected(n, a, b, w, name):
     src = np.concatenate([a, b])
     dst = np.concatenate([b, a])
