@@ -293,20 +293,33 @@ def paper_dag(n: int, m: int, seed: int = 11) -> Graph:
         cnt[u] += take
         left -= take
         u += 1
-    srcs, dsts = [np.arange(n - 1, dtype=np.int64)], [np.arange(1, n, dtype=np.int64)]
+    # CSR built row by row: vertex u's row is its chain edge (u, u+1) followed
+    # by its extra heads in increasing order (all > u+1), so rows come out
+    # sorted by target with no edge-list sort.
+    deg = cnt.copy()
+    deg[: n - 1] += 1
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(deg, out=offsets[1:])
+    targets = np.empty(int(offsets[-1]), dtype=np.uint32)
+    weights = np.empty(int(offsets[-1]), dtype=np.uint32)
     s2 = stream_seed(seed, 11)
-    for uu in np.nonzero(cnt)[0]:
+    for uu in range(n - 1):
+        o = int(offsets[uu])
+        targets[o] = uu + 1
+        weights[o] = 1
         k = int(cnt[uu])
+        if k == 0:
+            continue
         # k distinct heads among uu+2 .. n-1: the k smallest of one random draw per candidate
         cand = np.arange(uu + 2, n, dtype=np.int64)
-        r = rand_u64(s2, np.arange(uu * n, uu * n + cand.shape[0], dtype=np.uint64))
-        pick = cand if k == cand.shape[0] else cand[np.argpartition(r, k - 1)[:k]]
-        srcs.append(np.full(k, uu, dtype=np.int64))
-        dsts.append(np.sort(pick))
-    src = np.concatenate(srcs)
-    dst = np.concatenate(dsts)
-    w = np.where(dst == src + 1, 1, 2 * (dst - src)).astype(np.uint32)
-    return csr_from_edges(n, src.astype(np.uint64), dst.astype(np.uint64), w, f"dag_{n}_{m}")
+        if k == cand.shape[0]:
+            pick = cand
+        else:
+            r = rand_u64(s2, np.arange(uu * n, uu * n + cand.shape[0], dtype=np.uint64))
+            pick = np.sort(cand[np.argpartition(r, k - 1)[:k]])
+        targets[o + 1:o + 1 + k] = pick
+        weights[o + 1:o + 1 + k] = 2 * (pick - uu)
+    return Graph(f"dag_{n}_{m}", n, offsets, targets, weights)
 
 
 # ---------------------------------------------------------------------------
