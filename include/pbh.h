@@ -324,6 +324,38 @@ int sssp_batch(const sssp_query *queries, uint32_t nq, const sssp_opts *opts, ss
                void *stream);
 
 /*
+ * sssp_nearfar: single-source shortest paths by Near-Far, the GPU form of
+ * Delta-stepping (Meyer and Sanders; Davidson et al. 2014) that the paper
+ * compares parDijkstra against (Sections 1.1 and 4.2: Gunrock and ADDS are
+ * Delta-stepping codes).  A baseline, not the paper's method: vertices whose
+ * tentative distance is below a threshold T form the near frontier and are
+ * scanned phase by phase; the others wait in a far pile until T has grown
+ * past them by steps of delta (0 = Davidson et al.'s choice, mean weight x 64
+ * / mean out-degree).  Exact for any delta.  One cooperative launch over
+ * every compute unit; graph and dist_out as for sssp (device arrays).  stats
+ * (host, may be NULL) receives edges scanned, phases, threshold steps, the
+ * delta used, the workgroups and the kernel's HIP-event time.  The call
+ * allocates and frees its own work space (about 40 bytes per vertex).
+ * Errors: PBH_EINVAL (NULL arrays, n == 0, source >= n, malformed CSR),
+ * PBH_ENOMEM, PBH_EDEVICE, PBH_ETIMEOUT (a grid barrier's bounded wait ran
+ * out), PBH_EINTERNAL (a queue overflowed or the phase limit was reached);
+ * sssp_nearfar_last_error() describes the last failure of the calling thread.
+ */
+typedef struct {
+  uint64_t relaxations; /* edges scanned */
+  uint32_t phases;      /* relax and threshold phases */
+  uint32_t splits;      /* threshold steps */
+  uint64_t delta;       /* delta used */
+  uint32_t workgroups;
+  uint32_t reserved;
+  double kernel_ms;
+} sssp_nearfar_stats;
+int sssp_nearfar(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,
+                 uint64_t m, uint32_t source, uint64_t *dist_out, uint64_t delta, sssp_nearfar_stats *stats,
+                 void *stream);
+const char *sssp_nearfar_last_error(void);
+
+/*
  * sssp_autotune: picks opts->d and opts->k_max for this query by timing trial
  * runs on the query itself.  A plain trial of n/32 rounds finds a distance
  * frontier D (the smallest key left after them); then each candidate

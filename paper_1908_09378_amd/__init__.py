@@ -55,6 +55,12 @@ class SsspStats(C.Structure):
                 ("kernel_ms", C.c_double), ("last_key", C.c_uint64)]
 
 
+class NearFarStats(C.Structure):
+    _fields_ = [("relaxations", C.c_uint64), ("phases", C.c_uint32), ("splits", C.c_uint32),
+                ("delta", C.c_uint64), ("workgroups", C.c_uint32), ("reserved", C.c_uint32),
+                ("kernel_ms", C.c_double)]
+
+
 class SsspQuery(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("targets", C.c_void_p), ("weights", C.c_void_p), ("m", C.c_uint64),
                 ("n", C.c_uint32), ("source", C.c_uint32), ("dist_out", C.c_void_p)]
@@ -63,7 +69,7 @@ class SsspQuery(C.Structure):
 _lib = None
 EXPORTS = ["pbh_create", "pbh_create_ex", "pbh_bulk_update", "pbh_delete", "pbh_extract_min", "pbh_size", "pbh_traffic", "pbh_merge_profile", "pbh_kernel_profile", "pbh_set_profiling", "pbh_destroy",
            "pbh_debug_levels", "sssp", "sssp_ex", "sssp_noalloc", "sssp_batch", "sssp_autotune", "sssp_batch_autotune", "mlp_trace_labels", "mlp_feature_stats",
-           "mlp_grad", "mlp_train", "mlp_infer", "pbh_last_error"]
+           "mlp_grad", "mlp_train", "mlp_infer", "sssp_nearfar", "pbh_last_error"]
 
 
 def lib():
@@ -99,6 +105,8 @@ def lib():
         L.mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
         L.mlp_train.argtypes = [vp, vp, u32, vp, u32, u32, C.c_float, C.POINTER(C.c_float)]
         L.mlp_infer.argtypes = [vp, u32, vp, u32, vp]
+        L.sssp_nearfar.argtypes = [vp, vp, vp, u32, u64, u32, vp, u64, C.POINTER(NearFarStats), vp]
+        L.sssp_nearfar_last_error.restype = C.c_char_p
         L.pbh_last_error.restype = C.c_char_p
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = C.c_int
@@ -180,6 +188,21 @@ def sssp_noalloc(offsets, targets, weights, n: int, m: int, source: int, dist_ou
     _check(lib().sssp_noalloc(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source,
                               _ptr(dist_out, 8), C.byref(o), C.byref(s), sp))
     return _stats_dict(s)
+
+
+def sssp_nearfar(offsets, targets, weights, n: int, m: int, source: int, dist_out, delta: int = 0, *,
+                 stream=None) -> dict:
+    """Near-Far (Delta-stepping) baseline: dist_out = shortest distances from
+    source; delta = 0 picks mean weight x 64 / mean degree (sssp_nearfar in
+    include/pbh.h)."""
+    s = NearFarStats()
+    sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = lib().sssp_nearfar(_ptr(offsets, 8), _ptr(targets, 4), _ptr(weights, 4), n, m, source,
+                            _ptr(dist_out, 8), delta, C.byref(s), sp)
+    if rc != PBH_OK:
+        raise PBHError(rc, lib().sssp_nearfar_last_error().decode())
+    return dict(relaxations=s.relaxations, phases=s.phases, splits=s.splits, delta=s.delta,
+                workgroups=s.workgroups, kernel_ms=s.kernel_ms)
 
 
 def _tuned(o) -> dict:

@@ -142,3 +142,13 @@ def test_engine_states_follow_the_theorem1_schedule(engine, d):
         for f, gf in (("nB", "nB"), ("nS", "nS"), ("pk", "pk"), ("pv", "pv"), ("cnt", "resolves")):
             assert np.array_equal(np.asarray(G[gf][:q], np.uint64), np.asarray(M[f][:q], np.uint64)), (j, f)
     h.close()
+
+
+def test_paper_dag_m4e7_closed_form():
+    """The paper's DAG at n = 30,000 and m = 4e7 (Section 4.2): parDijkstra's
+    distances equal the closed form dist(i) = i, one round per vertex."""
+    g = W.paper_dag(30000, 40_000_000, seed=11)
+    print("[full] paper DAG m=4e7", flush=True)
+    got, st = run_sssp(pkg, g, 0, team=1024)
+    assert np.array_equal(got, np.arange(g.n, dtype=np.uint64))
+    assert st["rounds"] == g.n and st["relaxations"] == g.m
