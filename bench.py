@@ -43,7 +43,8 @@ sys.path.insert(0, ROOT)
 METRIC = "SSSP GTEPS (m/time) on 1 MI355X: learned-threshold & batched vs plain parDijkstra"
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1908_09378_amd", "csrc")
-KERNEL_SOURCES = ["pbh_core.h", "pbh_team.h", "pbh_launch.h", "kernels.hip", "wide.h", "wide.hip", "learn.hip"]
+KERNEL_SOURCES = ["pbh_core.h", "pbh_team.h", "pbh_launch.h", "kernels.hip", "wide.h", "wide.hip", "learn.hip",
+                  "nearfar.hip"]
 
 RING_DESC = "ring lattice n=2^20, 16 neighbours per side, w~U[1,1000], source 0"
 GRID64_DESC = "4-neighbour grid 64x64, w~U[1,100], source 0"
@@ -161,6 +162,41 @@ class Query:
                 "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
                 "roofline": roofline("k_sssp", workload, sssp_bytes(st), kern_ms)}
 
+    def nearfar(self, steps, factors=(0.25, 1.0, 4.0)):
+        """The Near-Far (Delta-stepping) baseline on the same graph: delta =
+        f x Davidson et al.'s choice for each f, one untimed and `steps` timed
+        runs each; the fastest delta is the record, the others are listed."""
+        import numpy as np
+        import torch
+        import paper_1908_09378_amd as pkg
+        base = pkg.sssp_nearfar(self.off, self.tg, self.wt, self.g.n, self.g.m, self.src, self.dist)["delta"]
+        tried = []
+        for f in factors:
+            delta = max(1, int(base * f))
+            pkg.sssp_nearfar(self.off, self.tg, self.wt, self.g.n, self.g.m, self.src, self.dist, delta)
+            torch.cuda.synchronize()
+            stats = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                stats.append(pkg.sssp_nearfar(self.off, self.tg, self.wt, self.g.n, self.g.m, self.src, self.dist,
+                                              delta))
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            ex = self.exact()
+            st = stats[-1]
+            tried.append({"delta": delta, "value": self.g.m / sec / 1e9, "ms_per_step": sec * 1e3, "exact": ex,
+                          "relaxations": st["relaxations"], "phases": st["phases"], "splits": st["splits"],
+                          "kernel_ms": sum(x["kernel_ms"] for x in stats) / len(stats)})
+            log(f"nearfar delta={delta}: {sec * 1e3:.1f} ms, {st['phases']} phases, exact={ex}")
+        best = min(tried, key=lambda r: r["ms_per_step"])
+        abytes = 16 * best["relaxations"]  # per scanned edge: target + weight + the dist atomic
+        return {"unit": "GTEPS", "value": best["value"], "ms_per_step": best["ms_per_step"], "steps": steps,
+                "delta": best["delta"], "exact": all(r["exact"] for r in tried),
+                "method": "Near-Far (Delta-stepping), one cooperative launch over every CU; the fastest of "
+                          "delta = f x (mean weight x 64 / mean degree), f in " + str(list(factors)),
+                "roofline": roofline("k_nearfar", "nearfar", abytes, best["kernel_ms"]),
+                "tried": tried}
+
     def tune(self, **kw):
         import torch
         import paper_1908_09378_amd as pkg
@@ -206,7 +242,8 @@ def run_ring(args):
     rec["plain_tuned"] = pt
     rec["speedup_vs_plain"] = lr["value"] / pl["value"]
     rec["speedup_vs_plain_tuned"] = lr["value"] / pt["value"]
-    rec["exact"] = lr["exact"] and pl["exact"] and pt["exact"]
+    rec["nearfar"] = q.nearfar(args.base_steps)
+    rec["exact"] = lr["exact"] and pl["exact"] and pt["exact"] and rec["nearfar"]["exact"]
     rec["config"] = {"workload": RING_DESC, "method": lr["method"], "n": g.n, "m": g.m, "d": lr["d"],
                      "team": lr["team"], "levels": lr["levels"], "lds_levels": lr["lds_levels"],
                      "parallelism": "1 workgroup per query"}
@@ -255,10 +292,11 @@ def run_grid8(args):
     pl = q.record(*q.timed(1, 0, "grid8 plain", **GRID8_PLAIN),
                   "plain parDijkstra (k = 1), d = 512, team 64 (autotuned settings for this graph)",
                   "grid8_plain", 1, 0)
+    nfr = q.nearfar(args.base_steps)
     rec = {"metric": "SSSP GTEPS (m/time), learned threshold", **lr,
            "config": {"workload": GRID8_DESC, "n": g.n, "m": g.m}, "plain": pl,
-           "speedup_vs_plain": lr["value"] / pl["value"],
-           "reinsertions": lr["extracted"] - g.n, "exact": lr["exact"] and pl["exact"]}
+           "speedup_vs_plain": lr["value"] / pl["value"], "nearfar": nfr,
+           "reinsertions": lr["extracted"] - g.n, "exact": lr["exact"] and pl["exact"] and nfr["exact"]}
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
     return rec
@@ -520,18 +558,42 @@ def run_heap(args):
 def run_dag(args):
     """The paper's high-diameter DAG (Section 4.2): n = 30,000, a weight-1
     chain plus random forward edges of weight 2(v-u); distances checked
-    against the closed form dist(i) = i."""
+    against the closed form dist(i) = i after every run.  --dag-m sets m,
+    --dag-seeds the number of random DAGs (the paper: 5) and --dag-trials the
+    timed runs on each (the paper: 10; one untimed run first).  Plain
+    parDijkstra and the Near-Far baseline run on every DAG; the means over all
+    DAGs and trials are the record."""
     import numpy as np
     import workloads as W
-    g = W.paper_dag(30000, args.dag_m, seed=11)
-    q = Query(g, 0, np.arange(g.n, dtype=np.uint64))
-    pl = q.record(*q.timed(args.base_steps, 1, "dag plain"), "plain parDijkstra (k = 1, d = max out-degree)",
-                  "dag", args.base_steps, 1)
-    rec = {"metric": "SSSP GTEPS (m/time), plain parDijkstra", **pl,
-           "config": {"workload": f"the paper's DAG: n=30000, m={g.m}, chain of weight 1 plus random forward "
-                                  f"edges of weight 2(v-u), source 0", "n": g.n, "m": g.m}}
+    per = []
+    for si in range(args.dag_seeds):
+        t0 = time.perf_counter()
+        g = W.paper_dag(30000, args.dag_m, seed=11 + si)
+        log(f"dag seed {11 + si}: m={g.m} built in {time.perf_counter() - t0:.1f} s")
+        q = Query(g, 0, np.arange(g.n, dtype=np.uint64))
+        pl = q.record(*q.timed(args.dag_trials, 1, "dag plain", team=1024),
+                      "plain parDijkstra (k = 1, d = max out-degree, 1024 threads)", "dag", args.dag_trials, 1)
+        nfr = q.nearfar(args.dag_trials, factors=(1.0,))
+        per.append({"seed": 11 + si, "plain": pl, "nearfar": nfr})
+        if si == 0 and not args.no_cpu:
+            cpu = cpu_sssp(g, 0, args.cpu_budget)
+        del q, g
+    mean = lambda xs: sum(xs) / len(xs)
+    pl_ms = mean([p["plain"]["ms_per_step"] for p in per])
+    nf_ms = mean([p["nearfar"]["ms_per_step"] for p in per])
+    rec = {"metric": "SSSP GTEPS (m/time), plain parDijkstra", "unit": "GTEPS", "value": args.dag_m / pl_ms * 1e-6,
+           "ms_per_step": pl_ms, "steps": args.dag_trials, "warmup": 1,
+           "us_per_round": mean([p["plain"]["us_per_round"] for p in per]),
+           "roofline": per[0]["plain"]["roofline"],
+           "nearfar": {"value": args.dag_m / nf_ms * 1e-6, "ms_per_step": nf_ms,
+                       "speedup_of_pardijkstra": nf_ms / pl_ms},
+           "exact": all(p["plain"]["exact"] and p["nearfar"]["exact"] for p in per),
+           "config": {"workload": f"the paper's DAGs: n=30000, m={args.dag_m}, chain of weight 1 plus random forward "
+                                  f"edges of weight 2(v-u), source 0; {args.dag_seeds} seeds x {args.dag_trials} "
+                                  f"timed trials", "n": 30000, "m": args.dag_m},
+           "per_dag": per}
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
+        rec["cpu_baseline"] = cpu
     return rec
 
 
@@ -569,6 +631,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--heap-rounds", type=int, default=256)
     ap.add_argument("--dag-m", type=int, default=40_000_000)
+    ap.add_argument("--dag-seeds", type=int, default=1)
+    ap.add_argument("--dag-trials", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
