@@ -234,7 +234,8 @@ typedef struct {
   uint32_t max_rounds;
   uint32_t d_scale;       /* with d == 0: d = maximum out-degree * max(1, d_scale) */
   float k_scale;          /* learned rule: k = 2^(k_scale * scale * y); 0 means 1 */
-  uint32_t reserved;      /* must be zero */
+  uint32_t k_every;       /* learned rule: the model runs every k_every-th round and the
+                             rounds between reuse its k (0 or 1 = every round) */
   /* Extraction record (may be NULL): settle_order[j] receives the id of the
    * j-th extracted vertex, for j < settle_cap (device array).  With the plain
    * rule this is parDijkstra's settle order; a round that extracts k > 1

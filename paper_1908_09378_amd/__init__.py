@@ -44,7 +44,7 @@ class SsspOpts(C.Structure):
                 ("trace_features", C.c_void_p), ("trace_keys", C.c_void_p), ("trace_ids", C.c_void_p),
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
                 ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
-                ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("reserved", C.c_uint32),
+                ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("k_every", C.c_uint32),
                 ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64)]
 
 
@@ -144,8 +144,9 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
-          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None):
+          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None, k_every=0):
     o = SsspOpts()
+    o.k_every = k_every
     if settle_order is not None:
         o.settle_order, o.settle_cap = _ptr(settle_order, 4), settle_order.numel()
     o.k_scale = k_scale
@@ -206,7 +207,7 @@ def sssp_nearfar(offsets, targets, weights, n: int, m: int, source: int, dist_ou
 
 
 def _tuned(o) -> dict:
-    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max, team=o.team, k_scale=o.k_scale)
+    return dict(d=o.d, d_scale=o.d_scale, k_max=o.k_max, team=o.team, k_scale=o.k_scale, k_every=o.k_every)
 
 
 def sssp_autotune(offsets, targets, weights, n: int, m: int, source: int, dist_out, *, stream=None, **kw) -> dict:

@@ -204,7 +204,7 @@ int spec_from_opts(const sssp_opts& o, u32 d, SpecCfg* sc, u32* kmax_out) {
   sc->stop_key = o.stop_key;
   sc->max_rounds = o.max_rounds;
   sc->kscale = o.k_scale > 0.0f ? o.k_scale : 1.0f;
-  if (o.reserved) return fail(PBH_EINVAL, "sssp: opts.reserved must be zero");
+  sc->kevery = o.k_every > 1 ? o.k_every : 1u;
   *kmax_out = kmax;
   return PBH_OK;
 }

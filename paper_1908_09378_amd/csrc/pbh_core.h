@@ -1041,6 +1041,7 @@ struct SpecCfg {
   u64 stop_key;
   u32 max_rounds;
   float kscale;  // learned rule: multiplies log2 k
+  u32 kevery;    // learned rule: the model runs every kevery-th round (>= 1)
   // LDS room for the round's list after the LDS levels: two buffers of lcap
   // pairs (keys, then ids); 0 = the intake sorts in global memory
   u32 lcap;
@@ -1075,6 +1076,7 @@ PBH_INL u64 b0_min_key(const T& t, const Geom& g, typename P::SP st) {
 
 struct RoundMemo {  // team-uniform facts about the previous round
   float avgdeg;
+  u32 k;  // the last k the learned rule proposed
 };
 
 PBH_INL float flog2p1(float x) { return __builtin_log2f(1.0f + x); }
@@ -1182,12 +1184,14 @@ PBH_INL float mlp_forward(const T& t, const float* m, const float* f) {
 
 template <class T, class SP, class A0>
 PBH_INL u32 propose_k(const T& t, const Geom& g, SP st, const SpecCfg& sc, A0 B, u32 nB, u64 round,
-                      const RoundMemo& memo) {
+                      RoundMemo& memo) {
   u32 k = 1;
   if (sc.rule == 1) {
     k = sc.kfix;
   } else if (sc.rule == 3) {
     k = sc.kseq[round % sc.kseq_len];
+  } else if (sc.rule == 2 && sc.kevery > 1 && round % sc.kevery != 0) {
+    k = memo.k;  // between model runs the last proposal stands
   } else if (sc.rule == 2) {
     float f[NFEAT];
     round_features(t, g, st, B, nB, memo, f);
@@ -1200,7 +1204,9 @@ PBH_INL u32 propose_k(const T& t, const Geom& g, SP st, const SpecCfg& sc, A0 B,
   }
   k = k < 1 ? 1 : k;
   k = k > sc.kmax ? sc.kmax : k;
-  return k > (u32)KMAX_ROUND ? (u32)KMAX_ROUND : k;
+  k = k > (u32)KMAX_ROUND ? (u32)KMAX_ROUND : k;
+  memo.k = k;
+  return k;
 }
 
 // Records one training trace: features and the TRACE_K smallest (key, id) of
@@ -1510,7 +1516,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
   }
   t.sync();
   SsspCounters c{0, 0, 1, 0, KINF, 0};
-  RoundMemo memo{0.0f};
+  RoundMemo memo{0.0f, 1u};
   u32 upos = 0, ulen = 0;
   for (;;) {
     // Resolve(0) and the schedule after the previous operation (the source's

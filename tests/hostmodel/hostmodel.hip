@@ -326,6 +326,7 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   sc.kseq_len = kseq_len;
   sc.model = model;
   sc.kscale = 1.0f;
+  sc.kevery = 1;
   sc.stop_key = stop_key;
   sc.max_rounds = max_rounds;
   std::vector<u64> uk(2ull * sc.kmax * d);
