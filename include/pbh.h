@@ -243,6 +243,11 @@ typedef struct {
    * (sssp_batch ignores it). */
   uint32_t *settle_order;
   uint64_t settle_cap;
+  /* Time accounting (sssp_ex only; 0 = off): the round loop reads the
+   * device's constant-rate clock around every Resolve and between the steps
+   * of each round, and sssp_stats.level_us / phase_us receive the totals.
+   * Adds a little time to every round; no effect on results. */
+  uint32_t profile;
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
@@ -264,6 +269,13 @@ typedef struct {
   double kernel_ms;       /* device time of the round-loop kernel (HIP events) */
   uint64_t last_key;      /* smallest key left in the heap when the rounds stopped
                              (UINT64_MAX if the heap ran empty; largest over a batch) */
+  /* With opts->profile (sssp_ex): microseconds inside Resolve(i) per level,
+   * and per round step: [0] Resolve(0) + schedule + refills after each
+   * operation (it includes the level times), [1] moving update pieces into
+   * S_0, [2] features + MLP, [3] extraction from B_0, [4] relaxation,
+   * [5] intake of the round's updates, [6] the rest.  Zero otherwise. */
+  double level_us[16];
+  double phase_us[8];
 } sssp_stats;
 
 /*

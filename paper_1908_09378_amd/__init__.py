@@ -45,14 +45,15 @@ class SsspOpts(C.Structure):
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
                 ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
                 ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("k_every", C.c_uint32),
-                ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64)]
+                ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64), ("profile", C.c_uint32)]
 
 
 class SsspStats(C.Structure):
     _fields_ = [("rounds", C.c_uint64), ("relaxations", C.c_uint64), ("updates", C.c_uint64),
                 ("heap_elems", C.c_uint64), ("extracted", C.c_uint64), ("resolves", C.c_uint64 * 16),
                 ("levels", C.c_uint32), ("d", C.c_uint32), ("team", C.c_uint32), ("lds_levels", C.c_uint32),
-                ("kernel_ms", C.c_double), ("last_key", C.c_uint64)]
+                ("kernel_ms", C.c_double), ("last_key", C.c_uint64), ("level_us", C.c_double * 16),
+                ("phase_us", C.c_double * 8)]
 
 
 class NearFarStats(C.Structure):
@@ -134,7 +135,12 @@ def _ptr(t, elem_bytes):
 def _stats_dict(s):
     return dict(rounds=s.rounds, relaxations=s.relaxations, updates=s.updates, heap_elems=s.heap_elems,
                 extracted=s.extracted, resolves=list(s.resolves), levels=s.levels, d=s.d, team=s.team,
-                lds_levels=s.lds_levels, kernel_ms=s.kernel_ms, last_key=s.last_key)
+                lds_levels=s.lds_levels, kernel_ms=s.kernel_ms, last_key=s.last_key, level_us=list(s.level_us),
+                phase_us=dict(zip(PHASES, s.phase_us)))
+
+
+# sssp_stats.phase_us slots (see include/pbh.h)
+PHASES = ("drive", "piece", "propose", "extract", "relax", "intake", "other")
 
 
 def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> None:
@@ -144,8 +150,10 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
-          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None, k_every=0):
+          k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None, k_every=0,
+          profile=0):
     o = SsspOpts()
+    o.profile = profile
     o.k_every = k_every
     if settle_order is not None:
         o.settle_order, o.settle_cap = _ptr(settle_order, 4), settle_order.numel()

@@ -618,6 +618,7 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
         lds += (size_t)lcap * 24u;
       }
     }
+    p.prof = o.profile ? 1u : 0u;
     p.spec.order = o.settle_order;
     p.spec.order_cap = o.settle_order ? o.settle_cap : 0;
     if (o.trace_features) {
@@ -685,6 +686,13 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
       stats->team = (u32)team;
       stats->lds_levels = (u32)qlds;
       stats->kernel_ms = ms;
+      if (o.profile) {
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const double us = khz > 0 ? 1e3 / (double)khz : 0.0;  // microseconds per tick
+        for (int i = 0; i < 16 && i < MAXL; ++i) stats->level_us[i] = (double)ds.prof[i] * us;
+        for (int i = 0; i < 8 && MAXL + i < PROF_N; ++i) stats->phase_us[i] = (double)ds.prof[MAXL + i] * us;
+      }
     }
     return PBH_OK;
   }

@@ -63,7 +63,10 @@ __device__ void sssp_query(DevTeam<NT>& t, HeapState PBH_LDS* st, unsigned char*
   const u64 nl = lvl_off(g.d, g.qlds);
   g.lk = reinterpret_cast<u64*>(dyn);
   g.lv = reinterpret_cast<u32*>(dyn + nl * sizeof(u64));
-  if (threadIdx.x == 0) state_init(st, g.d, g.q);
+  if (threadIdx.x == 0) {
+    state_init(st, g.d, g.q);
+    st->prof_on = p.prof;
+  }
   t.sync();
   SsspCounters c;
   sssp_rounds<DevTeam<NT>, DevPolicy>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, p.spec, &c);
@@ -79,6 +82,7 @@ __device__ void sssp_query(DevTeam<NT>& t, HeapState PBH_LDS* st, unsigned char*
     o->err = st->err;
     o->ell = st->ell;
     for (int i = 0; i < MAXL; ++i) o->resolves[i] = st->L[i].cnt;
+    for (int i = 0; i < PROF_N; ++i) o->prof[i] = st->prof[i];
   }
   t.sync();
 }

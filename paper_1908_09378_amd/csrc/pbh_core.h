@@ -94,6 +94,20 @@ struct Lvl {
   u32 cnt;       // Resolve(i) executions
 };
 
+// Time accounting of a profiled SSSP run (ticks of the device's constant
+// real-time clock): prof[i] for i < MAXL is the time inside Resolve(i); the
+// other slots split each round into its steps.
+enum {
+  PROF_DRIVE = MAXL,  // Resolve(0), the schedule and refills after each operation
+  PROF_PIECE,         // moving the next piece of a round's update list into S_0
+  PROF_PROPOSE,       // features and the MLP (learned rule)
+  PROF_EXTRACT,       // choosing and removing the round's minima from B_0
+  PROF_RELAX,         // scanning their out-edges (atomicMin on dist)
+  PROF_INTAKE,        // the round's updates: filter, sort by id, deduplicate
+  PROF_OTHER,
+  PROF_N
+};
+
 struct HeapState {
   Lvl L[MAXL];
   int ell;       // deepest non-empty level, -1 if the heap is empty
@@ -104,7 +118,33 @@ struct HeapState {
   u64 live;      // elements in the heap (queue size)
   u64 progress;  // resumable progress of a multi-piece operation
   u64 aux[5];
+  u32 prof_on;   // time accounting on (SSSP kernels only)
+  u32 prof_pad;
+  u64 prof_last;  // clock at the last lap mark
+  u64 prof_res;   // clock at the start of the running Resolve
+  u64 prof[PROF_N];
 };
+
+// The device's constant-rate real-time clock (0 on the host).
+PBH_INL u64 pbh_clock() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_s_memrealtime();
+#else
+  return 0;
+#endif
+}
+
+// Lap mark of a profiled run: the time since the previous mark goes to `cat`.
+// One thread keeps the books; marks sit after the team's barriers, so the
+// time of a step includes its slowest wavefront.
+template <class T, class SP>
+PBH_INL void prof_lap(const T& t, SP st, int cat) {
+  if (t.tid() == 0 && st->prof_on) {
+    const u64 now = pbh_clock();
+    st->prof[cat] += now - st->prof_last;
+    st->prof_last = now;
+  }
+}
 
 template <class SP>
 PBH_HD inline void state_init(SP st, u32 d, int q) {
@@ -119,6 +159,9 @@ PBH_HD inline void state_init(SP st, u32 d, int q) {
   st->q = q;
   st->elems = st->live = st->progress = 0;
   for (int i = 0; i < 5; ++i) st->aux[i] = 0;
+  st->prof_on = st->prof_pad = 0;
+  st->prof_last = st->prof_res = 0;
+  for (int i = 0; i < PROF_N; ++i) st->prof[i] = 0;
 }
 
 // Field-wise copies of a level's state (the state may live in LDS, whose
@@ -774,12 +817,14 @@ done:
 template <class T, class P>
 PBH_INL void resolve(const T& t, const Geom& g, typename P::SP st, const u64* cur, int i) {
   P::on_resolve(g, st, i, false);
+  if (t.tid() == 0 && st->prof_on) st->prof_res = pbh_clock();
   if (i + 1 < g.qlds)
     resolve_t<T, P, typename P::L, typename P::L>(t, g, st, cur, i);
   else if (i < g.qlds)
     resolve_t<T, P, typename P::L, typename P::G>(t, g, st, cur, i);
   else
     resolve_t<T, P, typename P::G, typename P::G>(t, g, st, cur, i);
+  if (t.tid() == 0 && st->prof_on) st->prof[i] += pbh_clock() - st->prof_res;
   P::on_resolve(g, st, i, true);
 }
 
@@ -962,6 +1007,7 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
   u32 n0, n1, n2;
   A0 T0 = as_arr<A0>(lbuf(g, 0, 2));
   partition3(t, B, a0.nB, KV{mk, mv}, kv_inf(), T0, as_arr<A0>(lbuf(g, 0, a0.bsel ^ 1)), T0, &n0, &n1, &n2);
+  prof_lap(t, st, PROF_EXTRACT);
   A0 S = as_arr<A0>(lbuf(g, 0, 3));
   u32 nu = 0;
   for (u64 eb = e0; eb < e1; eb += (u64)T::kNT) {
@@ -983,6 +1029,7 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
     nu += tot;
   }
   t.sync();
+  prof_lap(t, st, PROF_RELAX);
   nu = intake(t, S, nu, T0, as_arr<A0>(lbuf(g, 0, 4)), dist, idbits);
   if (t.tid() == 0) {
     st->L[0].bsel = a0.bsel ^ 1;
@@ -993,6 +1040,7 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
     if (st->ell < 0 && (n1 + nu) > 0) st->ell = 0;
   }
   t.sync();
+  prof_lap(t, st, PROF_INTAKE);
   *relax += e1 - e0;
   *upd += nu;
   return true;
@@ -1382,6 +1430,7 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
   if (sc.order)
     for (u32 j = (u32)t.tid(); j < take; j += (u32)T::kNT)
       if (c->extracted + j < sc.order_cap) sc.order[c->extracted + j] = X.v[j];
+  prof_lap(t, st, PROF_EXTRACT);
   // out-degree prefix sums of the extracted vertices
   u32 E = 0;
   for (u32 base = 0; base < take; base += (u32)T::kNT) {
@@ -1452,6 +1501,7 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
     nu += tot;
   }
   t.sync();
+  prof_lap(t, st, PROF_RELAX);
   if (sc.lcap != 0 && nu <= sc.lcap) {
     // the list fits in the LDS after the levels: sort it there
     using L = typename P::L;
@@ -1473,6 +1523,7 @@ PBH_INL bool round_spec(const T& t, const Geom& g, typename P::SP st, const u64*
     if (st->ell < 0 && n1 > 0) st->ell = 0;
   }
   t.sync();
+  prof_lap(t, st, PROF_INTAKE);
   c->relax += E;
   c->updates += nu;
   c->extracted += take;
@@ -1513,6 +1564,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     st->L[0].nS = 1;
     st->L[0].ssel = 0;
     st->ell = 0;
+    st->prof_last = pbh_clock();
   }
   t.sync();
   SsspCounters c{0, 0, 1, 0, KINF, 0};
@@ -1523,6 +1575,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     // insertion, a round's bulk update or a piece of it), then make sure B_0
     // holds the minimum if the heap is not empty.
     drive<T, P>(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
+    prof_lap(t, st, PROF_DRIVE);
     if (st->err) break;
     hook(g, st, c);
     if (upos < ulen) {  // next piece of the round's bulk update
@@ -1548,6 +1601,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
         if (st->ell < 0) st->ell = 0;
       }
       t.sync();
+      prof_lap(t, st, PROF_PIECE);
       upos += len;
       continue;
     }
@@ -1566,6 +1620,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
       t.sync();
       break;
     }
+    prof_lap(t, st, PROF_OTHER);
     bool more;
     if (sc.rule == 0 && !sc.trace_f) {
       more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
@@ -1581,11 +1636,13 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
         typename P::L B = as_arr<typename P::L>(Bg);
         if (sc.trace_f && a0.nB && c.rounds % sc.trace_every == 0) record_trace(t, g, st, sc, B, a0.nB, memo);
         k = propose_k(t, g, st, sc, B, a0.nB, c.rounds, memo);
+        prof_lap(t, st, PROF_PROPOSE);
         more = round_spec<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, k, sc, &c, &memo, &ulen);
       } else {
         G B = as_arr<G>(Bg);
         if (sc.trace_f && a0.nB && c.rounds % sc.trace_every == 0) record_trace(t, g, st, sc, B, a0.nB, memo);
         k = propose_k(t, g, st, sc, B, a0.nB, c.rounds, memo);
+        prof_lap(t, st, PROF_PROPOSE);
         more = round_spec<T, P, G>(t, g, st, off, tg, wt, dist, idbits, k, sc, &c, &memo, &ulen);
       }
       upos = 0;

@@ -12,6 +12,7 @@ struct SsspDevStats {
   long long err;
   long long ell;
   u64 resolves[MAXL];
+  u64 prof[PROF_N];  // time accounting of a profiled run (HeapState::prof)
 };
 
 struct SsspParams {
@@ -25,6 +26,7 @@ struct SsspParams {
   Geom g;  // lk/lv are set inside the kernel
   SsspDevStats* stats;
   SpecCfg spec;
+  u32 prof;  // time accounting on (single queries only)
 };
 
 

@@ -57,3 +57,27 @@ def test_sssp_rejects_bad_sizes_before_device_work():
     assert L.sssp(dummy, dummy, dummy, 0, 0, 0, dummy) == pkg.PBH_EINVAL
     assert L.sssp(dummy, dummy, dummy, 5, 0, 5, dummy) == pkg.PBH_EINVAL
     assert b"source" in L.pbh_last_error()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout: size and
+    every field offset, as a C compiler lays them out from include/pbh.h."""
+    import subprocess
+    mirrors = {"pbh_opts": pkg.PbhOpts, "sssp_opts": pkg.SsspOpts, "sssp_stats": pkg.SsspStats,
+               "sssp_query": pkg.SsspQuery, "sssp_nearfar_stats": pkg.NearFarStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pbh.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

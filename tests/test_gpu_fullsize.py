@@ -25,6 +25,7 @@ pytestmark = pytest.mark.gpu
 INF = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 
+@pytest.mark.timeout(900)
 def test_heap_all_256_rounds_full_size():
     n_ids, d, ext, rounds = 1 << 24, 1 << 20, 1 << 16, 256
     keys, ids = W.heap_init_pairs(n_ids, seed=3)
