@@ -27,8 +27,16 @@ def build(sanitize: bool = False) -> str:
     return out
 
 
+def _asan_runtime_loaded() -> bool:
+    with open("/proc/self/maps") as f:
+        return "libclang_rt.asan" in f.read()
+
+
 def lib():
     sanitize = os.environ.get("PBH_HOSTMODEL_ASAN") == "1"
+    if sanitize and not _asan_runtime_loaded():
+        raise RuntimeError("PBH_HOSTMODEL_ASAN=1 needs the ASan runtime loaded before Python starts: "
+                           "run tests/hostmodel/asan.sh (it sets LD_PRELOAD)")
     if sanitize not in _lib:
         L = C.CDLL(build(sanitize))
         u64p, u32p = C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
