@@ -248,6 +248,18 @@ typedef struct {
    * of each round, and sssp_stats.level_us / phase_us receive the totals.
    * Adds a little time to every round; no effect on results. */
   uint32_t profile;
+  /* Deep-level workers (sssp_ex and sssp_noalloc; Section 2.2.1, Theorem 1,
+   * Section 4.1's block per level).  0 = off: the workgroup that runs the
+   * rounds resolves every level itself.  L > 0: every level i >= max(L, 2,
+   * the LDS levels) gets a workgroup of its own that runs Resolve(i) when
+   * the level above asks for it (after every fourth Resolve of that level),
+   * while the rounds go on; levels two apart resolve at the same time and
+   * adjacent ones never do.  The round loop and the workers are one
+   * cooperative launch of 1 + (levels - first worker level) workgroups; every
+   * wait between them is bounded (PBH_ETIMEOUT after 10 s without progress).
+   * Same distances; rounds and relaxations as without workers for the plain
+   * rule.  Needs schedule 0.  Ignored by sssp_batch. */
+  uint32_t deep_level;
 } sssp_opts;
 
 #define PBH_MLP_PARAMS (8 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
@@ -273,7 +285,10 @@ typedef struct {
    * and per round step: [0] Resolve(0) + schedule + refills after each
    * operation (it includes the level times), [1] moving update pieces into
    * S_0, [2] features + MLP, [3] extraction from B_0, [4] relaxation,
-   * [5] intake of the round's updates, [6] the rest.  Zero otherwise. */
+   * [5] intake of the round's updates, [6] the rest, [7] waiting for a
+   * deep-level worker (inside [0]).  With deep-level workers, level_us[i] of a
+   * worker level is that worker's time inside Resolve(i), off the round
+   * loop's path.  Zero otherwise. */
   double level_us[16];
   double phase_us[8];
 } sssp_stats;

@@ -45,7 +45,8 @@ class SsspOpts(C.Structure):
                 ("trace_count", C.c_void_p), ("trace_query", C.c_void_p), ("trace_every", C.c_uint32),
                 ("trace_cap", C.c_uint32), ("stop_key", C.c_uint64), ("max_rounds", C.c_uint32),
                 ("d_scale", C.c_uint32), ("k_scale", C.c_float), ("k_every", C.c_uint32),
-                ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64), ("profile", C.c_uint32)]
+                ("settle_order", C.c_void_p), ("settle_cap", C.c_uint64), ("profile", C.c_uint32),
+                ("deep_level", C.c_uint32)]
 
 
 class SsspStats(C.Structure):
@@ -140,7 +141,7 @@ def _stats_dict(s):
 
 
 # sssp_stats.phase_us slots (see include/pbh.h)
-PHASES = ("drive", "piece", "propose", "extract", "relax", "intake", "other")
+PHASES = ("drive", "piece", "propose", "extract", "relax", "intake", "other", "wait")
 
 
 def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> None:
@@ -151,9 +152,10 @@ def sssp(offsets, targets, weights, n: int, m: int, source: int, dist_out) -> No
 
 def _opts(d=0, team=0, schedule=0, lds_levels=0, heap_capacity=0, k_rule=0, k_fixed=0, k_max=0, k_seq=None,
           k_model=None, trace=None, stop_key=0, max_rounds=0, d_scale=0, k_scale=0.0, settle_order=None, k_every=0,
-          profile=0):
+          profile=0, deep_level=0):
     o = SsspOpts()
     o.profile = profile
+    o.deep_level = deep_level
     o.k_every = k_every
     if settle_order is not None:
         o.settle_order, o.settle_cap = _ptr(settle_order, 4), settle_order.numel()

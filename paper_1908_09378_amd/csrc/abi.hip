@@ -474,6 +474,7 @@ static std::mutex g_sssp_mu;
 static Arena g_sssp_arena;        // reused across calls
 static Arena g_sssp_list;         // round update lists of speculative rounds
 static SsspDevStats* g_sssp_stats = nullptr;
+static DeepCtl* g_deep_ctl = nullptr;  // control block of the deep-level workers
 static CsrCheck* g_csr = nullptr;
 
 }  // extern "C"
@@ -491,6 +492,7 @@ struct FixedScratch {
 // (one 4096-byte header), the HBM levels (12 B per element) and the
 // speculative rounds' update lists.
 constexpr u64 FIXED_HEAD = 4096;
+constexpr u64 FIXED_DEEP = 1024;  // the deep-level workers' control block inside the header
 u64 fixed_bytes(u64 arena_elems, u64 list_elems) { return FIXED_HEAD + 12ull * (arena_elems + list_elems); }
 
 // sssp_ex with the query index that trace records carry (0 for a single
@@ -513,7 +515,8 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
   if (fx) {
     csr = reinterpret_cast<CsrCheck*>(fx->base);
     dstats = reinterpret_cast<SsspDevStats*>(fx->base + 256);
-    static_assert(256 + sizeof(SsspDevStats) <= FIXED_HEAD, "header of the fixed block");
+    static_assert(256 + sizeof(SsspDevStats) <= FIXED_DEEP, "header of the fixed block");
+    static_assert(FIXED_DEEP + sizeof(DeepCtl) <= FIXED_HEAD, "header of the fixed block");
   } else {
     if (!g_csr) HIPCHK(hipMalloc(&g_csr, sizeof(CsrCheck)));
     if (!g_sssp_stats) HIPCHK(hipMalloc(&g_sssp_stats, sizeof(SsspDevStats)));
@@ -534,6 +537,7 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
   int team = (int)o.team;
   if (team == 0) team = d <= 256 ? 64 : (d <= 4096 ? 256 : 1024);
   if (team != 64 && team != 256 && team != 1024) return fail(PBH_EINVAL, "sssp: team must be 64, 256 or 1024");
+  if (o.deep_level && o.schedule != 0) return fail(PBH_EINVAL, "sssp: deep-level workers need schedule 0");
   // Heap capacity: the arena is sized for hcap elements.  With the plain rule
   // every inserted element is a strict improvement from one scanned edge, so
   // at most m + 1 are ever inserted; rules that pull ahead re-insert vertices
@@ -619,6 +623,36 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
       }
     }
     p.prof = o.profile ? 1u : 0u;
+    // LDS staging for merges of the HBM levels, after the LDS levels (it
+    // shares that room with the speculative rounds' list)
+    p.stage = 0;
+    if (q > qlds) {
+      const u64 sb = stage_bytes(team, team == 64 ? 8 : 4);
+      const size_t lvb = (size_t)lvl_off(d, qlds) * 12ull;
+      if (lvb + sb <= budget) {
+        p.stage = (u32)sb;
+        lds = std::max(lds, lvb + (size_t)sb);
+      }
+    }
+    // Deep-level workers: one workgroup per level from max(deep_level, 2,
+    // LDS levels) down (none if that is past the deepest level).
+    p.deep = nullptr;
+    p.deep_lim = MAXL;
+    if (o.deep_level) {
+      const int lim = std::max<int>(std::max<int>((int)std::min<u32>(o.deep_level, MAXL), 2), qlds);
+      if (lim < q) {
+        DeepCtl* ctl;
+        if (fx) {
+          ctl = reinterpret_cast<DeepCtl*>(fx->base + FIXED_DEEP);
+        } else {
+          if (!g_deep_ctl) HIPCHK(hipMalloc(&g_deep_ctl, (sizeof(DeepCtl) + 7) / 8 * 8));
+          ctl = g_deep_ctl;
+        }
+        HIPCHK(launch_zero_u64(reinterpret_cast<u64*>(ctl), (sizeof(DeepCtl) + 7) / 8, s));
+        p.deep = ctl;
+        p.deep_lim = lim;
+      }
+    }
     p.spec.order = o.settle_order;
     p.spec.order_cap = o.settle_order ? o.settle_cap : 0;
     if (o.trace_features) {
@@ -671,6 +705,8 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
       continue;
     }
     if (ds.err == E_CAPACITY) return fail(PBH_ECAPACITY, "sssp: heap levels overflowed at %d levels", q);
+    if (ds.err == E_TIMEOUT)
+      return fail(PBH_ETIMEOUT, "sssp: a wait between the round loop and a deep-level worker ran out");
     if (ds.err) return fail(PBH_EINTERNAL, "sssp: device-side heap check failed (code %lld)", ds.err);
     if (stats) {
       std::memset(stats, 0, sizeof *stats);

@@ -105,6 +105,7 @@ enum {
   PROF_RELAX,         // scanning their out-edges (atomicMin on dist)
   PROF_INTAKE,        // the round's updates: filter, sort by id, deduplicate
   PROF_OTHER,
+  PROF_WAIT,          // waiting for a deep-level worker (inside PROF_DRIVE)
   PROF_N
 };
 
@@ -119,7 +120,12 @@ struct HeapState {
   u64 progress;  // resumable progress of a multi-piece operation
   u64 aux[5];
   u32 prof_on;   // time accounting on (SSSP kernels only)
-  u32 prof_pad;
+  // Levels resolved by their own workers (the deep-level service of the SSSP
+  // kernel): this team's copies of their states are not kept up to date, so
+  // the deepest level known to hold elements (-1: none) and the number of
+  // elements in the worker levels stand in for them.
+  int deep_floor;
+  u64 deep_n;
   u64 prof_last;  // clock at the last lap mark
   u64 prof_res;   // clock at the start of the running Resolve
   u64 prof[PROF_N];
@@ -159,7 +165,9 @@ PBH_HD inline void state_init(SP st, u32 d, int q) {
   st->q = q;
   st->elems = st->live = st->progress = 0;
   for (int i = 0; i < 5; ++i) st->aux[i] = 0;
-  st->prof_on = st->prof_pad = 0;
+  st->prof_on = 0;
+  st->deep_floor = -1;
+  st->deep_n = 0;
   st->prof_last = st->prof_res = 0;
   for (int i = 0; i < PROF_N; ++i) st->prof[i] = 0;
 }
@@ -301,23 +309,210 @@ PBH_INL u32 merge_dedup_e(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u6
   return out;
 }
 
+// Bytes of the staging area of a team of NT threads walking E outputs each.
+PBH_HD inline u64 stage_bytes(int nt, int e) {
+  const u64 w = (u64)nt * (u64)e + 2u;
+  return ((2u * w * 12u + ((u64)nt + 1u) * 4u) + 7u) & ~7ull;
+}
+// Carves the staging area out of `base` (8-byte aligned).
+template <class T, class BP>
+PBH_INL void stage_setup(T& t, BP base) {
+  const u64 w = (u64)T::kNT * T::kE + 2u;
+  t.stk = (decltype(t.stk))base;
+  t.stv = (decltype(t.stv))(base + 2u * w * 8u);
+  t.stp = (decltype(t.stp))(base + 2u * w * 12u);
+}
+
+// Merge + DeleteDuplicates of arrays in HBM through the team's LDS staging
+// area, with the same result as merge_dedup_e.  The merge-path split of every
+// tile boundary is found first, a team-sized batch of boundaries at a time
+// (one binary search per thread, all in flight together), instead of one
+// search per thread per tile; then each tile's two input windows are loaded
+// into LDS with coalesced reads (plus A's element before the window and B's
+// element after it, which the duplicate checks look at), and the per-thread
+// merge-path searches and walks run on LDS.
+template <class T, class AA, class AB, class AC>
+PBH_INL u32 merge_dedup_staged(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64* cur, bool filterB,
+                               int prefer) {
+  constexpr int E = T::kE;
+  constexpr u32 TILE = (u32)T::kNT * E;
+  constexpr u32 W = TILE + 2u;
+  const u32 total = na + nb;
+  const auto ka = t.stk;  // window of A: keys ka[0..W), ids va[0..W)
+  const auto kb = ka + W;  // window of B
+  const auto va = t.stv;
+  const auto vb = va + W;
+  const auto sp = t.stp;
+  u32 out = 0;
+  for (u32 cbase = 0; cbase < total; cbase += TILE * (u32)T::kNT) {
+    u32 ntile = (total - cbase + TILE - 1) / TILE;
+    ntile = ntile < (u32)T::kNT ? ntile : (u32)T::kNT;
+    for (u32 j = (u32)t.tid(); j <= ntile; j += (u32)T::kNT) {
+      const u64 dg = (u64)cbase + (u64)j * TILE;
+      sp[j] = merge_path(A.v, na, B.v, nb, dg < total ? (u32)dg : total);
+    }
+    t.sync();
+    for (u32 k = 0; k < ntile; ++k) {
+      const u32 d0 = cbase + k * TILE, d1 = total - d0 < TILE ? total : d0 + TILE;
+      const u32 a0 = sp[k], a1 = sp[k + 1], b0 = d0 - a0, b1 = d1 - a1;
+      // the windows reach one element past the tile's inputs (the walk
+      // compares with the next element of the other array) and A's one
+      // before (a B element is checked against A's previous id)
+      const u32 abase = a0 > 0 ? a0 - 1 : 0;
+      const u32 aend = a1 < na ? a1 + 1 : a1, bend = b1 < nb ? b1 + 1 : b1;
+      {
+        // every load of both windows in flight before the first LDS store
+        constexpr int R = (int)((W + T::kNT - 1) / T::kNT);
+        const u32 la = aend - abase, lb = bend - b0;
+        u64 xk[R], yk[R];
+        u32 xv[R], yv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const u32 x = (u32)t.tid() + (u32)r * (u32)T::kNT;
+          if (x < la) {
+            xk[r] = A.k[abase + x];
+            xv[r] = A.v[abase + x];
+          }
+          if (x < lb) {
+            yk[r] = B.k[b0 + x];
+            yv[r] = B.v[b0 + x];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const u32 x = (u32)t.tid() + (u32)r * (u32)T::kNT;
+          if (x < la) {
+            ka[x] = xk[r];
+            va[x] = xv[r];
+          }
+          if (x < lb) {
+            kb[x] = yk[r];
+            vb[x] = yv[r];
+          }
+        }
+      }
+      t.sync();
+      // this thread's outputs [e0, e1) of the tile, relative to d0
+      u32 e0 = (u32)t.tid() * E;
+      e0 = e0 < d1 - d0 ? e0 : d1 - d0;
+      const u32 e1 = e0 + E < d1 - d0 ? e0 + E : d1 - d0;
+      u32 i = a0 + merge_path(va + (a0 - abase), a1 - a0, vb, b1 - b0, e0), j = d0 + e0 - i;
+      u64 ko[E];
+      u32 vo[E];
+      u32 keep = 0;
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        ko[s] = 0;
+        vo[s] = 0;
+        if (e0 + s < e1) {
+          const bool takeA = i < na && (j >= nb || va[i - abase] <= vb[j - b0]);
+          if (takeA) {
+            u64 kx = ka[i - abase];
+            const u32 vx = va[i - abase];
+            bool kp = true;
+            if (j < nb && vb[j - b0] == vx) {
+              const u64 ky = kb[j - b0];
+              if (prefer == PREFER_B) {
+                kx = ky;
+              } else if (prefer == PREFER_A) {
+              } else if (ky != kx) {
+                if (cur) {
+                  const u64 c = t.load_cur(cur + vx);
+                  if (kx == c) {
+                  } else if (ky == c) {
+                    kx = ky;
+                  } else {
+                    kp = false;
+                  }
+                } else if (ky < kx) {
+                  kx = ky;
+                }
+              }
+            }
+            ko[s] = kx;
+            vo[s] = vx;
+            keep |= (u32)kp << s;
+            ++i;
+          } else {
+            const u64 ky = kb[j - b0];
+            const u32 vy = vb[j - b0];
+            bool kp = !(i > 0 && va[i - 1 - abase] == vy);
+            if (kp && filterB && t.load_cur(cur + vy) != ky) kp = false;
+            ko[s] = ky;
+            vo[s] = vy;
+            keep |= (u32)kp << s;
+            ++j;
+          }
+        }
+      }
+      u32 tot;
+      u32 w = out + t.scan_excl((u32)__builtin_popcount(keep), &tot);
+#pragma unroll
+      for (int s = 0; s < E; ++s)
+        if ((keep >> s) & 1u) {
+          C.k[w] = ko[s];
+          C.v[w] = vo[s];
+          ++w;
+        }
+      out += tot;
+      t.sync();  // the next tile overwrites the windows
+    }
+  }
+  t.sync();
+  return out;
+}
+
+// Arrays that live in LDS are merged in place; the others (HBM) go through
+// the staging area when the team has one.
+template <class A>
+struct in_lds {
+  static constexpr bool v = false;
+};
+template <>
+struct in_lds<ArrT<u64 PBH_LDS*, u32 PBH_LDS*>> {
+  static constexpr bool v = true;
+};
+
 // Merge with the per-thread walk length chosen by size: a long walk amortises
 // the merge-path search on big arrays, a short one keeps the chain of
-// dependent reads short on the small top levels.
+// dependent reads short on the small top levels.  Arrays in HBM larger than a
+// tile are merged through the LDS staging area when there is one.
 template <class T, class AA, class AB, class AC>
 PBH_INL u32 merge_dedup(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64* cur, bool filterB,
                         int prefer = PREFER_LIVE) {
+  if constexpr (!in_lds<AA>::v && !in_lds<AB>::v) {
+    if (t.stk && na + nb > (u32)T::kNT * T::kE)
+      return merge_dedup_staged(t, A, na, B, nb, C, cur, filterB, prefer);
+  }
   if (T::kE > 2 && na + nb <= 2u * (u32)T::kNT)
     return merge_dedup_e<T, 2>(t, A, na, B, nb, C, cur, filterB, prefer);
   return merge_dedup_e<T, T::kE>(t, A, na, B, nb, C, cur, filterB, prefer);
 }
 
 // |{e in A : e <= p}|
+// Loads per thread issued together by the streaming loops over one array
+// (count, the Select passes): enough bytes in flight for HBM arrays.
+constexpr int RU = 4;
+
 template <class T, class AA>
 PBH_INL u32 count_le(const T& t, AA A, u32 n, KV p) {
   if (p.k == KINF) return n;
   u32 c = 0;
-  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) c += kv_le(KV{A.k[x], A.v[x]}, p) ? 1u : 0u;
+  for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
+    u64 k[RU];
+    u32 v[RU];
+#pragma unroll
+    for (int r = 0; r < RU; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      k[r] = x < n ? A.k[x] : KINF;
+      v[r] = x < n ? A.v[x] : VINF;
+    }
+#pragma unroll
+    for (int r = 0; r < RU; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      c += (x < n && kv_le(KV{k[r], v[r]}, p)) ? 1u : 0u;
+    }
+  }
   return t.sum(c);
 }
 
@@ -435,10 +630,19 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   if (n <= 8u * (u32)T::kNT && (r <= 2 || n - r + 1 <= 2)) return select_small(t, A, n, r);
   if (n <= 2u * (u32)T::kNT) return select_rank(t, A, n, r);
   u64 lo = KINF, hi = 0;
-  for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
-    u64 k = A.k[x];
-    lo = k < lo ? k : lo;
-    hi = k > hi ? k : hi;
+  for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
+    u64 k[RU];
+#pragma unroll
+    for (int r = 0; r < RU; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      k[r] = x < n ? A.k[x] : KINF;
+    }
+#pragma unroll
+    for (int r = 0; r < RU; ++r) {
+      const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+      lo = k[r] < lo ? k[r] : lo;
+      hi = (x < n && k[r] > hi) ? k[r] : hi;
+    }
   }
   t.minmax64(lo, hi);
   u64 span = hi - lo;
@@ -449,10 +653,20 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   for (int s = top - 8; s >= 0; s -= 8) {
     for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
     t.sync();
-    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
-      u64 dk = A.k[x] - lo;
-      bool m = (s + 8 >= 64) ? true : ((dk >> (s + 8)) == prefix);
-      if (m) t.hist_add(t.sh->hist, (u32)(dk >> s) & 255u);
+    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
+      u64 k[RU];
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+        k[r] = x < n ? A.k[x] : 0;
+      }
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+        const u64 dk = k[r] - lo;
+        const bool m = x < n && ((s + 8 >= 64) ? true : ((dk >> (s + 8)) == prefix));
+        if (m) t.hist_add(t.sh->hist, (u32)(dk >> s) & 255u);
+      }
     }
     t.sync();
     u32 D, below;
@@ -462,8 +676,17 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   }
   const u64 K = lo + prefix;
   if (cnt == 1) {
-    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT)
-      if (A.k[x] == K) t.sh->b32[3] = A.v[x];
+    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
+      u64 k[RU];
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+        k[r] = x < n ? A.k[x] : ~K;
+      }
+#pragma unroll
+      for (int r = 0; r < RU; ++r)
+        if (k[r] == K) t.sh->b32[3] = A.v[base + (u32)r * (u32)T::kNT + (u32)t.tid()];
+    }
     t.sync();
     u32 id = t.sh->b32[3];
     t.sync();
@@ -473,9 +696,18 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   for (int s = 24; s >= 0; s -= 8) {
     for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
     t.sync();
-    for (u32 x = (u32)t.tid(); x < n; x += (u32)T::kNT) {
-      u32 v = A.v[x];
-      if (A.k[x] == K && (s == 24 || (v >> (s + 8)) == idp)) t.hist_add(t.sh->hist, (v >> s) & 255u);
+    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
+      u64 k[RU];
+      u32 v[RU];
+#pragma unroll
+      for (int r = 0; r < RU; ++r) {
+        const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+        k[r] = x < n ? A.k[x] : ~K;
+        v[r] = x < n ? A.v[x] : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < RU; ++r)
+        if (k[r] == K && (s == 24 || (v[r] >> (s + 8)) == idp)) t.hist_add(t.sh->hist, (v[r] >> s) & 255u);
     }
     t.sync();
     u32 D, below, c2;
@@ -491,7 +723,8 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
 template <class T, class AA, class A0, class A1, class A2>
 PBH_INL void partition3(const T& t, AA A, u32 n, KV p1, KV p2, A0 O0, A1 O1, A2 O2, u32* n0, u32* n1,
                         u32* n2, const u64* live0 = nullptr) {
-  constexpr int E = T::kE;
+  // twice the elements per thread from HBM: more loads in flight per tile
+  constexpr int E = in_lds<AA>::v ? T::kE : 2 * T::kE;
   u32 c0t = 0, c1t = 0, c2t = 0;
   for (u32 base = 0; base < n; base += (u32)T::kNT * E) {
     u32 x0 = base + (u32)t.tid() * E;
@@ -677,6 +910,7 @@ PBH_INL void copy_arr(const T& t, AS src, AD dst, u32 n) {
 
 // Recomputes ell (deepest non-empty level) and sets p_j = +inf for j >= ell:
 // the deepest non-empty level has nothing below it to separate from.
+// A deep_floor set by the deep-level service counts as a non-empty level.
 template <class SP>
 PBH_INL void fix_ell(SP st, int q) {
   int e = -1;
@@ -685,6 +919,7 @@ PBH_INL void fix_ell(SP st, int q) {
       e = j;
       break;
     }
+  if (st->deep_floor > e) e = st->deep_floor;
   st->ell = e;
   for (int j = e < 0 ? 0 : e; j < MAXL; ++j) {
     st->L[j].pk = KINF;
@@ -864,8 +1099,18 @@ enum { DRIVE_AFTER = 1, DRIVE_ENSURE = 2 };
 //
 // `res(i)` performs Resolve(i) on `st`: the team's own Resolve in the kernels,
 // or the device-wide engine driven from the host.
-template <class T, class SP, class R>
-PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R&& res) {
+//
+// With the deep-level service (levels >= lim resolved by their own workers,
+// Section 2.2.1), this caller never resolves a level >= lim itself: when the
+// Theorem 1 schedule reaches Resolve(lim), `post(lim)` hands it to level lim's
+// worker and the schedule of this caller ends there (the worker continues
+// it); levels lack room only up to lim - 1 here (res(lim - 1) makes room in
+// level lim itself); and when B_0 must be refilled but every level below 0
+// that this caller holds is empty, `ensure()` refills it from the worker
+// levels and the drive ends.  lim >= q: no workers.
+template <class T, class SP, class R, class PO, class EN>
+PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R&& res, int lim, PO&& post,
+                        EN&& ensure) {
   int tgt = -1, chain = -1;  // pending chain: levels chain, chain-1, ..., tgt
   int stage = (what & DRIVE_AFTER) ? 0 : 2;
   int si = 0;                // schedule position
@@ -894,7 +1139,10 @@ PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R
                  (si + 1 < st->ell && bB < nomS(g.d, si + 1) + nomS(g.d, si));
           }
         }
-        if (go) {
+        if (go && si + 1 >= lim) {
+          post(si + 1);
+          stage = 2;
+        } else if (go) {
           x = si + 1;
           ++si;
         } else {
@@ -909,7 +1157,11 @@ PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R
           int j = 1;
           u64 tot = 0;
           for (int l = 0; l <= ell; ++l) tot += (u64)st->L[l].nB + st->L[l].nS;
-          while (j <= ell && st->L[j].nB + st->L[j].nS == 0) ++j;
+          while (j <= ell && j < lim && st->L[j].nB + st->L[j].nS == 0) ++j;
+          if (j >= lim && j <= ell) {
+            ensure();
+            break;
+          }
           if (cascades == 0) climit = (tot + 1) * (u64)(g.q + 1);
           if (j > ell || ++cascades > climit) {
             t.sync();
@@ -922,7 +1174,7 @@ PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R
         x = ek--;
       }
       int j = x;
-      while (j + 1 < g.q && !room_below(g, st, j)) ++j;
+      while (j + 1 < g.q && j + 1 < lim && !room_below(g, st, j)) ++j;
       tgt = x;
       lvl = j;
       chain = j > x ? j - 1 : -1;
@@ -931,10 +1183,271 @@ PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R
   }
 }
 
+template <class T, class SP, class R>
+PBH_INL void drive_with(const T& t, const Geom& g, SP st, int sched, int what, R&& res) {
+  drive_with(t, g, st, sched, what, res, MAXL, [](int) {}, [] {});
+}
+
 template <class T, class P>
 PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur, int sched, int what) {
   drive_with(t, g, st, sched, what, [&](int lvl) { resolve<T, P>(t, g, st, cur, lvl); });
 }
+
+// ---------------------------------------------------------------- deep-level service
+// Section 2.2.1 and Theorem 1: Resolve(i) only needs levels i and i+1, so
+// Resolves of levels two apart can run at the same time.  The paper gives
+// every level its own thread block (Section 4.1).  Here the team that runs the
+// rounds (the "front") keeps levels 0 .. lim-1 -- among them every level in
+// its LDS -- and each level i >= lim has a worker team of its own that runs
+// Resolve(i) on request.  Level i+1's owner is idle whenever Resolve(i) runs:
+//
+//  * the owner of level i-1 (the front for i = lim) posts a request for
+//    Resolve(i) after every fourth Resolve(i-1) (Theorem 1), and before each
+//    Resolve(i-1) waits until every posted Resolve(i) is done;
+//  * worker i, before each Resolve(i), waits until every posted Resolve(i+1)
+//    is done; if level i+1 lacks room for what Resolve(i) can push down, it
+//    posts an extra Resolve(i+1) and waits for it first.
+//
+// So Resolve(i) never overlaps Resolve(i-1) or Resolve(i+1), and the levels
+// below lim leave the front's critical path: they run while the front goes on
+// with its rounds.  A worker posts its own follow-up request (Theorem 1 again)
+// before it reports its Resolve done, so "every level idle" is observed
+// correctly by a scan from lim downwards.
+//
+// Whoever runs Resolve(i) sees real states of levels i and i+1 only.  Two
+// facts stand in for the levels further down: deeper[j] = the number of
+// elements in levels >= j (j >= lim; Resolve(i) moves elements between levels
+// i and i+1 and drops dead ones, so it changes deeper[i+1] and lowers
+// deeper[lim .. i]; a concurrent drop makes the value an upper bound), and
+// HeapState::deep_floor, which makes the deepest-level computation (fix_ell)
+// count "something below" as a non-empty level.  An upper bound is safe: a
+// pivot stays finite (the last Select result) one Resolve longer than needed,
+// which only moves elements down that could have stayed; a pivot never
+// becomes +infinity while anything lies below it.
+//
+// Refilling an empty B_0 from the worker levels, which the schedule does not
+// cover, is done by the front with every worker idle (it holds all levels and
+// runs the one-team code), as are the final statistics.
+struct DeepCtl {
+  u32 req[MAXL];          // Resolve(i) requests posted
+  u32 done[MAXL];         // Resolve(i) finished
+  u64 deeper[MAXL + 1];   // elements in levels >= i, for i >= lim
+  Lvl L[MAXL];            // states of the worker levels (level lim: also the front's, while worker lim is idle)
+  u64 elems;              // heap elements touched by the workers' Resolves
+  u64 busy[MAXL];         // clock ticks inside Resolve(i) of worker i (profiled runs)
+  int err;                // first error of any team (E_*), 0 if none
+  u32 exit;               // set by the front once every worker is idle at the end
+};
+
+enum { E_TIMEOUT = -5 };
+
+template <class SP>
+PBH_INL u64 lvl_count(SP st, int i) {
+  return (u64)st->L[i].nB + st->L[i].nS;
+}
+
+// Worker i: one requested Resolve(i).  `sy` is the synchronisation layer
+// (device spin waits and fences in the kernel, a deterministic scheduler in
+// the CPU tests): wait_idle(t, j) returns once every posted Resolve(j) is done
+// (false on an error), post(t, j) / done(t, j) count a request / completion
+// after making this team's writes visible, get/put copy level states from /
+// to the control block, deeper(t, j) reads deeper[j], account(...) applies a
+// Resolve's changes to deeper[] and the element count.
+template <class T, class P, class SY>
+PBH_INL void deep_step(const T& t, const Geom& g, typename P::SP st, const u64* cur, int i, SY& sy) {
+  const bool nx = i + 1 < g.q;
+  if (nx && !sy.wait_idle(t, i + 1)) return;
+  for (int tries = 0;; ++tries) {
+    sy.get(t, st, i);
+    if (nx) sy.get(t, st, i + 1);
+    const u64 below = i + 2 < g.q ? sy.deeper(t, i + 2) : 0ull;
+    if (t.tid() == 0) {
+      st->deep_floor = below ? i + 2 : -1;
+      fix_ell(st, g.q);
+    }
+    t.sync();
+    if (!nx || room_below(g, st, i)) break;
+    if (tries > 2 * MAXL) {
+      sy.fail(t, E_INTERNAL);
+      return;
+    }
+    sy.post(t, i + 1);  // an extra Resolve(i+1) makes room
+    if (!sy.wait_idle(t, i + 1)) return;
+  }
+  const u64 c01 = lvl_count(st, i) + (nx ? lvl_count(st, i + 1) : 0ull);
+  const u64 c1 = nx ? lvl_count(st, i + 1) : 0ull;
+  const u64 e0 = st->elems;
+  // worker levels are never in LDS: only the global placement is needed
+  if (t.tid() == 0 && st->prof_on) st->prof_res = pbh_clock();
+  resolve_t<T, P, typename P::G, typename P::G>(t, g, st, cur, i);
+  if (t.tid() == 0 && st->prof_on) st->prof[i] += pbh_clock() - st->prof_res;
+  if (st->err) {
+    sy.fail(t, st->err);
+    return;
+  }
+  const u64 n01 = lvl_count(st, i) + (nx ? lvl_count(st, i + 1) : 0ull);
+  const u64 n1 = nx ? lvl_count(st, i + 1) : 0ull;
+  sy.put(t, st, i);
+  if (nx) sy.put(t, st, i + 1);
+  sy.account(t, i, (long long)n01 - (long long)c01, (long long)n1 - (long long)c1, st->elems - e0,
+             st->prof_on ? st->prof[i] : 0ull);
+  if (nx && (st->L[i].cnt & 3u) == 0 && i + 1 <= st->ell) sy.post(t, i + 1);
+  sy.done(t, i);
+}
+
+// The front's side of the service (levels 0 .. lim-1), handed to the round
+// loop.  `sy` null: no workers, every level is the front's.
+template <class T, class P, class SY>
+struct DeepFront {
+  SY* sy;
+  int lim;
+  bool hold;  // every worker idle and every level held by the front
+
+  // Resolve(lvl) as the front runs it.  Resolve(lim - 1) shares level lim
+  // with worker lim: wait until that worker is idle, take level lim's state,
+  // make room in it if needed (an extra Resolve(lim) by the worker), and
+  // hand the level back afterwards.  (One call of resolve() per kernel: each
+  // placement variant of Resolve is instantiated once.)
+  PBH_INL void res(const T& t, const Geom& g, typename P::SP st, const u64* cur, int lvl) {
+    const bool shared = sy && !hold && lvl == lim - 1;
+    u64 c = 0;
+    if (shared) {
+      if (!take_lim(t, g, st)) return;
+      c = lvl_count(st, lim);
+    }
+    resolve<T, P>(t, g, st, cur, lvl);
+    if (shared && !st->err) give_lim(t, g, st, c);
+  }
+
+  PBH_INL bool take_lim(const T& t, const Geom& g, typename P::SP st) {
+    if (!sy->wait_idle(t, lim)) {
+      fail(t, st);
+      return false;
+    }
+    for (int tries = 0;; ++tries) {
+      sy->get(t, st, lim);
+      const u64 below = lim + 1 < g.q ? sy->deeper(t, lim + 1) : 0ull;
+      if (t.tid() == 0) {
+        st->deep_floor = below ? lim + 1 : -1;
+        fix_ell(st, g.q);
+      }
+      t.sync();
+      if (room_below(g, st, lim - 1)) return true;
+      if (tries > 2 * MAXL) {
+        sy->fail(t, E_INTERNAL);
+        fail(t, st);
+        return false;
+      }
+      sy->post(t, lim);
+      if (!sy->wait_idle(t, lim)) {
+        fail(t, st);
+        return false;
+      }
+    }
+  }
+
+  // After Resolve(lim - 1): level lim (which held c elements) goes back to
+  // its worker; the front keeps only the count of the worker levels.
+  PBH_INL void give_lim(const T& t, const Geom& g, typename P::SP st, u64 c) {
+    const u64 nc = lvl_count(st, lim);
+    sy->put(t, st, lim);
+    const u64 dn = sy->front_account(t, lim, (long long)nc - (long long)c);
+    if (t.tid() == 0) {
+      st->L[lim].nB = st->L[lim].nS = 0;
+      st->deep_n = dn;
+      st->deep_floor = dn ? lim : -1;
+      fix_ell(st, g.q);
+    }
+    t.sync();
+  }
+
+  PBH_INL void fail(const T& t, typename P::SP st) {
+    t.sync();
+    if (t.tid() == 0 && st->err == 0) st->err = sy->error(t);
+    t.sync();
+  }
+
+  // Every worker idle; the front takes every level's real state.
+  PBH_INL bool hold_all(const T& t, const Geom& g, typename P::SP st) {
+    for (int j = lim; j < g.q; ++j)
+      if (!sy->wait_idle(t, j)) return false;
+    for (int j = lim; j < g.q; ++j) sy->get(t, st, j);
+    if (t.tid() == 0) {
+      st->deep_floor = -1;
+      st->deep_n = 0;
+      fix_ell(st, g.q);
+    }
+    t.sync();
+    hold = true;
+    return true;
+  }
+
+  PBH_INL void release_all(const T& t, const Geom& g, typename P::SP st) {
+    u64 tot = 0;
+    for (int j = g.q - 1; j >= lim; --j) {
+      tot += lvl_count(st, j);
+      sy->put(t, st, j);
+      sy->set_deeper(t, j, tot);
+    }
+    sy->publish(t);
+    if (t.tid() == 0) {
+      for (int j = lim; j < g.q; ++j) st->L[j].nB = st->L[j].nS = 0;
+      st->deep_n = tot;
+      st->deep_floor = tot ? lim : -1;
+      fix_ell(st, g.q);
+    }
+    t.sync();
+    hold = false;
+  }
+
+  // Resolve(0) and the schedule after an operation (and the refill of B_0).
+  // A refill that needs the worker levels makes a second pass with every
+  // level held (all workers idle): the one-team refill of drive_with.
+  PBH_INL void drive(const T& t, const Geom& g, typename P::SP st, const u64* cur, int sched, int what) {
+    if constexpr (!SY::kOn) {
+      drive_with(t, g, st, sched, what, [&](int lvl) { resolve<T, P>(t, g, st, cur, lvl); });
+    } else {
+      int w = what;
+      for (int pass = 0; pass < 2; ++pass) {
+        bool refill = false;
+        drive_with(
+            t, g, st, sched, w, [&](int lvl) { res(t, g, st, cur, lvl); }, (sy && !hold) ? lim : MAXL,
+            [&](int lvl) { sy->post(t, lvl); }, [&] { refill = true; });
+        if (!refill || st->err) break;
+        if (!hold_all(t, g, st)) {
+          fail(t, st);
+          break;
+        }
+        w = DRIVE_ENSURE;
+      }
+      if (hold) {
+        if (!st->err) release_all(t, g, st);
+        hold = false;
+      }
+    }
+  }
+
+  // End of the run: every worker idle, their levels' Resolve counts and
+  // element traffic merged into st, then the workers leave.
+  PBH_INL void finish(const T& t, const Geom& g, typename P::SP st) {
+    if constexpr (SY::kOn) {
+      if (!sy) return;
+      if (!st->err) {
+        if (hold_all(t, g, st)) {
+          sy->merge_stats(t, st, lim, g.q);
+        } else {
+          fail(t, st);
+        }
+      }
+      sy->leave(t);
+    }
+  }
+};
+
+// No workers (every level is the front's).
+struct NoDeepSync {
+  static constexpr bool kOn = false;
+};
 
 // ---------------------------------------------------------------- parDijkstra
 
@@ -1142,7 +1655,7 @@ PBH_INL void round_features(const T& t, const Geom& g, SP st, A0 B, u32 nB, cons
     hi = k > hi ? k : hi;
   }
   t.minmax64(lo, hi);
-  u64 tot = 0;
+  u64 tot = st->deep_n;
   for (int i = 0; i < g.q; ++i) tot += (u64)st->L[i].nB + st->L[i].nS;
   const float spread = (float)(hi - lo);
   f[0] = flog2p1((float)tot);
@@ -1544,11 +2057,14 @@ struct NoHook {
 
 // `hook` sees the heap after every operation's Resolve schedule (the CPU
 // tests use it to check invariants; the kernels pass NoHook).
-template <class T, class P, class Hook = NoHook>
+// With `sy` (and lim < q), levels >= lim are resolved by their own workers
+// (the deep-level service above).
+template <class T, class P, class Hook = NoHook, class SY = NoDeepSync>
 PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
                          const u32* wt, u64* dist, u32 n, u32 src, int sched, const SpecCfg& sc, SsspCounters* cnt,
-                         const Hook& hook = Hook()) {
+                         const Hook& hook = Hook(), SY* sy = nullptr, int lim = MAXL) {
   using G = typename P::G;
+  DeepFront<T, P, SY> fr{sy, lim, false};
   const int idbits = bits_for(n);
   if (t.tid() == 0) {
     Arr S = lbuf(g, 0, 3);
@@ -1574,7 +2090,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     // Resolve(0) and the schedule after the previous operation (the source's
     // insertion, a round's bulk update or a piece of it), then make sure B_0
     // holds the minimum if the heap is not empty.
-    drive<T, P>(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
+    fr.drive(t, g, st, dist, sched, DRIVE_AFTER | DRIVE_ENSURE);
     prof_lap(t, st, PROF_DRIVE);
     if (st->err) break;
     hook(g, st, c);
@@ -1658,6 +2174,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     }
     ++c.rounds;
   }
+  fr.finish(t, g, st);
   *cnt = c;
 }
 

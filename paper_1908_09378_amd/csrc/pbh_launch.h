@@ -27,6 +27,13 @@ struct SsspParams {
   SsspDevStats* stats;
   SpecCfg spec;
   u32 prof;  // time accounting on (single queries only)
+  // deep-level workers: levels >= deep_lim each have a workgroup of their own
+  // (blocks 1 .. q - deep_lim of a cooperative launch); null = none
+  DeepCtl* deep;
+  int deep_lim;
+  // bytes of LDS staging for merges of HBM levels, after the LDS levels in
+  // the dynamic block (the round loop) or at its start (workers); 0 = none
+  u32 stage;
 };
 
 

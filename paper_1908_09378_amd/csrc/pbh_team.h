@@ -113,6 +113,11 @@ struct DevTeam {
   static constexpr int kNW = NT / 64;
   static constexpr int kE = NT == 64 ? 8 : 4;  // elements per thread per tile
   TeamShared<kNW> PBH_LDS* sh;
+  // LDS staging area for merges of arrays in HBM (null: none): two windows of
+  // kNT * kE + 2 elements (keys, then ids) and kNT + 1 split points
+  u64 PBH_LDS* stk = nullptr;
+  u32 PBH_LDS* stv = nullptr;
+  u32 PBH_LDS* stp = nullptr;
 
   __device__ __forceinline__ int tid() const { return (int)threadIdx.x; }
   __device__ __forceinline__ int lane() const { return (int)(threadIdx.x & 63); }
@@ -242,6 +247,9 @@ struct HostTeam {
   static constexpr int kNW = 1;
   static constexpr int kE = 4;
   TeamShared<1>* sh;
+  u64* stk = nullptr;  // staging area (as DevTeam's)
+  u32* stv = nullptr;
+  u32* stp = nullptr;
   int tid() const { return 0; }
   int lane() const { return 0; }
   int wave() const { return 0; }

@@ -56,7 +56,8 @@ def lib():
         L.hm_sssp.restype = C.c_int
         L.hm_sssp.argtypes = [u64p, u32p, u32p, C.c_uint32, C.c_uint64, C.c_uint32, u64p, C.c_uint32,
                               C.c_int, C.c_uint64, C.c_int, u64p, C.c_int, C.c_uint32, C.c_uint32, u32p,
-                              C.c_uint32, C.POINTER(C.c_float), C.c_int, C.c_uint64, C.c_uint32]
+                              C.c_uint32, C.POINTER(C.c_float), C.c_int, C.c_uint64, C.c_uint32, C.c_int,
+                              C.c_int, C.c_uint64]
         _lib[sanitize] = L
     return _lib[sanitize]
 
@@ -133,7 +134,10 @@ class HostHeap:
 
 
 def sssp(g, src, d=0, sched=0, hcap=0, qlds=0, rule=0, kfix=0, kmax=0, kseq=None, model=None, check_live=False,
-         stop_key=0, max_rounds=0):
+         stop_key=0, max_rounds=0, deep_lim=0, deep_mode=1, deep_seed=0):
+    """The kernel's round loop on the CPU.  deep_lim > 0: levels >= max(deep_lim,
+    2, qlds) are resolved by simulated deep-level workers (deep_mode 0 eager,
+    1 lazy, 2 seeded random)."""
     off = np.ascontiguousarray(g.offsets, np.uint64)
     tg = np.ascontiguousarray(g.targets, np.uint32)
     wt = np.ascontiguousarray(g.weights, np.uint32)
@@ -144,8 +148,10 @@ def sssp(g, src, d=0, sched=0, hcap=0, qlds=0, rule=0, kfix=0, kmax=0, kseq=None
     rc = lib().hm_sssp(_p(off, C.c_uint64), _p(tg, C.c_uint32), _p(wt, C.c_uint32), g.n, g.m, src,
                        _p(dist, C.c_uint64), d, sched, hcap, qlds, _p(st, C.c_uint64), rule, kfix, kmax,
                        None if ks is None else _p(ks, C.c_uint32), 0 if ks is None else ks.shape[0],
-                       None if mdl is None else _p(mdl, C.c_float), int(check_live), stop_key, max_rounds)
+                       None if mdl is None else _p(mdl, C.c_float), int(check_live), stop_key, max_rounds,
+                       deep_lim, deep_mode, deep_seed)
     return rc, dist, dict(rounds=int(st[0]), relax=int(st[1]), updates=int(st[2]), elems=int(st[3]),
                           levels=int(st[4]), resolves=st[5:21].tolist(), extracted=int(st[21]),
                           first_bad=int(st[22].astype(np.int64)), violation=st[23:26].tolist(),
-                          last_key=int(st[26]), stopped=bool(st[27]))
+                          last_key=int(st[26]), stopped=bool(st[27]), worker_runs=int(st[28]),
+                          deep_lim=int(st[29]))

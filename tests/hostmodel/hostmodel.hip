@@ -5,7 +5,9 @@
 // operation scripts through the exact schedule, capacity and growth logic.
 // It is not part of the library and the library never calls it; results from
 // here are checked against the oracle like any other implementation.
+#include <algorithm>
 #include <cmath>
+#include <new>
 #include <cstring>
 #include <vector>
 
@@ -244,18 +246,118 @@ int hm_level_items(void* hp, int i, u64* bk, u32* bv, u64* sk, u32* sv) {
   return 0;
 }
 
-// Invariant check run after every operation of the round loop: the smallest
-// live element of the heap (key == dist[id]) sits in B_0, and with the plain
-// rule every reached vertex is either extracted or live in the heap exactly
-// once.  Records the round of the first violation.
+// The deep-level service of the SSSP kernel with the workers simulated on one
+// thread: a worker's Resolve runs when a team waits for its level (mode 1,
+// lazy: the workers are as slow as they may be), as soon as it is posted
+// (mode 0, eager), or, from the round loop's own synchronisation points, at
+// seeded random times (mode 2).  Every order it produces is one the device's
+// workgroups can produce, at the granularity of whole Resolves: a Resolve(j)
+// only starts when nobody holds level j or j+1.
+struct SimDeep {
+  static constexpr bool kOn = true;
+  DeepCtl c;
+  int lim, mode;
+  u64 rng;
+  int depth = 0;  // worker steps on the stack
+  Geom g;
+  const u64* cur;
+  HeapState wst[MAXL];
+  TeamShared<1> wts[MAXL];
+  u64 runs = 0;
+
+  bool coin() {
+    rng = rng * 6364136223846793005ull + 1442695040888963407ull;
+    return (rng >> 33) & 1u;
+  }
+  u64 wstage[MAXL][32];
+  void run(int j) {
+    HostTeam wt{&wts[j]};
+    static_assert(sizeof(wstage[0]) >= 2 * 6 * 12 + 8, "worker staging (one thread, 4 outputs)");
+    stage_setup(wt, reinterpret_cast<unsigned char*>(wstage[j]));
+    ++depth;
+    ++runs;
+    deep_step<HostTeam, HostPolicy>(wt, g, &wst[j], cur, j, *this);
+    --depth;
+  }
+  // Random mode, from the round loop only (no worker step on the stack):
+  // run pending Resolves of random levels.
+  void maybe_run() {
+    if (mode != 2 || depth) return;
+    for (int j = g.q - 1; j >= lim; --j)
+      while (!c.err && c.done[j] != c.req[j] && coin()) run(j);
+  }
+  bool wait_idle(const HostTeam&, int j) {
+    while (!c.err && c.done[j] != c.req[j]) run(j);
+    return c.err == 0;
+  }
+  void post(const HostTeam&, int j) {
+    c.req[j]++;
+    if (mode == 0 || (mode == 2 && depth == 0 && coin()))
+      while (!c.err && c.done[j] != c.req[j]) run(j);
+  }
+  void done(const HostTeam&, int j) { c.done[j]++; }
+  void publish(const HostTeam&) {}
+  void get(const HostTeam&, HeapState* st, int j) { st->L[j] = c.L[j]; }
+  void put(const HostTeam&, HeapState* st, int j) { c.L[j] = st->L[j]; }
+  u64 deeper(const HostTeam&, int j) { return c.deeper[j]; }
+  void set_deeper(const HostTeam&, int j, u64 v) { c.deeper[j] = v; }
+  void account(const HostTeam&, int i, long long drop, long long d1, u64 elems, u64) {
+    for (int j = lim; j <= i; ++j) c.deeper[j] += (u64)drop;
+    c.deeper[i + 1] += (u64)d1;
+    c.elems += elems;
+  }
+  u64 front_account(const HostTeam&, int j, long long d) { return c.deeper[j] += (u64)d; }
+  void fail(const HostTeam&, int code) {
+    if (!c.err) c.err = code;
+  }
+  int error(const HostTeam&) { return c.err; }
+  void merge_stats(const HostTeam&, HeapState* st, int, int) { st->elems += c.elems; }
+  void leave(const HostTeam&) { c.exit = 1; }
+};
+
+// Invariant checks run after every operation of the round loop: the smallest
+// live element of the heap (key == dist[id]) sits in B_0; with the plain rule
+// every reached vertex is either extracted or live in the heap exactly once;
+// and the level order of Section 2.2: every element of B_i is <= p_i, and
+// every element of every deeper level is > p_i.  With simulated deep-level
+// workers the state checked is the round loop's levels plus the workers'
+// published ones (every worker is between Resolves here).  Records the round
+// of the first violation.
 struct LiveCheck {
   const u64* dist;
   u32 n;
   bool plain;
   int* first_bad;  // -1 if none
-  u64* info;       // what was violated: (1, key, id) misplaced minimum, (2, live, reached)
-  void operator()(const Geom& g, HeapState* st, const SsspCounters& c) const {
+  u64* info;       // what was violated: (1, key, id) misplaced minimum, (2, live, reached), (3, level, 0)
+  SimDeep* deep;   // null: no workers
+  void operator()(const Geom& g, HeapState* st0, const SsspCounters& c) const {
     if (*first_bad >= 0) return;
+    HeapState merged;
+    HeapState* st = st0;
+    if (deep) {
+      deep->maybe_run();
+      merged = *st0;
+      for (int j = deep->lim; j < g.q; ++j) merged.L[j] = deep->c.L[j];
+      st = &merged;
+    }
+    for (int i = 0; i + 1 < g.q; ++i) {
+      const KV p{st->L[i].pk, st->L[i].pv};
+      if (p.k == KINF) continue;
+      bool ok = true;
+      Arr B = lbuf(g, i, st->L[i].bsel);
+      for (u32 x = 0; x < st->L[i].nB; ++x) ok = ok && kv_le(KV{B.k[x], B.v[x]}, p);
+      for (int j = i + 1; j < g.q; ++j)
+        for (int w = 0; w < 2; ++w) {
+          Arr A = lbuf(g, j, w ? 3 + st->L[j].ssel : st->L[j].bsel);
+          const u32 na = w ? st->L[j].nS : st->L[j].nB;
+          for (u32 x = 0; x < na; ++x) ok = ok && kv_less(p, KV{A.k[x], A.v[x]});
+        }
+      if (!ok) {
+        *first_bad = (int)c.rounds;
+        info[0] = 3, info[1] = (u64)i, info[2] = 0;
+        return;
+      }
+    }
     std::vector<char> seen(n, 0);
     u64 live = 0, mk = KINF, mk0 = KINF;
     u32 mv = VINF, mv0 = VINF;
@@ -291,9 +393,12 @@ struct LiveCheck {
 // parDijkstra with the kernel's round loop.  qlds levels are placed in a
 // separate buffer, standing in for LDS.  stats: rounds, relaxations, updates,
 // heap element touches, levels, resolves[0..15].
+// deep_lim > 0: levels >= max(deep_lim, 2, qlds) are resolved by simulated
+// deep-level workers (SimDeep, deep_mode, deep_seed).
 int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src, u64* dist, u32 d_opt,
             int sched, u64 hcap, int qlds, u64* stats, int rule, u32 kfix, u32 kmax, const u32* kseq, u32 kseq_len,
-            const float* model, int check_live, u64 stop_key, u32 max_rounds) {
+            const float* model, int check_live, u64 stop_key, u32 max_rounds, int deep_lim, int deep_mode,
+            u64 deep_seed) {
   u64 md = 0;
   for (u32 u = 0; u < n; ++u) md = off[u + 1] - off[u] > md ? off[u + 1] - off[u] : md;
   u32 d = d_opt ? d_opt : (u32)(md ? md : 1);
@@ -314,6 +419,10 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   state_init(&st, d, q);
   TeamShared<1> ts;
   HostTeam t{&ts};
+  // the kernel's LDS staging for merges of HBM levels (here: every merge of
+  // more than one tile goes through it)
+  std::vector<u64> stage_buf(stage_bytes(1, HostTeam::kE) / 8 + 1);
+  stage_setup(t, reinterpret_cast<unsigned char*>(stage_buf.data()));
   for (u32 v = 0; v < n; ++v) dist[v] = KINF;
   dist[src] = 0;
   SpecCfg sc;
@@ -338,12 +447,41 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   SsspCounters c;
   int first_bad = -1;
   u64 info[3] = {0, 0, 0};
+  int lim = deep_lim > 0 ? std::max(std::max(deep_lim, 2), qlds) : MAXL;
+  SimDeep* sim = nullptr;
+  std::vector<char> simbuf;
+  if (lim < q) {
+    simbuf.assign(sizeof(SimDeep), 0);
+    sim = new (simbuf.data()) SimDeep();
+    std::memset(&sim->c, 0, sizeof sim->c);
+    sim->lim = lim;
+    sim->mode = deep_mode;
+    sim->rng = deep_seed * 2654435761ull + 1;
+    sim->g = g;
+    sim->cur = dist;
+    for (int j = 0; j < MAXL; ++j) {
+      state_init(&sim->wst[j], d, q);
+      sim->c.L[j] = Lvl{0, 0, 0, 0, KINF, VINF, 0};
+    }
+  } else {
+    lim = MAXL;
+  }
   if (check_live) {
-    LiveCheck hk{dist, n, rule == 0, &first_bad, info};
-    sssp_rounds<HostTeam, HostPolicy, LiveCheck>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk);
+    LiveCheck hk{dist, n, rule == 0, &first_bad, info, sim};
+    if (sim)
+      sssp_rounds<HostTeam, HostPolicy, LiveCheck, SimDeep>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk,
+                                                            sim, lim);
+    else
+      sssp_rounds<HostTeam, HostPolicy, LiveCheck>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk);
+  } else if (sim) {
+    sssp_rounds<HostTeam, HostPolicy, NoHook, SimDeep>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, NoHook(),
+                                                       sim, lim);
   } else {
     sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
   }
+  stats[28] = sim ? sim->runs : 0;
+  stats[29] = sim ? (u64)sim->lim : 0;
+  if (sim) sim->~SimDeep();
   stats[26] = c.last_key;
   stats[27] = c.stopped;
   stats[22] = (u64)(i64)first_bad;

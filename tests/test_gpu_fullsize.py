@@ -65,7 +65,10 @@ def _run_dev(gd, g, **kw):
     return host64(dist), st
 
 
-@pytest.mark.parametrize("kw", [dict(d=1024, team=256, k_max=256), dict(d=8)], ids=["tuned", "d8"])
+GRID8_TUNED = dict(d=1024, team=256, k_max=256)
+
+
+@pytest.mark.parametrize("kw", [GRID8_TUNED, dict(d=8)], ids=["tuned", "d8"])
 def test_grid8_2048_learned(grid8_full, kw):
     from paper_1908_09378_amd import learn
     g, ref, gd = grid8_full
@@ -75,6 +78,19 @@ def test_grid8_2048_learned(grid8_full, kw):
     print(f"[full]   {st['kernel_ms']:.0f} ms, {st['rounds']} rounds, {st['extracted']} extracted", flush=True)
     assert np.array_equal(got, ref), f"{int((got != ref).sum())} distances differ"
     assert st["extracted"] >= g.n
+
+
+def test_grid8_2048_learned_deep_workers(grid8_full):
+    """The learned threshold at the tuned settings with deep-level workers
+    (levels >= 2 resolved by workgroups of their own)."""
+    from paper_1908_09378_amd import learn
+    g, ref, gd = grid8_full
+    blob = torch.from_numpy(learn.load_model()).to(DEV)
+    print("[full] grid8 2048^2 learned, deep-level workers", flush=True)
+    got, st = _run_dev(gd, g, k_rule=2, k_model=blob, deep_level=2, **GRID8_TUNED)
+    print(f"[full]   {st['kernel_ms']:.0f} ms, {st['rounds']} rounds, resolves {st['resolves'][:st['levels']]}",
+          flush=True)
+    assert np.array_equal(got, ref), f"{int((got != ref).sum())} distances differ"
 
 
 def test_grid8_2048_plain_tuned_settings(grid8_full):

@@ -381,3 +381,76 @@ def test_algorithm1_postconditions_with_duplicates_and_deletes(seed):
                 above += r["nB"] > 2 * d * 4 ** r["lvl"]
         check_structure(h, o.cur(), d)
     print(f"Resolves entered with B_i above its nominal size: {above}")
+
+
+# ------------------------------------------------------------ deep-level service
+# Levels >= max(deep_lim, 2, qlds) resolved by their own workers (Section
+# 2.2.1, Theorem 1), with the workers simulated on the CPU: lazy (a worker
+# runs only when a team waits for it), eager (as soon as it is asked) and
+# seeded random interleavings of whole Resolves.
+
+
+def _deep_graphs():
+    yield W.grid8(40, 40, wmax=10000, seed=4)
+    yield W.random_graph(3000, 30000, 0, 9, seed=4)
+    yield W.rgg(1500, seed=6)
+    yield W.paper_dag(200, 6000, seed=7)
+    yield W.shuffle_rows(W.grid8(30, 30, wmax=10000, seed=9), 1)
+    yield W.grid8(96, 96, wmax=10000, seed=9)   # dead copies: refills of B_0 from the worker levels
+
+
+@pytest.mark.parametrize("gi", range(6))
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("rule", ["plain", "plain_d4x", "fixed8", "random_k"])
+def test_deep_workers_exact_and_ordered(gi, mode, rule):
+    """With deep-level workers the distances equal the oracle's for every
+    interleaving, after every operation the level order of Section 2.2 holds
+    over the round loop's and the workers' levels together (B_i <= p_i < every
+    deeper element) and the smallest live element is in B_0; the plain rule
+    keeps one round per settled vertex and one relaxation per out-edge."""
+    g = list(_deep_graphs())[gi]
+    src = (gi * 11) % g.n
+    ref, order, nrelax = oracle.dijkstra(g, src, want_order=True)
+    kw = dict(check_live=True, deep_lim=2, deep_mode=mode, deep_seed=gi * 3 + mode)
+    if rule == "plain_d4x":
+        kw["d"] = 4 * max(1, g.max_degree())
+    elif rule == "fixed8":
+        kw.update(rule=1, kfix=8)
+    elif rule == "random_k":
+        kw.update(rule=3, kseq=np.random.default_rng(gi).integers(1, 64, size=61), kmax=256)
+    rc, dist, st = hm_sssp(g, src, **kw)
+    assert rc == 0
+    assert st["first_bad"] == -1, st["violation"]
+    assert np.array_equal(dist, ref)
+    if rule.startswith("plain"):
+        assert st["rounds"] == order.shape[0] and st["relax"] == nrelax
+    else:
+        assert st["extracted"] >= order.shape[0]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_deep_workers_take_the_deep_levels(mode):
+    """The workers run the Resolves of their levels (all but the few the
+    round loop runs itself while refilling an empty B_0 with every worker
+    idle), and Theorem 1's pacing holds between the levels (Resolve(i+1) is
+    asked for after every fourth Resolve(i), so cnt(i+1) <= cnt(i) / 4 +
+    extra room-making ones, which stay rare here)."""
+    g = W.grid8(64, 64, wmax=10000, seed=4)
+    ref = oracle.dijkstra(g, 0)
+    rc, dist, st = hm_sssp(g, 0, d=8, deep_lim=2, deep_mode=mode, deep_seed=5, check_live=True)
+    assert rc == 0 and np.array_equal(dist, ref) and st["first_bad"] == -1
+    res = st["resolves"][:st["levels"]]
+    assert st["deep_lim"] == 2 and 0.9 * sum(res[2:]) <= st["worker_runs"] <= sum(res[2:])
+    for i in range(1, len(res) - 1):
+        assert res[i + 1] <= res[i] // 4 + 2, res
+
+
+def test_deep_workers_off_past_the_deepest_level_and_lds_levels():
+    """deep_lim at or past the deepest level means no workers; the first
+    worker level is never above the LDS levels."""
+    g = W.grid4(20, 20, 1, 100, seed=3)
+    rc, dist, st = hm_sssp(g, 0, deep_lim=15)
+    assert rc == 0 and st["deep_lim"] == 0 and st["worker_runs"] == 0
+    rc, dist, st = hm_sssp(g, 0, d=4, qlds=3, deep_lim=2)
+    assert rc == 0 and np.array_equal(dist, oracle.dijkstra(g, 0))
+    assert st["deep_lim"] in (0, 3)
