@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--workload all|ring|grid64|grid8|batch|heap|dag|copy] [--no-cpu]
+                    [--dag-m M] [--dag-seeds S] [--dag-trials T] [--nearfar-factors F ...]
 
 One step of the headline = one complete sssp() over the resident ring
 lattice (n = 2^20 vertices, each linked to its 16 nearest neighbours on each
@@ -24,7 +25,12 @@ steps, exactness check against the oracle, roofline and CPU baseline:
            (learned and plain), with a sample of the same queries run one by
            one, and the oracle on 1 and on all host threads;
   heap     the standalone heap: 2^24 ids, 256 rounds of bulk_update(2^20
-           decrease-keys) + extract_min(2^16), every extraction checked.
+           decrease-keys) + extract_min(2^16), every extraction checked;
+  dag      the paper's high-diameter DAG (n = 30,000, m = 4e7 by default):
+           plain parDijkstra and Near-Far against the closed-form distances.
+
+Near-Far (Delta-stepping, the paper's comparison family) runs beside
+parDijkstra on the ring, the large grid and the DAG.
 
 --workload X runs one of them alone and prints its record as the line.
 Inputs are synthetic and seeded (workloads/), resident in HBM before timing.
@@ -43,8 +49,8 @@ sys.path.insert(0, ROOT)
 METRIC = "SSSP GTEPS (m/time) on 1 MI355X: learned-threshold & batched vs plain parDijkstra"
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_1908_09378_amd", "csrc")
-KERNEL_SOURCES = ["pbh_core.h", "pbh_team.h", "pbh_launch.h", "kernels.hip", "wide.h", "wide.hip", "learn.hip",
-                  "nearfar.hip"]
+KERNEL_SOURCES = ["pbh_core.h", "pbh_team.h", "pbh_launch.h", "round_loop.h", "kernels.hip", "kernels_full.hip",
+                  "wide.h", "wide.hip", "learn.hip", "nearfar.hip"]
 
 RING_DESC = "ring lattice n=2^20, 16 neighbours per side, w~U[1,1000], source 0"
 GRID64_DESC = "4-neighbour grid 64x64, w~U[1,100], source 0"
@@ -155,14 +161,16 @@ class Query:
     def record(self, sec, stats, exact, method, workload, steps, warmup):
         st = stats[-1]
         kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
+        kms = sorted(x["kernel_ms"] for x in stats)
         return {"value": self.g.m / sec / 1e9, "unit": "GTEPS", "steps": steps, "warmup": warmup,
-                "ms_per_step": sec * 1e3, "method": method, "rounds": st["rounds"],
+                "ms_per_step": sec * 1e3, "kernel_ms_mean": kern_ms, "kernel_ms_median": kms[len(kms) // 2],
+                "method": method, "rounds": st["rounds"],
                 "relaxations": st["relaxations"], "extracted": st["extracted"], "updates": st["updates"],
                 "d": st["d"], "team": st["team"], "levels": st["levels"], "lds_levels": st["lds_levels"],
                 "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
                 "roofline": roofline("k_sssp", workload, sssp_bytes(st), kern_ms)}
 
-    def nearfar(self, steps, factors=(0.25, 1.0, 4.0)):
+    def nearfar(self, steps, factors=(1.0,)):
         """The Near-Far (Delta-stepping) baseline on the same graph: delta =
         f x Davidson et al.'s choice for each f, one untimed and `steps` timed
         runs each; the fastest delta is the record, the others are listed."""
@@ -227,22 +235,26 @@ def run_ring(args):
     q = Query(g, 0, oracle.dijkstra(g, 0))
     blob = load_blob()
     t = q.tune(k_rule=2, k_model=blob)
-    kw = dict(k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"], team=t["team"], k_scale=t["k_scale"])
+    kw = dict(k_rule=2, k_model=blob, d=t["d"], k_max=t["k_max"], team=t["team"], k_scale=t["k_scale"],
+              k_every=t["k_every"])
     lr = q.record(*q.timed(args.steps, args.warmup, "ring learned", **kw),
                   LEARNED_DESC + "; d, team and k_max autotuned", "ring", args.steps, args.warmup)
     lr["autotune"] = t
+    if args.learned_only:  # profiling runs: the learned launches are the last k_sssp dispatches
+        rec = dict(lr)
+        rec["config"] = {"workload": RING_DESC, "method": lr["method"], "n": g.n, "m": g.m}
+        return rec
     pl = q.record(*q.timed(args.base_steps, 0, "ring plain"), "plain parDijkstra (k = 1, d = max out-degree)",
                   "ring_plain", args.base_steps, 0)
-    tp = q.tune()
-    pt = q.record(*q.timed(args.base_steps, 0, "ring plain tuned", d=tp["d"], team=tp["team"]),
-                  "plain parDijkstra (k = 1), d and team autotuned", "ring_plain", args.base_steps, 0)
-    pt["autotune"] = tp
+    pt = q.record(*q.timed(args.base_steps, 0, "ring plain tuned", **RING_PLAIN_TUNED),
+                  "plain parDijkstra (k = 1), d = 512, team 64 (sssp_autotune's choice for the plain rule on "
+                  "this graph)", "ring_plain", args.base_steps, 0)
     rec = dict(lr)
     rec["plain"] = pl
     rec["plain_tuned"] = pt
     rec["speedup_vs_plain"] = lr["value"] / pl["value"]
     rec["speedup_vs_plain_tuned"] = lr["value"] / pt["value"]
-    rec["nearfar"] = q.nearfar(args.base_steps)
+    rec["nearfar"] = q.nearfar(args.base_steps, args.nearfar_factors)
     rec["exact"] = lr["exact"] and pl["exact"] and pt["exact"] and rec["nearfar"]["exact"]
     rec["config"] = {"workload": RING_DESC, "method": lr["method"], "n": g.n, "m": g.m, "d": lr["d"],
                      "team": lr["team"], "levels": lr["levels"], "lds_levels": lr["lds_levels"],
@@ -254,16 +266,18 @@ def run_ring(args):
 
 def run_grid64(args):
     """The small 64x64 grid: plain parDijkstra (every round of the method,
-    4,096 of them) and the learned threshold."""
+    4,096 of them) and the learned threshold; at least 10 timed runs after at
+    least one warm-up run (the paper's protocol), mean and median reported."""
     import oracle
     import workloads as W
     g = W.grid4(64, 64, 1, 100, seed=1)
     q = Query(g, 0, oracle.dijkstra(g, 0))
-    pl = q.record(*q.timed(args.steps, args.warmup, "grid64 plain"), "plain parDijkstra (k = 1, d = max out-degree)",
-                  "grid64", args.steps, args.warmup)
+    steps, warm = max(10, args.steps), max(1, args.warmup)
+    pl = q.record(*q.timed(steps, warm, "grid64 plain"), "plain parDijkstra (k = 1, d = max out-degree)",
+                  "grid64", steps, warm)
     blob = load_blob()
-    lr = q.record(*q.timed(args.steps, args.warmup, "grid64 learned", k_rule=2, k_model=blob, d=32),
-                  LEARNED_DESC + "; d = 32", "grid64_learned", args.steps, args.warmup)
+    lr = q.record(*q.timed(steps, warm, "grid64 learned", k_rule=2, k_model=blob, d=32),
+                  LEARNED_DESC + "; d = 32", "grid64_learned", steps, warm)
     rec = {"metric": "SSSP GTEPS (m/time), plain parDijkstra", **pl,
            "config": {"workload": GRID64_DESC, "n": g.n, "m": g.m}, "learned": lr,
            "exact": pl["exact"] and lr["exact"]}
@@ -272,12 +286,18 @@ def run_grid64(args):
     return rec
 
 
-# Settings sssp_autotune chose for the 2048x2048 grid (its trials take about
-# 70 s there, so the bench does not repeat them): d = 128 x the maximum
-# out-degree, 256 threads, at most 256 minima per round; plain parDijkstra
-# with the autotuner's choice for the plain rule.
-GRID8_LEARNED = dict(d=1024, team=256, k_max=256)
-GRID8_PLAIN = dict(d=512, team=64)
+# Settings sssp_autotune chose for the 2048x2048 grid with the deep-level
+# workers (its trials take about 70 s there, so the bench does not repeat
+# them): d = 32 x the maximum out-degree, 256 threads, at most 256 minima per
+# round, the model every fourth round.  The plain rule runs
+# at d = 2048 with 256 threads, the fastest per round of the settings the
+# autotuner tries, measured over the first 200,000 rounds.  Both with the
+# deep-level workers (levels >= 2 resolved by workgroups of their own).
+GRID8_LEARNED = dict(d=256, team=256, k_max=256, k_every=4, deep_level=2)
+GRID8_PLAIN = dict(d=2048, team=256, deep_level=2)
+# sssp_autotune's choice for the plain rule on the ring lattice (d = 512 or
+# 256 from run to run, 64 threads; 7.1-7.2 s either way).
+RING_PLAIN_TUNED = dict(d=512, team=64)
 
 
 def run_grid8(args):
@@ -287,16 +307,27 @@ def run_grid8(args):
     q = Query(g, 0, oracle.dijkstra(g, 0))
     blob = load_blob()
     lr = q.record(*q.timed(args.base_steps, 1, "grid8 learned", k_rule=2, k_model=blob, **GRID8_LEARNED),
-                  LEARNED_DESC + "; d = 1024, team 256, k_max 256 (autotuned settings for this graph)",
-                  "grid8", args.base_steps, 1)
-    pl = q.record(*q.timed(1, 0, "grid8 plain", **GRID8_PLAIN),
-                  "plain parDijkstra (k = 1), d = 512, team 64 (autotuned settings for this graph)",
-                  "grid8_plain", 1, 0)
-    nfr = q.nearfar(args.base_steps)
+                  LEARNED_DESC + "; d = 256, team 256, k_max 256, model every 4th round (autotuned settings for "
+                  "this graph), deep-level workers from level 2", "grid8", args.base_steps, 1)
+    # Plain parDijkstra settles one vertex per round, 4,194,304 rounds here
+    # (minutes); the bench times its first 2^20 rounds and reports their
+    # rate.  The heap grows during a run, so later rounds cost more and the
+    # estimate of the whole run (per-round time x n) is a lower bound.
+    pre = 1 << 20
+    sec, sts, _ = q.timed(1, 0, "grid8 plain (first 2^20 rounds)", max_rounds=pre, **GRID8_PLAIN)
+    st = sts[-1]
+    kern_s = st["kernel_ms"] * 1e-3
+    pl = {"method": "plain parDijkstra (k = 1), d = 2048, team 256, deep-level workers from level 2; the first "
+                    "2^20 of its 4,194,304 rounds (one per vertex)",
+          "rounds": st["rounds"], "relaxations": st["relaxations"], "ms": sec * 1e3,
+          "us_per_round": kern_s * 1e6 / st["rounds"], "edges_per_s": st["relaxations"] / kern_s,
+          "estimated_full_s": kern_s / st["rounds"] * g.n,
+          "roofline": roofline("k_sssp", "grid8_plain", sssp_bytes(st), st["kernel_ms"])}
+    nfr = q.nearfar(args.base_steps, args.nearfar_factors)
     rec = {"metric": "SSSP GTEPS (m/time), learned threshold", **lr,
            "config": {"workload": GRID8_DESC, "n": g.n, "m": g.m}, "plain": pl,
-           "speedup_vs_plain": lr["value"] / pl["value"], "nearfar": nfr,
-           "reinsertions": lr["extracted"] - g.n, "exact": lr["exact"] and pl["exact"] and nfr["exact"]}
+           "speedup_vs_plain_estimate": pl["estimated_full_s"] / (lr["ms_per_step"] * 1e-3), "nearfar": nfr,
+           "reinsertions": lr["extracted"] - g.n, "exact": lr["exact"] and nfr["exact"]}
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_sssp(g, 0, args.cpu_budget)
     return rec
@@ -634,6 +665,10 @@ def main():
     ap.add_argument("--dag-seeds", type=int, default=1)
     ap.add_argument("--dag-trials", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="ring: only the autotuned learned runs (for profiling; not a bench line)")
+    ap.add_argument("--nearfar-factors", type=float, nargs="+", default=[1.0],
+                    help="Near-Far deltas tried, as multiples of Davidson et al.'s choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the bench runs on one GPU only; --gpus must be 1 "
@@ -648,7 +683,7 @@ def main():
         return
     head = run_ring(args)
     subs = {}
-    for name in ("grid64", "grid8", "batch", "heap"):
+    for name in ("grid64", "grid8", "batch", "heap", "dag"):
         t0 = time.perf_counter()
         subs[name] = RUNNERS[name](args)
         subs[name]["wall_s"] = time.perf_counter() - t0

@@ -248,17 +248,19 @@ typedef struct {
    * of each round, and sssp_stats.level_us / phase_us receive the totals.
    * Adds a little time to every round; no effect on results. */
   uint32_t profile;
-  /* Deep-level workers (sssp_ex and sssp_noalloc; Section 2.2.1, Theorem 1,
-   * Section 4.1's block per level).  0 = off: the workgroup that runs the
-   * rounds resolves every level itself.  L > 0: every level i >= max(L, 2,
-   * the LDS levels) gets a workgroup of its own that runs Resolve(i) when
-   * the level above asks for it (after every fourth Resolve of that level),
-   * while the rounds go on; levels two apart resolve at the same time and
-   * adjacent ones never do.  The round loop and the workers are one
-   * cooperative launch of 1 + (levels - first worker level) workgroups; every
-   * wait between them is bounded (PBH_ETIMEOUT after 10 s without progress).
-   * Same distances; rounds and relaxations as without workers for the plain
-   * rule.  Needs schedule 0.  Ignored by sssp_batch. */
+  /* Large-heap form with deep-level workers (sssp_ex and sssp_noalloc;
+   * Section 2.2.1, Theorem 1, Section 4.1's block per level).  0 = off: one
+   * workgroup runs the rounds and resolves every level itself.  L > 0: every
+   * level i >= max(L, 2, the LDS levels) gets a workgroup of its own that
+   * runs Resolve(i) when the level above asks for it (after every fourth
+   * Resolve of that level), while the rounds go on; levels two apart resolve
+   * at the same time and adjacent ones never do.  The round loop and the
+   * workers are one cooperative launch of 1 + (levels - first worker level)
+   * workgroups; every wait between them is bounded (PBH_ETIMEOUT after 10 s
+   * without progress).  This form also merges and selects on levels in HBM
+   * through an LDS staging area (used whether or not a level gets a worker).
+   * Same distances; rounds and relaxations as without it for the plain rule.
+   * Needs schedule 0.  sssp_batch always uses the staging (no workers). */
   uint32_t deep_level;
 } sssp_opts;
 
@@ -395,8 +397,11 @@ const char *sssp_nearfar_last_error(void);
  * of n/8 plain rounds, the two fastest there run to the end (the cost of a
  * large d grows with the heap, which the early frontiers do not show), and
  * the faster of those is written back into *opts (d, team, k_max; the other
- * fields, k_scale included, are kept and used for the trials).  A query that
- * finishes within a frontier trial skips the later stages.
+ * fields, k_scale and deep_level included, are kept and used for the
+ * trials).  With the learned rule and opts->k_every == 0, the winner also
+ * runs once with the model every fourth round, and opts->k_every becomes 4
+ * or 1, whichever was faster.  A query that finishes within a frontier
+ * trial skips the later stages.
  * dist_out is used as scratch.  Errors: those of sssp_ex.
  */
 int sssp_autotune(const uint64_t *offsets, const uint32_t *targets, const uint32_t *weights, uint32_t n,

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbh.so")
-SOURCES = ["kernels.hip", "abi.hip", "learn.hip", "wide.hip", "nearfar.hip"]
+SOURCES = ["kernels.hip", "kernels_full.hip", "abi.hip", "learn.hip", "wide.hip", "nearfar.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are disabled for all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -65,16 +65,21 @@ struct Arena {
   u64 elems = 0;
 };
 
+// On failure *a is left empty (elems 0, no pointers), so a later call that
+// needs less allocates again instead of using the missing arrays.
 int arena_alloc(Arena* a, u64 elems) {
-  a->elems = elems;
+  *a = Arena{};
   if (elems == 0) return PBH_OK;
-  HIPCHK(hipMalloc(&a->k, elems * sizeof(u64)));
-  hipError_t e = hipMalloc(&a->v, elems * sizeof(u32));
-  if (e != hipSuccess) {
-    (void)hipFree(a->k);
-    a->k = nullptr;
+  u64* k = nullptr;
+  u32* v = nullptr;
+  if (hipMalloc(&k, elems * sizeof(u64)) != hipSuccess || hipMalloc(&v, elems * sizeof(u32)) != hipSuccess) {
+    if (k) (void)hipFree(k);
+    (void)hipGetLastError();  // clear the sticky allocation error
     return fail(PBH_ENOMEM, "hipMalloc of the level arena (%llu elements) failed", (unsigned long long)elems);
   }
+  a->k = k;
+  a->v = v;
+  a->elems = elems;
   return PBH_OK;
 }
 
@@ -623,10 +628,12 @@ int sssp_run(const uint64_t* offsets, const uint32_t* targets, const uint32_t* w
       }
     }
     p.prof = o.profile ? 1u : 0u;
-    // LDS staging for merges of the HBM levels, after the LDS levels (it
-    // shares that room with the speculative rounds' list)
+    // deep_level selects the large-heap form of the round loop: LDS staging
+    // for merges of the HBM levels, after the LDS levels (it shares that
+    // room with the speculative rounds' list), and the deep-level workers
+    p.full = o.deep_level ? 1u : 0u;
     p.stage = 0;
-    if (q > qlds) {
+    if (p.full && q > qlds) {
       const u64 sb = stage_bytes(team, team == 64 ? 8 : 4);
       const size_t lvb = (size_t)lvl_off(d, qlds) * 12ull;
       if (lvb + sb <= budget) {
@@ -892,6 +899,16 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
       if (lvl_off(d, qlds) * 12ull > budget) return fail(PBH_EINVAL, "sssp_batch: LDS levels do not fit");
     }
     lds = std::max(lds, (size_t)(lvl_off(d, qlds) * 12ull));
+    // LDS staging for merges of the HBM levels, after the LDS levels
+    u32 stage = 0;
+    if (qv > qlds) {
+      const u64 sb = stage_bytes(team, team == 64 ? 8 : 4);
+      const size_t lvb = (size_t)lvl_off(d, qlds) * 12ull;
+      if (lvb + sb <= budget) {
+        stage = (u32)sb;
+        lds = std::max(lds, lvb + (size_t)sb);
+      }
+    }
     gel[j] = lvl_off(d, qv) - lvl_off(d, qlds);
     total_gel += gel[j];
     maxn = std::max(maxn, q.n);
@@ -906,6 +923,8 @@ int sssp_batch(const sssp_query* queries, uint32_t nq, const sssp_opts* opts, ss
     p.g.d = d;
     p.g.q = qv;
     p.g.qlds = qlds;
+    p.stage = stage;
+    p.full = 1;
   }
   if (o.trace_features && (!o.trace_keys || !o.trace_ids || !o.trace_count || o.trace_every == 0))
     return fail(PBH_EINVAL, "sssp_batch: trace needs keys, ids, count and trace_every");
@@ -1155,6 +1174,20 @@ int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32
   opts->k_max = ranked[0].kmax;
   opts->team = ranked[0].team;
   opts->k_scale = opts->k_scale > 0.0f ? opts->k_scale : 1.0f;
+  // Learned rule, k_every left to the tuner: the winner (whose time is that
+  // of a whole run) also runs with the model every fourth round; the faster
+  // of the two stays.
+  if (opts->k_rule == 2 && opts->k_every == 0 && ranked[0].kmax != 1) {
+    sssp_opts t = *opts;
+    t.stop_key = 0;
+    t.max_rounds = 0;
+    t.trace_features = nullptr;
+    t.k_every = 4;
+    sssp_stats st;
+    rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
+    if (rc) return rc;
+    opts->k_every = st.kernel_ms < ranked[0].ms ? 4u : 1u;
+  }
   return PBH_OK;
 }
 

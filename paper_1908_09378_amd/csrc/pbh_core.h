@@ -480,7 +480,7 @@ struct in_lds<ArrT<u64 PBH_LDS*, u32 PBH_LDS*>> {
 template <class T, class AA, class AB, class AC>
 PBH_INL u32 merge_dedup(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64* cur, bool filterB,
                         int prefer = PREFER_LIVE) {
-  if constexpr (!in_lds<AA>::v && !in_lds<AB>::v) {
+  if constexpr (T::kStage && !in_lds<AA>::v && !in_lds<AB>::v) {
     if (t.stk && na + nb > (u32)T::kNT * T::kE)
       return merge_dedup_staged(t, A, na, B, nb, C, cur, filterB, prefer);
   }
@@ -490,25 +490,22 @@ PBH_INL u32 merge_dedup(const T& t, AA A, u32 na, AB B, u32 nb, AC C, const u64*
 }
 
 // |{e in A : e <= p}|
-// Loads per thread issued together by the streaming loops over one array
-// (count, the Select passes): enough bytes in flight for HBM arrays.
-constexpr int RU = 4;
 
 template <class T, class AA>
 PBH_INL u32 count_le(const T& t, AA A, u32 n, KV p) {
   if (p.k == KINF) return n;
   u32 c = 0;
-  for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
-    u64 k[RU];
-    u32 v[RU];
+  for (u32 base = 0; base < n; base += (u32)T::kNT * T::kRU) {
+    u64 k[T::kRU];
+    u32 v[T::kRU];
 #pragma unroll
-    for (int r = 0; r < RU; ++r) {
+    for (int r = 0; r < T::kRU; ++r) {
       const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
       k[r] = x < n ? A.k[x] : KINF;
       v[r] = x < n ? A.v[x] : VINF;
     }
 #pragma unroll
-    for (int r = 0; r < RU; ++r) {
+    for (int r = 0; r < T::kRU; ++r) {
       const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
       c += (x < n && kv_le(KV{k[r], v[r]}, p)) ? 1u : 0u;
     }
@@ -618,27 +615,103 @@ PBH_INL KV select_rank(const T& t, AA A, u32 n, u32 r) {
   return res;
 }
 
+// Select over an array in HBM of at most RS elements per thread: every
+// element is read once into registers and the radix passes run there (the
+// same passes as select_kth, without re-reading the array for each byte).
+constexpr int RS = 16;
+
+template <class T, class AA>
+PBH_INL KV select_reg(const T& t, AA A, u32 n, u32 r) {
+  u64 k[RS];
+  u32 v[RS];
+  u64 lo = KINF, hi = 0;
+#pragma unroll
+  for (int q = 0; q < RS; ++q) {
+    const u32 x = (u32)t.tid() + (u32)q * (u32)T::kNT;
+    k[q] = x < n ? A.k[x] : KINF;
+    v[q] = x < n ? A.v[x] : VINF;
+  }
+#pragma unroll
+  for (int q = 0; q < RS; ++q) {
+    const bool in = (u32)t.tid() + (u32)q * (u32)T::kNT < n;
+    lo = k[q] < lo ? k[q] : lo;
+    hi = (in && k[q] > hi) ? k[q] : hi;
+  }
+  t.minmax64(lo, hi);
+  const u64 span = hi - lo;
+  const int nb = span ? 64 - __builtin_clzll(span) : 0;
+  const int top = (nb + 7) & ~7;
+  u64 prefix = 0;
+  u32 cnt = n;
+  for (int s = top - 8; s >= 0; s -= 8) {
+    for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
+    t.sync();
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      const bool in = (u32)t.tid() + (u32)q * (u32)T::kNT < n;
+      const u64 dk = k[q] - lo;
+      const bool m = in && ((s + 8 >= 64) ? true : ((dk >> (s + 8)) == prefix));
+      if (m) t.hist_add(t.sh->hist, (u32)(dk >> s) & 255u);
+    }
+    t.sync();
+    u32 D, below;
+    hist_pick(t, r, &D, &below, &cnt);
+    prefix = (prefix << 8) | D;
+    r -= below;
+  }
+  const u64 K = lo + prefix;
+  if (cnt == 1) {
+#pragma unroll
+    for (int q = 0; q < RS; ++q)
+      if ((u32)t.tid() + (u32)q * (u32)T::kNT < n && k[q] == K) t.sh->b32[3] = v[q];
+    t.sync();
+    const u32 id = t.sh->b32[3];
+    t.sync();
+    return KV{K, id};
+  }
+  u32 idp = 0;
+  for (int s = 24; s >= 0; s -= 8) {
+    for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
+    t.sync();
+#pragma unroll
+    for (int q = 0; q < RS; ++q) {
+      const bool in = (u32)t.tid() + (u32)q * (u32)T::kNT < n;
+      if (in && k[q] == K && (s == 24 || (v[q] >> (s + 8)) == idp)) t.hist_add(t.sh->hist, (v[q] >> s) & 255u);
+    }
+    t.sync();
+    u32 D, below, c2;
+    hist_pick(t, r, &D, &below, &c2);
+    idp = (idp << 8) | D;
+    r -= below;
+  }
+  return KV{K, idp};
+}
+
 // Select(A, r): the r-th smallest (key, id) of A, 1 <= r <= n.  Radix select,
 // most significant byte first, over key - min(key) (only the bytes the key
 // range needs), then over the id among elements with the selected key.  The
 // paper sorted with a radix sort to select (Section 4.1); a radix select reads
 // the candidates once per byte and sorts nothing.  Ranks within two of either
 // end of a small array use select_small; other ranks in arrays of at most two
-// elements per thread use select_rank.
+// elements per thread use select_rank; arrays in HBM of at most RS elements
+// per thread use select_reg.
 template <class T, class AA>
 PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   if (n <= 8u * (u32)T::kNT && (r <= 2 || n - r + 1 <= 2)) return select_small(t, A, n, r);
   if (n <= 2u * (u32)T::kNT) return select_rank(t, A, n, r);
+  if constexpr (T::kStage && !in_lds<AA>::v) {
+    if (n <= (u32)RS * (u32)T::kNT) return select_reg(t, A, n, r);
+  }
   u64 lo = KINF, hi = 0;
-  for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
-    u64 k[RU];
+  for (u32 base = 0; base < n; base += (u32)T::kNT * T::kRU) {
+    u64 k[T::kRU];
 #pragma unroll
-    for (int r = 0; r < RU; ++r) {
+    for (int r = 0; r < T::kRU; ++r) {
       const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
       k[r] = x < n ? A.k[x] : KINF;
     }
 #pragma unroll
-    for (int r = 0; r < RU; ++r) {
+    for (int r = 0; r < T::kRU; ++r) {
       const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
       lo = k[r] < lo ? k[r] : lo;
       hi = (x < n && k[r] > hi) ? k[r] : hi;
@@ -653,15 +726,15 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   for (int s = top - 8; s >= 0; s -= 8) {
     for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
     t.sync();
-    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
-      u64 k[RU];
+    for (u32 base = 0; base < n; base += (u32)T::kNT * T::kRU) {
+      u64 k[T::kRU];
 #pragma unroll
-      for (int r = 0; r < RU; ++r) {
+      for (int r = 0; r < T::kRU; ++r) {
         const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
         k[r] = x < n ? A.k[x] : 0;
       }
 #pragma unroll
-      for (int r = 0; r < RU; ++r) {
+      for (int r = 0; r < T::kRU; ++r) {
         const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
         const u64 dk = k[r] - lo;
         const bool m = x < n && ((s + 8 >= 64) ? true : ((dk >> (s + 8)) == prefix));
@@ -676,15 +749,15 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   }
   const u64 K = lo + prefix;
   if (cnt == 1) {
-    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
-      u64 k[RU];
+    for (u32 base = 0; base < n; base += (u32)T::kNT * T::kRU) {
+      u64 k[T::kRU];
 #pragma unroll
-      for (int r = 0; r < RU; ++r) {
+      for (int r = 0; r < T::kRU; ++r) {
         const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
         k[r] = x < n ? A.k[x] : ~K;
       }
 #pragma unroll
-      for (int r = 0; r < RU; ++r)
+      for (int r = 0; r < T::kRU; ++r)
         if (k[r] == K) t.sh->b32[3] = A.v[base + (u32)r * (u32)T::kNT + (u32)t.tid()];
     }
     t.sync();
@@ -696,17 +769,17 @@ PBH_INL KV select_kth(const T& t, AA A, u32 n, u32 r) {
   for (int s = 24; s >= 0; s -= 8) {
     for (u32 b = (u32)t.tid(); b < 256; b += (u32)T::kNT) t.sh->hist[b] = 0;
     t.sync();
-    for (u32 base = 0; base < n; base += (u32)T::kNT * RU) {
-      u64 k[RU];
-      u32 v[RU];
+    for (u32 base = 0; base < n; base += (u32)T::kNT * T::kRU) {
+      u64 k[T::kRU];
+      u32 v[T::kRU];
 #pragma unroll
-      for (int r = 0; r < RU; ++r) {
+      for (int r = 0; r < T::kRU; ++r) {
         const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
         k[r] = x < n ? A.k[x] : ~K;
         v[r] = x < n ? A.v[x] : 0u;
       }
 #pragma unroll
-      for (int r = 0; r < RU; ++r)
+      for (int r = 0; r < T::kRU; ++r)
         if (k[r] == K && (s == 24 || (v[r] >> (s + 8)) == idp)) t.hist_add(t.sh->hist, (v[r] >> s) & 255u);
     }
     t.sync();
@@ -724,7 +797,7 @@ template <class T, class AA, class A0, class A1, class A2>
 PBH_INL void partition3(const T& t, AA A, u32 n, KV p1, KV p2, A0 O0, A1 O1, A2 O2, u32* n0, u32* n1,
                         u32* n2, const u64* live0 = nullptr) {
   // twice the elements per thread from HBM: more loads in flight per tile
-  constexpr int E = in_lds<AA>::v ? T::kE : 2 * T::kE;
+  constexpr int E = (T::kStage && !in_lds<AA>::v) ? 2 * T::kE : T::kE;
   u32 c0t = 0, c1t = 0, c2t = 0;
   for (u32 base = 0; base < n; base += (u32)T::kNT * E) {
     u32 x0 = base + (u32)t.tid() * E;

@@ -34,6 +34,9 @@ struct SsspParams {
   // bytes of LDS staging for merges of HBM levels, after the LDS levels in
   // the dynamic block (the round loop) or at its start (workers); 0 = none
   u32 stage;
+  // 1: the large-heap form of the round loop (k_sssp_full: staging, deep
+  // workers when `deep` is set); 0: the plain one-workgroup form (k_sssp)
+  u32 full;
 };
 
 
@@ -46,6 +49,7 @@ hipError_t launch_fill_dist(u64* dist, u32 n, u32 src, hipStream_t s);
 hipError_t launch_zero_u64(u64* p, u64 n, hipStream_t s);
 hipError_t launch_check_csr(const u64* off, const u32* tg, u32 n, u64 m, CsrCheck* out, hipStream_t s);
 hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sssp_full(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s);
 size_t sssp_static_lds(int team);
 hipError_t launch_sssp_multi(int team, const SsspParams* qs, u32 nq, u32* counter, size_t lds, int grid,
                              hipStream_t s);

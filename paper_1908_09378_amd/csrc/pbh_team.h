@@ -107,11 +107,17 @@ __device__ __forceinline__ void wave_minmax64(u64& lo, u64& hi) {
   hi = readlane64(hi, 63);
 }
 
-template <int NT>
+// FULL: the team of the large-heap round loop (deep-level workers), whose
+// primitives on HBM levels use the LDS staging area, keep more loads in
+// flight and select in registers; the default team keeps the plain forms,
+// which leave the one-workgroup round loop's registers as they are.
+template <int NT, bool FULL = false>
 struct DevTeam {
   static constexpr int kNT = NT;
   static constexpr int kNW = NT / 64;
   static constexpr int kE = NT == 64 ? 8 : 4;  // elements per thread per tile
+  static constexpr bool kStage = FULL;
+  static constexpr int kRU = FULL ? 4 : 1;     // loads in flight per thread in streaming loops
   TeamShared<kNW> PBH_LDS* sh;
   // LDS staging area for merges of arrays in HBM (null: none): two windows of
   // kNT * kE + 2 elements (keys, then ids) and kNT + 1 split points
@@ -241,11 +247,15 @@ struct DevTeam {
   __device__ __forceinline__ void fence() const { __threadfence(); }
 };
 
-// One-thread team for the CPU logic tests.
-struct HostTeam {
+// One-thread team for the CPU logic tests; STAGE picks the large-heap forms
+// of the primitives (as DevTeam's FULL) or the plain ones.
+template <bool STAGE>
+struct HostTeamT {
   static constexpr int kNT = 1;
   static constexpr int kNW = 1;
   static constexpr int kE = 4;
+  static constexpr bool kStage = STAGE;
+  static constexpr int kRU = STAGE ? 4 : 1;
   TeamShared<1>* sh;
   u64* stk = nullptr;  // staging area (as DevTeam's)
   u32* stv = nullptr;
@@ -289,5 +299,7 @@ struct HostTeam {
   void store_cur(u64* p, u64 v) const { *p = v; }
   void fence() const {}
 };
+using HostTeam = HostTeamT<true>;
+using HostTeamPlain = HostTeamT<false>;
 
 }  // namespace bkt

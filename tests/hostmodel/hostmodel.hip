@@ -1,4 +1,7 @@
 // CPU driver for the heap and parDijkstra logic of the GPU kernels, for tests.
+// The heap operations run the plain forms of the primitives (those of the
+// one-workgroup kernels), the round loop the large-heap forms (staging,
+// register select, more loads in flight).
 //
 // It instantiates the same team-templated code as kernels.hip with a
 // one-thread team on host memory, so that CPU tests can run adversarial
@@ -140,9 +143,9 @@ int hm_update(void* hp, const u64* keys, const u32* ids, u64 count) {
     p.count = count;
     p.ukeys = h->uk.data();
     p.uids = h->ui.data();
-    HostTeam t{&h->ts};
+    HostTeamPlain t{&h->ts};
     LogScope ls(h);
-    pbh_update_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
+    pbh_update_body<HostTeamPlain, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) return 0;
     if (h->q >= MAXL) return -2;
@@ -165,9 +168,9 @@ int hm_delete(void* hp, const u32* ids, u64 count) {
     p.idbits = ceil_log2(h->id_cap);
     p.ids = ids;
     p.count = count;
-    HostTeam t{&h->ts};
+    HostTeamPlain t{&h->ts};
     LogScope ls(h);
-    pbh_delete_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
+    pbh_delete_body<HostTeamPlain, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) return 0;
     if (h->q >= MAXL) return -2;
@@ -190,9 +193,9 @@ int hm_extract(void* hp, u64 k, u64* ko, u32* io, u64* count) {
     p.k = k;
     p.okeys = ko;
     p.oids = io;
-    HostTeam t{&h->ts};
+    HostTeamPlain t{&h->ts};
     LogScope ls(h);
-    pbh_extract_body<HostTeam, TracePolicy>(t, p.g, &h->st, p);
+    pbh_extract_body<HostTeamPlain, TracePolicy>(t, p.g, &h->st, p);
     if (h->st.err) return h->st.err;
     if (h->st.aux[3] == 0) break;
     if (h->q >= MAXL) return -2;

@@ -299,3 +299,19 @@ def test_batch_autotune_then_exact():
     pkg.sssp_batch(qs, k_rule=1, k_fixed=6, **t)
     for q, r in zip(qs, refs):
         assert np.array_equal(host64(q[6]), r)
+
+
+def test_out_of_memory_reports_enomem_and_the_next_call_works():
+    """A heap arena far beyond the GPU's memory: sssp_ex returns PBH_ENOMEM
+    (nothing runs); the library keeps no half-made arena, so the next call,
+    which needs a small one, allocates it and is exact."""
+    g = W.grid4(32, 32, 1, 100, seed=3)
+    ref = oracle.dijkstra(g, 0)
+    print("[sssp] out of memory", flush=True)
+    with pytest.raises(pkg.PBHError) as e:
+        run_sssp(pkg, g, 0, d=4, heap_capacity=1 << 40)
+    assert e.value.code == pkg.PBH_ENOMEM
+    got, st = run_sssp(pkg, g, 0, d=4, heap_capacity=1 << 14)
+    assert np.array_equal(got, ref)
+    got, st = run_sssp(pkg, g, 0)
+    assert np.array_equal(got, ref)
