@@ -3,8 +3,10 @@
 //  k_sssp          one workgroup (one team) runs all parDijkstra rounds; the
 //                  small top levels of the heap live in its LDS, deeper
 //                  levels in HBM.  One kernel per query: no host round trip
-//                  per round.  (The large-heap form with deep-level workers
-//                  and the batched launch are in kernels_full.hip.)
+//                  per round.  Two instantiations: every k rule, or the
+//                  plain rule only (lighter).  (The large-heap form with
+//                  deep-level workers and the batched launch are in
+//                  kernels_full.hip.)
 //  k_pbh_update    BulkUpdate of a host call (current keys + id bitmap,
 //                  then pieces of at most d into S_0, each followed by
 //                  Resolve(0) and the schedule).
@@ -48,14 +50,15 @@ __global__ void k_check_update(const u64* keys, const u32* ids, u64 count, u32 i
   if (b) atomicOr(bad, 1ull);
 }
 
-// One query, one workgroup: the plain form of the round loop.
-template <int NT>
+// One query, one workgroup: the plain form of the round loop, with every k
+// rule (k_sssp) or the plain rule only (k_sssp_plain, lighter).
+template <int NT, bool SPEC>
 __global__ __launch_bounds__(NT) void k_sssp(SsspParams p) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ TeamShared<NT / 64> ts;
   __shared__ HeapState st_lds;
   DevTeam<NT> t{(TeamShared<NT / 64> PBH_LDS*)&ts};
-  sssp_query<NT, false>(t, (HeapState PBH_LDS*)&st_lds, dyn, p);
+  sssp_query<NT, false, SPEC>(t, (HeapState PBH_LDS*)&st_lds, dyn, p);
 }
 
 // dist = INF except dist[src] = 0, for every query (blockIdx.y = query).
@@ -155,13 +158,14 @@ size_t sssp_static_lds(int team) {
   }
 }
 
-template <int NT>
+template <int NT, bool SPEC>
 static hipError_t sssp_go(const SsspParams& p, size_t lds, hipStream_t s) {
   if (lds > 65536 - sssp_static_lds(NT)) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sssp<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_sssp<NT, SPEC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_sssp<NT>, dim3(1), dim3(NT), lds, s, p);
+  hipLaunchKernelGGL((k_sssp<NT, SPEC>), dim3(1), dim3(NT), lds, s, p);
   return hipGetLastError();
 }
 
@@ -174,10 +178,11 @@ hipError_t launch_fill_multi(const SsspParams* qs, u32 nq, u32 maxn, u32* counte
 
 hipError_t launch_sssp(int team, const SsspParams& p, size_t lds_bytes, hipStream_t s) {
   if (p.full) return launch_sssp_full(team, p, lds_bytes, s);
+  const bool spec = p.spec.rule != 0 || p.spec.trace_f;
   switch (team) {
-    case 64: return sssp_go<64>(p, lds_bytes, s);
-    case 256: return sssp_go<256>(p, lds_bytes, s);
-    case 1024: return sssp_go<1024>(p, lds_bytes, s);
+    case 64: return spec ? sssp_go<64, true>(p, lds_bytes, s) : sssp_go<64, false>(p, lds_bytes, s);
+    case 256: return spec ? sssp_go<256, true>(p, lds_bytes, s) : sssp_go<256, false>(p, lds_bytes, s);
+    case 1024: return spec ? sssp_go<1024, true>(p, lds_bytes, s) : sssp_go<1024, false>(p, lds_bytes, s);
     default: return hipErrorInvalidValue;
   }
 }

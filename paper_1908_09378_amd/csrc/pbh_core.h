@@ -1310,6 +1310,8 @@ struct DeepCtl {
   u64 busy[MAXL];         // clock ticks inside Resolve(i) of worker i (profiled runs)
   int err;                // first error of any team (E_*), 0 if none
   u32 exit;               // set by the front once every worker is idle at the end
+  u32 beat;               // the front's round count, published every 1024 rounds (it is alive)
+  u32 beat_pad;
 };
 
 enum { E_TIMEOUT = -5 };
@@ -1497,6 +1499,14 @@ struct DeepFront {
         if (!st->err) release_all(t, g, st);
         hold = false;
       }
+    }
+  }
+
+  // Every 1024 rounds the front shows it is alive, so that a worker whose
+  // level gets no request for a long time can tell that from a stopped front.
+  PBH_INL void tick(const T& t, u64 rounds) {
+    if constexpr (SY::kOn) {
+      if (sy && (rounds & 1023u) == 0) sy->beat(t, (u32)rounds);
     }
   }
 
@@ -2132,7 +2142,10 @@ struct NoHook {
 // tests use it to check invariants; the kernels pass NoHook).
 // With `sy` (and lim < q), levels >= lim are resolved by their own workers
 // (the deep-level service above).
-template <class T, class P, class Hook = NoHook, class SY = NoDeepSync>
+// SPEC false: the plain rule only (one extraction per round, no traces) --
+// the speculative rounds, the model and the update pieces are left out of
+// the code, which lightens the kernel of plain runs.
+template <class T, class P, class Hook = NoHook, class SY = NoDeepSync, bool SPEC = true>
 PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
                          const u32* wt, u64* dist, u32 n, u32 src, int sched, const SpecCfg& sc, SsspCounters* cnt,
                          const Hook& hook = Hook(), SY* sy = nullptr, int lim = MAXL) {
@@ -2167,7 +2180,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     prof_lap(t, st, PROF_DRIVE);
     if (st->err) break;
     hook(g, st, c);
-    if (upos < ulen) {  // next piece of the round's bulk update
+    if (SPEC && upos < ulen) {  // next piece of the round's bulk update
       u32 len = ulen - upos < g.d ? ulen - upos : g.d;
       G U{(decltype(G::k))sc.uk, (decltype(G::v))sc.uv};
       if (g.qlds > 0) {
@@ -2211,13 +2224,13 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     }
     prof_lap(t, st, PROF_OTHER);
     bool more;
-    if (sc.rule == 0 && !sc.trace_f) {
+    if (!SPEC || (sc.rule == 0 && !sc.trace_f)) {
       more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
                                                           sc.order, sc.order_cap, c.extracted)
                         : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
                                                           sc.order, sc.order_cap, c.extracted);
       c.extracted += more ? 1 : 0;
-    } else {
+    } else if constexpr (SPEC) {
       const Lvl a0 = lvl_load(st, 0);
       Arr Bg = lbuf(g, 0, a0.bsel);
       u32 k;
@@ -2236,6 +2249,7 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
       }
       upos = 0;
     }
+    fr.tick(t, c.rounds);
     if (!more) {
       // B_0 is empty only once the heap is (the refill above guarantees it).
       if (st->ell >= 0) {

@@ -22,11 +22,11 @@ struct DevPolicy {
 // it wrote are visible to the team that sees the count; a waiting team's
 // thread 0 issues an agent-scope acquire once the condition holds.  Waits
 // poll with s_sleep and give up at once when another team has failed, or
-// with E_TIMEOUT after DEEP_TIMEOUT of the 100 MHz clock (a Resolve never takes
-// that long) -- or, for a worker waiting for its next request (which may not
-// come for the rest of a long run), after DEEP_RUN_LIMIT.
-constexpr u64 DEEP_TIMEOUT = 1000000000ull;      // 10 s
-constexpr u64 DEEP_RUN_LIMIT = 30000000000ull;   // 300 s
+// with E_TIMEOUT after DEEP_TIMEOUT of the 100 MHz clock without the condition
+// (a Resolve never takes that long); a worker waiting for its next request,
+// which may not come for the rest of a long run, restarts that clock whenever
+// the front's heartbeat (its round count, every 1024 rounds) moves.
+constexpr u64 DEEP_TIMEOUT = 1000000000ull;  // 10 s
 
 template <class T>
 struct DevDeepSync {
@@ -70,16 +70,24 @@ struct DevDeepSync {
   // Thread 0 polls until ready() (true), another team failed or the time ran
   // out (false), or leave_ok and the exit flag is set (false); then acquires.
   template <class F>
-  __device__ bool spin(const T& t, F ready, bool leave_ok, u64 limit = DEEP_TIMEOUT) const {
+  __device__ bool spin(const T& t, F ready, bool leave_ok) const {
     u64 r = 1;
     if (t.tid() == 0) {
-      const u64 t0 = __builtin_amdgcn_s_memrealtime();
+      u64 t0 = __builtin_amdgcn_s_memrealtime();
+      u32 beat = ld(&c->beat);
       while (!ready()) {
         if (ld((const u32*)&c->err) || (leave_ok && ld(&c->exit))) {
           r = 0;
           break;
         }
-        if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+        if (leave_ok) {
+          const u32 b = ld(&c->beat);
+          if (b != beat) {
+            beat = b;
+            t0 = __builtin_amdgcn_s_memrealtime();
+          }
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > DEEP_TIMEOUT) {
           set_err(E_TIMEOUT);
           r = 0;
           break;
@@ -96,7 +104,7 @@ struct DevDeepSync {
   }
   // A Resolve(j) request is pending (true), or the run is over (false).
   __device__ bool wait_request(const T& t, int j) const {
-    return spin(t, [&] { return ld(&c->done[j]) != ld(&c->req[j]); }, true, DEEP_RUN_LIMIT);
+    return spin(t, [&] { return ld(&c->done[j]) != ld(&c->req[j]); }, true);
   }
   __device__ void post(const T& t, int j) const { count(t, &c->req[j]); }
   __device__ void done(const T& t, int j) const { count(t, &c->done[j]); }
@@ -151,6 +159,9 @@ struct DevDeepSync {
     }
     t.sync();
   }
+  __device__ void beat(const T& t, u32 rounds) const {
+    if (t.tid() == 0) __hip_atomic_store((u32 PBH_GLB*)&c->beat, rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __device__ void leave(const T& t) const {
     release(t);
     if (t.tid() == 0) __hip_atomic_store((u32 PBH_GLB*)&c->exit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -182,8 +193,8 @@ __device__ void deep_worker(DevTeam<NT, true>& t, HeapState PBH_LDS* st, unsigne
 // One parDijkstra query on one team: heap state in LDS, levels 0..qlds-1 in
 // the dynamic LDS block, deeper levels in the query's slice of the HBM arena.
 // FULL: the large-heap form (staging for HBM merges, deep-level workers when
-// p.deep is set); otherwise the plain form.
-template <int NT, bool FULL>
+// p.deep is set); otherwise the plain form.  SPEC false: the plain rule only.
+template <int NT, bool FULL, bool SPEC = true>
 __device__ void sssp_query(DevTeam<NT, FULL>& t, HeapState PBH_LDS* st, unsigned char* dyn, const SsspParams& p) {
   Geom g = p.g;
   const u64 nl = lvl_off(g.d, g.qlds);
@@ -213,7 +224,8 @@ __device__ void sssp_query(DevTeam<NT, FULL>& t, HeapState PBH_LDS* st, unsigned
                                                         p.spec, &c, NoHook(), p.deep ? &sy : nullptr,
                                                         p.deep ? p.deep_lim : MAXL);
   } else {
-    sssp_rounds<TT, DevPolicy>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched, p.spec, &c);
+    sssp_rounds<TT, DevPolicy, NoHook, NoDeepSync, SPEC>(t, g, st, p.off, p.tg, p.wt, p.dist, p.n, p.src, p.sched,
+                                                         p.spec, &c);
   }
   t.sync();
   if (threadIdx.x == 0) {

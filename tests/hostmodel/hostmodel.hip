@@ -316,6 +316,7 @@ struct SimDeep {
   int error(const HostTeam&) { return c.err; }
   void merge_stats(const HostTeam&, HeapState* st, int, int) { st->elems += c.elems; }
   void leave(const HostTeam&) { c.exit = 1; }
+  void beat(const HostTeam&, u32 r) { c.beat = r; }
 };
 
 // Invariant checks run after every operation of the round loop: the smallest
