@@ -1580,7 +1580,10 @@ PBH_INL u32 intake(const T& t, A S, u32 n, A tmp, A tmp2, const u64* dist, int i
 // (atomicMin on dist) and compact the improved (dist, v) pairs with a prefix
 // sum straight into S_0 (a BulkUpdate of at most d = max out-degree pairs).
 // Returns false when the heap is empty.
-template <class T, class P, class A0>
+// LONG: the forms for long rows and a large B_0 in HBM (the plain-rule-only
+// kernel, whose registers have room for them; in the kernel that also runs
+// speculative rounds they would change the register allocation of those).
+template <class T, class P, class A0, bool LONG = false>
 PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64* off, const u32* tg,
                         const u32* wt, u64* dist, int idbits, u64* relax, u64* upd, u32* order, u64 order_cap,
                         u64 nth) {
@@ -1589,12 +1592,33 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
   A0 B = as_arr<A0>(lbuf(g, 0, a0.bsel));
   u64 mk = KINF;
   u32 mv = VINF;
-  for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) {
-    u64 k = B.k[x];
-    u32 v = B.v[x];
-    if (k < mk || (k == mk && v < mv)) {
-      mk = k;
-      mv = v;
+  if constexpr (!LONG || in_lds<A0>::v) {
+    for (u32 x = (u32)t.tid(); x < a0.nB; x += (u32)T::kNT) {
+      u64 k = B.k[x];
+      u32 v = B.v[x];
+      if (k < mk || (k == mk && v < mv)) {
+        mk = k;
+        mv = v;
+      }
+    }
+  } else {
+    // B_0 in HBM (large d): eight loads per thread in flight per pass
+    constexpr int U = 8;
+    for (u32 base = 0; base < a0.nB; base += (u32)T::kNT * U) {
+      u64 k[U];
+      u32 v[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const u32 x = base + (u32)r * (u32)T::kNT + (u32)t.tid();
+        k[r] = x < a0.nB ? B.k[x] : KINF;
+        v[r] = x < a0.nB ? B.v[x] : VINF;
+      }
+#pragma unroll
+      for (int r = 0; r < U; ++r)
+        if (k[r] < mk || (k[r] == mk && v[r] < mv)) {
+          mk = k[r];
+          mv = v[r];
+        }
     }
   }
   t.minkv(mk, mv);
@@ -1606,7 +1630,35 @@ PBH_INL bool round_body(const T& t, const Geom& g, typename P::SP st, const u64*
   prof_lap(t, st, PROF_EXTRACT);
   A0 S = as_arr<A0>(lbuf(g, 0, 3));
   u32 nu = 0;
-  for (u64 eb = e0; eb < e1; eb += (u64)T::kNT) {
+  u64 eb = e0;
+  // Long rows: four edges per thread per pass, their loads and atomics in
+  // flight together (the scans place the improvements in edge order, edge
+  // eb + r * NT + tid before those of r + 1).
+  constexpr int RE = 4;
+  for (; LONG && e1 - eb >= (u64)T::kNT * RE; eb += (u64)T::kNT * RE) {
+    u64 cand[RE];
+    u32 v[RE];
+    bool imp[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const u64 e = eb + (u64)r * T::kNT + (u64)t.tid();
+      v[r] = tg[e];
+      cand[r] = mk + (u64)wt[e];
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) imp[r] = cand[r] < t.atomic_min(dist + v[r], cand[r]);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      u32 tot;
+      const u32 p = t.scan_excl(imp[r] ? 1u : 0u, &tot);
+      if (imp[r]) {
+        S.k[nu + p] = cand[r];
+        S.v[nu + p] = v[r];
+      }
+      nu += tot;
+    }
+  }
+  for (; eb < e1; eb += (u64)T::kNT) {
     u64 e = eb + (u64)t.tid();
     bool imp = false;
     u64 cand = 0;
@@ -2225,9 +2277,10 @@ PBH_INL void sssp_rounds(const T& t, const Geom& g, typename P::SP st, const u64
     prof_lap(t, st, PROF_OTHER);
     bool more;
     if (!SPEC || (sc.rule == 0 && !sc.trace_f)) {
-      more = g.qlds > 0 ? round_body<T, P, typename P::L>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
+      more = g.qlds > 0
+                 ? round_body<T, P, typename P::L, !SPEC>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
                                                           sc.order, sc.order_cap, c.extracted)
-                        : round_body<T, P, typename P::G>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
+                 : round_body<T, P, typename P::G, !SPEC>(t, g, st, off, tg, wt, dist, idbits, &c.relax, &c.updates,
                                                           sc.order, sc.order_cap, c.extracted);
       c.extracted += more ? 1 : 0;
     } else if constexpr (SPEC) {

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <new>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../paper_1908_09378_amd/csrc/pbh_core.h"
@@ -470,19 +471,29 @@ int hm_sssp(const u64* off, const u32* tg, const u32* wt, u32 n, u64 m, u32 src,
   } else {
     lim = MAXL;
   }
-  if (check_live) {
-    LiveCheck hk{dist, n, rule == 0, &first_bad, info, sim};
-    if (sim)
-      sssp_rounds<HostTeam, HostPolicy, LiveCheck, SimDeep>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk,
-                                                            sim, lim);
-    else
-      sssp_rounds<HostTeam, HostPolicy, LiveCheck>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, hk);
-  } else if (sim) {
-    sssp_rounds<HostTeam, HostPolicy, NoHook, SimDeep>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c, NoHook(),
-                                                       sim, lim);
-  } else {
-    sssp_rounds<HostTeam, HostPolicy>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
-  }
+  // The plain rule runs the plain-rule-only instantiation (as the kernel
+  // does), the other rules the general one.
+  auto run = [&](auto spec_tag) {
+    constexpr bool SPEC = decltype(spec_tag)::value;
+    if (check_live) {
+      LiveCheck hk{dist, n, rule == 0, &first_bad, info, sim};
+      if (sim)
+        sssp_rounds<HostTeam, HostPolicy, LiveCheck, SimDeep, SPEC>(t, g, &st, off, tg, wt, dist, n, src, sched, sc,
+                                                                    &c, hk, sim, lim);
+      else
+        sssp_rounds<HostTeam, HostPolicy, LiveCheck, NoDeepSync, SPEC>(t, g, &st, off, tg, wt, dist, n, src, sched,
+                                                                       sc, &c, hk);
+    } else if (sim) {
+      sssp_rounds<HostTeam, HostPolicy, NoHook, SimDeep, SPEC>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c,
+                                                               NoHook(), sim, lim);
+    } else {
+      sssp_rounds<HostTeam, HostPolicy, NoHook, NoDeepSync, SPEC>(t, g, &st, off, tg, wt, dist, n, src, sched, sc, &c);
+    }
+  };
+  if (rule == 0)
+    run(std::false_type());
+  else
+    run(std::true_type());
   stats[28] = sim ? sim->runs : 0;
   stats[29] = sim ? (u64)sim->lim : 0;
   if (sim) sim->~SimDeep();
