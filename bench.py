@@ -64,9 +64,26 @@ def log(msg):
 
 
 # ----------------------------------------------------------------- helpers
-def kernel_source_sha():
+# The sources each measured kernel is built from: a change to any of them
+# voids that kernel's recorded counters.
+_CORE = ["pbh_team.h", "pbh_core.h"]
+KERNEL_FAMILIES = {
+    "k_sssp": _CORE + ["pbh_launch.h", "round_loop.h", "kernels.hip"],
+    "k_sssp_full": _CORE + ["pbh_launch.h", "round_loop.h", "kernels_full.hip"],
+    "k_sssp_multi": _CORE + ["pbh_launch.h", "round_loop.h", "kernels_full.hip"],
+    "k_nearfar": ["pbh_team.h", "nearfar.hip"],
+    "heap": _CORE + ["wide.h", "wide.hip"],
+}
+
+
+def kernel_source_sha(kernel=None, workload=None):
+    """Hash of the sources `kernel` is built from (all kernel sources when
+    no kernel is named; every engine kernel of the standalone heap shares the
+    "heap" family)."""
+    fam = "heap" if workload == "heap" else kernel
+    files = KERNEL_FAMILIES.get(fam, KERNEL_SOURCES)
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,12 +92,12 @@ def kernel_source_sha():
 def counter_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the calibrated
     rocprofv3 counters recorded in profiles/traffic.md -- or None when none
-    were taken, or when the kernel sources changed since (the row's source
+    were taken, or when the kernel's sources changed since (the row's source
     hash differs from the current one)."""
     path = os.path.join(ROOT, "profiles", "traffic.md")
     if not os.path.exists(path):
         return None
-    sha = kernel_source_sha()
+    sha = kernel_source_sha(kernel, workload)
     for line in open(path):
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) >= 5 and cells[0] == kernel and cells[1] == workload and cells[2] == sha:
@@ -158,7 +175,7 @@ class Query:
         log(f"{label}: {sec * 1e3:.1f} ms/step over {steps}, {stats[-1]['rounds']} rounds, exact={ex}")
         return sec, stats, ex
 
-    def record(self, sec, stats, exact, method, workload, steps, warmup):
+    def record(self, sec, stats, exact, method, workload, steps, warmup, kernel="k_sssp"):
         st = stats[-1]
         kern_ms = sum(x["kernel_ms"] for x in stats) / len(stats)
         kms = sorted(x["kernel_ms"] for x in stats)
@@ -168,7 +185,7 @@ class Query:
                 "relaxations": st["relaxations"], "extracted": st["extracted"], "updates": st["updates"],
                 "d": st["d"], "team": st["team"], "levels": st["levels"], "lds_levels": st["lds_levels"],
                 "us_per_round": kern_ms * 1e3 / max(1, st["rounds"]), "exact": exact,
-                "roofline": roofline("k_sssp", workload, sssp_bytes(st), kern_ms)}
+                "roofline": roofline(kernel, workload, sssp_bytes(st), kern_ms)}
 
     def nearfar(self, steps, factors=(1.0,)):
         """The Near-Far (Delta-stepping) baseline on the same graph: delta =
@@ -308,7 +325,8 @@ def run_grid8(args):
     blob = load_blob()
     lr = q.record(*q.timed(args.base_steps, 1, "grid8 learned", k_rule=2, k_model=blob, **GRID8_LEARNED),
                   LEARNED_DESC + "; d = 256, team 256, k_max 256, model every 4th round (autotuned settings for "
-                  "this graph), deep-level workers from level 2", "grid8", args.base_steps, 1)
+                  "this graph), deep-level workers from level 2", "grid8", args.base_steps, 1,
+                  kernel="k_sssp_full")
     # Plain parDijkstra settles one vertex per round, 4,194,304 rounds here
     # (many minutes); the bench times its first 2^18 rounds and reports their
     # rate.  The heap grows during a run, so later rounds cost more and the
@@ -322,7 +340,7 @@ def run_grid8(args):
           "rounds": st["rounds"], "relaxations": st["relaxations"], "ms": sec * 1e3,
           "us_per_round": kern_s * 1e6 / st["rounds"], "edges_per_s": st["relaxations"] / kern_s,
           "estimated_full_s": kern_s / st["rounds"] * g.n,
-          "roofline": roofline("k_sssp", "grid8_plain", sssp_bytes(st), st["kernel_ms"])}
+          "roofline": roofline("k_sssp_full", "grid8_plain", sssp_bytes(st), st["kernel_ms"])}
     nfr = q.nearfar(args.base_steps, args.nearfar_factors)
     rec = {"metric": "SSSP GTEPS (m/time), learned threshold", **lr,
            "config": {"workload": GRID8_DESC, "n": g.n, "m": g.m}, "plain": pl,
