@@ -86,7 +86,8 @@ int pbh_create_ex(pbh_t **out, uint32_t id_capacity, uint32_t d, const pbh_opts 
  * are applied in pieces of at most d (the paper's bound on |U|), with the same
  * result.  Errors: PBH_EINVAL (NULL handle, NULL arrays with count > 0, any
  * id >= id_capacity or key == UINT64_MAX; nothing is applied), PBH_ECAPACITY,
- * PBH_EDEVICE, PBH_EINTERNAL.
+ * PBH_EDEVICE, PBH_ETIMEOUT (device-wide engine: a step's kernels ended
+ * without publishing its results within a second), PBH_EINTERNAL.
  */
 int pbh_bulk_update(pbh_t *h, const uint64_t *keys, const uint32_t *ids, uint64_t count);
 
@@ -96,7 +97,8 @@ int pbh_bulk_update(pbh_t *h, const uint64_t *keys, const uint32_t *ids, uint64_
  * elements and writes them in ascending (key, id) order to keys_out[] and
  * ids_out[] (device arrays with room for k); *count_out (host) receives their
  * number.  Equal to k successive ExtractMins.  Errors: PBH_EINVAL (NULL handle
- * or count_out, NULL outputs with k > 0), PBH_EDEVICE, PBH_EINTERNAL.
+ * or count_out, NULL outputs with k > 0), PBH_EDEVICE, PBH_ETIMEOUT (as for
+ * pbh_bulk_update), PBH_EINTERNAL.
  */
 int pbh_extract_min(pbh_t *h, uint64_t k, uint64_t *keys_out, uint32_t *ids_out,
                     uint64_t *count_out);
@@ -111,7 +113,7 @@ int pbh_extract_min(pbh_t *h, uint64_t k, uint64_t *keys_out, uint32_t *ids_out,
  * at once, followed by Resolve(0) and the schedule as after any operation.
  * Errors: PBH_EINVAL (NULL handle, NULL ids with count > 0, any id >=
  * id_capacity; nothing is applied), PBH_ECAPACITY, PBH_EDEVICE,
- * PBH_EINTERNAL.
+ * PBH_ETIMEOUT (as for pbh_bulk_update), PBH_EINTERNAL.
  */
 int pbh_delete(pbh_t *h, const uint32_t *ids, uint64_t count);
 

@@ -156,6 +156,8 @@ int push_state(pbh* h) {
 int state_error(const HeapState& s) {
   if (s.err == E_CAPACITY) return fail(PBH_ECAPACITY, "a heap level overflowed its allocation");
   if (s.err == E_DEVICE) return fail(PBH_EDEVICE, "a HIP call of the device-wide heap engine failed");
+  if (s.err == E_TIMEOUT)
+    return fail(PBH_ETIMEOUT, "a step of the device-wide heap engine ended without publishing its results");
   if (s.err) return fail(PBH_EINTERNAL, "device-side heap check failed (code %d)", s.err);
   return PBH_OK;
 }

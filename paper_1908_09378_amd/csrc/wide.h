@@ -31,7 +31,8 @@ struct WideHeap {
   void* ctx;
 };
 
-// Error codes: 0, E_CAPACITY, E_INTERNAL, or E_DEVICE for a failed HIP call.
+// Error codes: 0, E_CAPACITY, E_INTERNAL, E_DEVICE for a failed HIP call, or
+// E_TIMEOUT for a step whose kernels ended without publishing its results.
 constexpr int E_DEVICE = -4;
 
 int wide_create(WideScratch** out, u32 d);

@@ -1247,7 +1247,8 @@ int prof_collect(WideScratch* w) {
 // polling the mailbox's sequence number (a stream synchronisation would add
 // the runtime's completion path and a system-scope cache write-back to every
 // step).  Should the number not arrive within a second, the stream is
-// synchronised, which also reports a failed kernel.
+// synchronised, which also reports a failed kernel (E_DEVICE); a step whose
+// kernels all ended without the number arriving gives E_TIMEOUT.
 int fetch(WideScratch* w) {
   const u32 want = ++w->seq;
   plaunch(w, WK_OTHER, 2ull * sizeof(Mail),
@@ -1259,7 +1260,7 @@ int fetch(WideScratch* w) {
     if ((spin & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) break;
   }
   WCHK(hipStreamSynchronize(w->s));
-  return __atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want ? 0 : E_DEVICE;
+  return __atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want ? 0 : E_TIMEOUT;
 }
 
 // C = DeleteDuplicates(Merge(A, B)) by id; *num_le = outputs <= piv.
