@@ -646,6 +646,40 @@ def run_dag(args):
     return rec
 
 
+def run_train(args):
+    """Training of the extraction-threshold model, timed stage by stage with
+    the settings that produced the committed model (paper_1908_09378_amd/learn.py):
+    200 seeded training graphs (ring / 4-neighbour / 8-neighbour grids, n in
+    2^14..2^18), plain runs with traces every 16th round in one batched
+    launch, labels, then 4000 Adam steps of batch 1024 on the GPU."""
+    import torch
+    import workloads as W
+    from paper_1908_09378_amd import learn
+    t0 = time.perf_counter()
+    graphs = W.training_graphs(args.train_graphs)
+    gen_s = time.perf_counter() - t0
+    log(f"train: {len(graphs)} graphs generated in {gen_s:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, Y, st = learn.collect(graphs, 16)
+    torch.cuda.synchronize()
+    trace_s = time.perf_counter() - t0
+    log(f"train: {X.shape[0]} traced rounds in {trace_s:.1f} s")
+    t0 = time.perf_counter()
+    blob, losses = learn.train(X, Y, 4000, 1024, 1e-3)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    log(f"train: 4000 steps in {fit_s:.1f} s")
+    return {"metric": "extraction-threshold model training time", "value": trace_s + fit_s, "unit": "s",
+            "higher_is_better": False, "graphs": len(graphs), "sum_n": sum(g.n for g in graphs),
+            "traced_rounds": int(X.shape[0]), "graph_generation_s": gen_s, "trace_and_label_s": trace_s,
+            "fit_s": fit_s, "steps": 4000, "batch": 1024,
+            "loss_first_10": float(losses[:10].mean()), "loss_last_50": float(losses[-50:].mean()),
+            "label_variance": float(Y.var().item()),
+            "what": "value = trace collection + labels + training on the GPU (graph generation on the host "
+                    "reported apart)"}
+
+
 def run_copy(args):
     """Calibration for the HBM counters: a plain device-to-device copy of
     2 GiB (torch's copy kernel), repeated `steps` times.  FETCH_SIZE and
@@ -666,7 +700,7 @@ def run_copy(args):
 
 
 RUNNERS = {"ring": run_ring, "grid64": run_grid64, "grid8": run_grid8, "batch": run_batch, "heap": run_heap,
-           "dag": run_dag, "copy": run_copy}
+           "dag": run_dag, "copy": run_copy, "train": run_train}
 
 
 def main():
@@ -682,6 +716,7 @@ def main():
     ap.add_argument("--dag-m", type=int, default=40_000_000)
     ap.add_argument("--dag-seeds", type=int, default=1)
     ap.add_argument("--dag-trials", type=int, default=2)
+    ap.add_argument("--train-graphs", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned-only", action="store_true",
                     help="ring: only the autotuned learned runs (for profiling; not a bench line)")
