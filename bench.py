@@ -736,7 +736,7 @@ def main():
         return
     head = run_ring(args)
     subs = {}
-    for name in ("grid64", "grid8", "batch", "heap", "dag"):
+    for name in ("grid64", "grid8", "batch", "heap", "dag", "train"):
         t0 = time.perf_counter()
         subs[name] = RUNNERS[name](args)
         subs[name]["wall_s"] = time.perf_counter() - t0

@@ -70,6 +70,7 @@ struct Ctl {
   u32 sncand;
   u32 passdone;  // workgroups finished with the current pass (the last one picks)
   u32 npass;     // passes that did work since the last gather (profiling)
+  u32 scandone;  // workgroups of a publishing k_scan finished (the last one publishes)
   u32 shist[SEL_BINS];
 };
 
@@ -419,9 +420,39 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
   }
 }
 
+// A step published by the kernel that computes the last result the host
+// reads (a one-workgroup scan or reduction), instead of by k_post after the
+// step's last kernel: the host then reads the sizes and goes on while the
+// step's writing pass, whose output it never reads, still runs (its next
+// launches queue behind that pass on the stream).  mail == nullptr: the
+// kernel does not publish.
+struct Pub {
+  const Mail* box;
+  Mail* mail;
+  u32 seq;
+};
+
+// Copies the box into the host-mapped mailbox and then writes the sequence
+// number (as k_post).  Called by every thread of the publishing workgroup
+// once its results are in the box: the wait and the barrier make this
+// workgroup's stores reach the L2, which the agent-scope loads read.
+__device__ __forceinline__ void publish(const Pub& p) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const u32 l = threadIdx.x;
+  if (l + 1 < MAIL_WORDS) {
+    ((u32*)p.mail)[l] =
+        __hip_atomic_load((const u32 PBH_GLB*)p.box + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence_system();
+  }
+  __syncthreads();
+  if (l == 0) __hip_atomic_store(&p.mail->seq, p.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Sums n partial counts into *sum (when sum != null) and folds the partial
-// key ranges into ctl->kmin / kmax.  One workgroup.
-__global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32, u64* sum64, Ctl* c) {
+// key ranges into ctl->kmin / kmax.  One workgroup; publishes the step when
+// pub.mail is set.
+__global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32, u64* sum64, Ctl* c, Pub pub) {
   __shared__ u32 sw[16];
   __shared__ u64 swl[16], swh[16];
   u64 tot = 0, lo = KINF, hi = 0;
@@ -442,12 +473,18 @@ __global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32,
       c->kmax = hi;
     }
   }
+  if (pub.mail) publish(pub);
 }
 
 // Exclusive scan of n tile counts (one workgroup of 1024); *total = the sum.
 // blockIdx.x selects one of several count arrays spaced `stride` apart.
-__global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride, u32* off, u32* total) {
+// With pub.mail set, the last of the workgroups to finish publishes the step
+// (ctl->scandone counts them; the totals are stored with agent-scope stores
+// so that it reads every one).
+__global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride, u32* off, u32* total, Ctl* ctl,
+                                               Pub pub) {
   __shared__ u32 sw[16];
+  __shared__ int s_last;
   cnt += (u64)blockIdx.x * stride;
   off += (u64)blockIdx.x * stride;
   u32 carry = 0;
@@ -459,7 +496,22 @@ __global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride
     if (x < n) off[x] = carry + e;
     carry += tot;
   }
-  if (threadIdx.x == 0) total[blockIdx.x] = carry;
+  if (threadIdx.x == 0)
+    __hip_atomic_store((u32 PBH_GLB*)(total + blockIdx.x), carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!pub.mail) return;
+  if (gridDim.x > 1) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const u32 prev =
+          __hip_atomic_fetch_add((u32 PBH_GLB*)&ctl->scandone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = prev == gridDim.x - 1;
+      if (s_last) __hip_atomic_store((u32 PBH_GLB*)&ctl->scandone, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!s_last) return;
+  }
+  publish(pub);
 }
 
 
@@ -1243,17 +1295,13 @@ int prof_collect(WideScratch* w) {
   return 0;
 }
 
-// Ends a step: publishes its results and waits until the host sees them, by
-// polling the mailbox's sequence number (a stream synchronisation would add
-// the runtime's completion path and a system-scope cache write-back to every
-// step).  Should the number not arrive within a second, the stream is
-// synchronised, which also reports a failed kernel (E_DEVICE); a step whose
-// kernels all ended without the number arriving gives E_TIMEOUT.
-int fetch(WideScratch* w) {
-  const u32 want = ++w->seq;
-  plaunch(w, WK_OTHER, 2ull * sizeof(Mail),
-          [&] { hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, w->s, w->box, w->mail_d, want); });
-  if (int rc = launch_ok()) return rc;
+// Waits until the host sees step `want` published, by polling the mailbox's
+// sequence number (a stream synchronisation would add the runtime's
+// completion path and a system-scope cache write-back to every step).
+// Should the number not arrive within a second, the stream is synchronised,
+// which also reports a failed kernel (E_DEVICE); a step whose kernels all
+// ended without the number arriving gives E_TIMEOUT.
+int wait_mail(WideScratch* w, u32 want) {
   const auto t0 = std::chrono::steady_clock::now();
   for (u32 spin = 1;; ++spin) {
     if (__atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want) return 0;
@@ -1261,6 +1309,16 @@ int fetch(WideScratch* w) {
   }
   WCHK(hipStreamSynchronize(w->s));
   return __atomic_load_n(&w->mail_h->seq, __ATOMIC_ACQUIRE) == want ? 0 : E_TIMEOUT;
+}
+
+// Ends a step whose kernels do not publish it: k_post publishes the box,
+// then the host waits for it.
+int fetch(WideScratch* w) {
+  const u32 want = ++w->seq;
+  plaunch(w, WK_OTHER, 2ull * sizeof(Mail),
+          [&] { hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, w->s, w->box, w->mail_d, want); });
+  if (int rc = launch_ok()) return rc;
+  return wait_mail(w, want);
 }
 
 // C = DeleteDuplicates(Merge(A, B)) by id; *num_le = outputs <= piv.
@@ -1279,8 +1337,14 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
     hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
                        (const u32*)nullptr, w->pt, 0);
   });
+  // The step is published by the scan (the output size) or, when the count
+  // of outputs <= the pivot is wanted, by the reduction after the writing
+  // pass.
+  const u32 want = ++w->seq;
+  const Pub pub{w->box, w->mail_d, want}, none{nullptr, nullptr, 0u};
   plaunch(w, WK_OTHER, 8ull * nt, [&] {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total, w->ctl,
+                       stats ? none : pub);
   });
   const int iw = plaunch(w, WK_MERGE_WRITE, 12ull * total, [&] {
     hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, (u32*)nullptr,
@@ -1288,10 +1352,11 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   });
   if (stats)
     plaunch(w, WK_OTHER, 20ull * nt, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl);
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl,
+                         pub);
     });
   if (int rc = launch_ok()) return rc;
-  if (int rc = fetch(w)) return rc;
+  if (int rc = wait_mail(w, want)) return rc;
   *m = w->mail_h->total;
   *num_le = stats ? w->mail_h->num_le : 0u;
   patch_bytes(w, iw, 12ull * (total + *m));  // 12 B per input read + 12 B per output written
@@ -1312,7 +1377,8 @@ int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2
     const u32 gm = grid_for(n);
     plaunch(w, WK_OTHER, 8ull * n, [&] { hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt); });
     plaunch(w, WK_OTHER, 20ull * gm, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl,
+                         Pub{nullptr, nullptr, 0u});
     });
   }
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
@@ -1359,14 +1425,17 @@ int wpartition3_sel(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, 
   plaunch(w, WK_SPLIT_COUNT, 12ull * n, [&] {
     hipLaunchKernelGGL(k_part<false>, dim3(nt), dim3(NT), 0, w->s, a, w->tc, (const u32*)nullptr, w->maxtiles);
   });
+  // published by the scan: the sizes are known before the writing pass
+  const u32 want = ++w->seq;
   plaunch(w, WK_OTHER, 24ull * nt, [&] {
-    hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part);
+    hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part, w->ctl,
+                       Pub{w->box, w->mail_d, want});
   });
   plaunch(w, WK_SPLIT_WRITE, 24ull * n, [&] {
     hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
   });
   if (int rc = launch_ok()) return rc;
-  if (int rc = fetch(w)) return rc;
+  if (int rc = wait_mail(w, want)) return rc;
   *n0 = w->mail_h->part[0];
   *n1 = w->mail_h->part[1];
   *n2 = w->mail_h->part[2];
@@ -1634,7 +1703,7 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
   });
   plaunch(w, WK_OTHER, 4ull * gi, [&] {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                       (u32*)nullptr, &w->box->newly, w->ctl);
+                       (u32*)nullptr, &w->box->newly, w->ctl, Pub{nullptr, nullptr, 0u});
   });
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
@@ -1646,15 +1715,18 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
     hipLaunchKernelGGL(k_bits<false>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, w->tc, (const u32*)nullptr,
                        (const u64*)h->cur, uk, uv);
   });
+  // published by the scan: the count of U is known before the compaction
+  const u32 want = ++w->seq;
   plaunch(w, WK_OTHER, 8ull * nt, [&] {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total, w->ctl,
+                       Pub{w->box, w->mail_d, want});
   });
   const int ib = plaunch(w, WK_BITS_WRITE, nmark, [&] {
     hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, (u32*)nullptr, w->toff,
                        (const u64*)h->cur, uk, uv);
   });
   if (int rc = launch_ok()) return rc;
-  if (int rc = fetch(w)) return rc;
+  if (int rc = wait_mail(w, want)) return rc;
   const u64 nu = w->mail_h->total;
   // marks read, plus per output its current key read (8 B) and the pair written (12 B)
   patch_bytes(w, ib, nmark + 20ull * nu);
@@ -1692,7 +1764,7 @@ int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count) {
           [&] { hipLaunchKernelGGL(k_delete, dim3(gi), dim3(NT), 0, w->s, ids, count, h->cur, w->pt); });
   plaunch(w, WK_OTHER, 4ull * gi, [&] {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                       (u32*)nullptr, &w->box->newly, w->ctl);
+                       (u32*)nullptr, &w->box->newly, w->ctl, Pub{nullptr, nullptr, 0u});
   });
   if (int rc = launch_ok()) return rc;
   const Lvl a0 = st->L[0];
