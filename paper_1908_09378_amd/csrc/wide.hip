@@ -7,9 +7,10 @@
 //       points), a scan of the tile counts, and a writing pass; in both passes
 //       each thread walks 8 consecutive merge positions from one merge-path
 //       search in LDS, and the writing pass stores its outputs through an
-//       LDS transpose.  The writing pass can also count outputs <= a pivot
+//       LDS transpose.  The counting pass can also count outputs <= a pivot
 //       (the count in Resolve's EMPTY step) and the key range (the start of
-//       Select), as per-workgroup partials folded by k_reduce.
+//       Select), as per-workgroup partials folded by the scan, which then
+//       publishes the step before the writing pass runs.
 //   k_part<false> / k_scan (three arrays) / k_part<true>
 //       Stable three-way split by two (key, id) pivots.
 //   k_sel_pass / k_sel_collect
@@ -251,30 +252,31 @@ constexpr u32 SPW = NT / 64;
 // start, then a sequential walk merges them (ties: A first), so a copy of an
 // id present in both inputs sits right after A's copy.  The pair is decided
 // at A's slot (pair_keep) and B's slot is dropped; a partner just outside the
-// tile is A[i0-1] or B[j1].  Counting pass: tcnt[t] = kept outputs.  Writing
-// pass: a scan of the threads' kept counts gives each output its place in the
-// tile's output range; the outputs are transposed through LDS (reusing the
-// input staging, at index o + o/8 so that the threads' runs of WE spread over
-// the banks) and stored coalesced at toff[t] + o.  Stored straight from the
-// walk, each store instruction would touch 64 cache lines (a thread's
-// outputs are consecutive), which measured 1.6x slower.  With `stats` the
-// writing pass also counts outputs <= (pk, pv) and the key range.
-// Per-workgroup partial results (a count and a key range), reduced by
-// k_reduce: thousands of workgroups updating the same word with atomics would
-// serialise in the L2.
+// tile is A[i0-1] or B[j1].  Counting pass: tcnt[t] = kept outputs; with
+// KEYS it also stages the keys and counts the outputs <= (pk, pv) and their
+// key range, as per-workgroup partials (thousands of workgroups updating the
+// same word with atomics would serialise in the L2) that the scan folds.
+// So the scan, which runs before the writing pass, has every result the host
+// reads.  Writing pass: a scan of the threads' kept counts gives each output
+// its place in the tile's output range; the outputs are transposed through
+// LDS (reusing the input staging, at index o + o/8 so that the threads' runs
+// of WE spread over the banks) and stored coalesced at toff[t] + o.  Stored
+// straight from the walk, each store instruction would touch 64 cache lines
+// (a thread's outputs are consecutive), which measured 1.6x slower.
 struct Partials {
   u32* cnt;
   u64* lo;
   u64* hi;
 };
 
-template <bool WRITE>
+template <bool WRITE, bool KEYS = WRITE>
 __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* part_out, u32* tcnt, const u32* toff,
-                                              Partials pt, int stats) {
+                                              Partials pt) {
+  static_assert(KEYS || !WRITE, "the writing pass stages keys");
   constexpr u32 NONE = 0xFFFFFFFFu;  // exhausted input (ids are < 2^32 - 1)
   constexpr u32 PAD = WRITE ? TILE / 8 : 0;  // room for the transposed index o + o/8
   __shared__ u32 sv[TILE + PAD];
-  __shared__ u64 sk[WRITE ? TILE + PAD : 1];
+  __shared__ u64 sk[KEYS ? TILE + PAD : 1];
   __shared__ u32 sw[NT / 64];
   __shared__ u64 swl[NT / 64], swh[NT / 64];
   const u32 t = blockIdx.x, total = a.na + a.nb;
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
       lk[q] = 0;
       if (x < nT) {
         lv[q] = fromA ? a.av[g] : a.bv[g];
-        if constexpr (WRITE) lk[q] = fromA ? a.ak[g] : a.bk[g];
+        if constexpr (KEYS) lk[q] = fromA ? a.ak[g] : a.bk[g];
       }
     }
 #pragma unroll
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
       const u32 x = threadIdx.x + (u32)q * NT;
       if (x < nT) {
         sv[x] = lv[q];
-        if constexpr (WRITE) sk[x] = lk[q];
+        if constexpr (KEYS) sk[x] = lk[q];
       }
     }
   }
@@ -350,11 +352,11 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
     bool kp = true;
     if (va <= vb) {  // A's element (first on equal ids)
       const u32 v = va;
-      u64 k = WRITE ? sk[i] : 0ull;
+      u64 k = KEYS ? sk[i] : 0ull;
       const bool dup = j < nB ? vb == v : (hasNext && bnext == v);
-      if (dup && (WRITE || a.prefer == PREFER_LIVE)) {
-        const u64 ka = WRITE ? k : a.ak[i0 + i];
-        const u64 kb = j < nB ? (WRITE ? sk[nA + j] : a.bk[j0 + j]) : a.bk[j1];
+      if (dup && (KEYS || a.prefer == PREFER_LIVE)) {
+        const u64 ka = KEYS ? k : a.ak[i0 + i];
+        const u64 kb = j < nB ? (KEYS ? sk[nA + j] : a.bk[j0 + j]) : a.bk[j1];
         kp = pair_keep(a, ka, kb, v, &k);
       }
       vo[q] = v;
@@ -365,9 +367,9 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
       va = i < nA ? sA[i] : NONE;
     } else {  // B's element: dropped when A holds the id
       const u32 v = vb;
-      const u64 k = WRITE ? sk[nA + j] : 0ull;
+      const u64 k = KEYS ? sk[nA + j] : 0ull;
       kp = !(havePrevA && prevA == v);
-      if (kp && a.filterB) kp = a.cur[v] == (WRITE ? k : a.bk[j0 + j]);
+      if (kp && a.filterB) kp = a.cur[v] == (KEYS ? k : a.bk[j0 + j]);
       vo[q] = v;
       ko[q] = k;
       ++j;
@@ -379,11 +381,29 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
   if constexpr (!WRITE) {
     const u32 tot = block_sum<NT>(nk, sw);
     if (threadIdx.x == 0) tcnt[t] = tot;
+    if constexpr (KEYS) {
+      // statistics of the kept outputs: how many are <= (pk, pv), and the
+      // key range
+      u32 nle = 0;
+      u64 lo = KINF, hi = 0;
+#pragma unroll
+      for (int q = 0; q < WE; ++q)
+        if ((keep >> q) & 1u) {
+          nle += kv_le(KV{ko[q], vo[q]}, KV{a.pk, a.pv});
+          lo = ko[q] < lo ? ko[q] : lo;
+          hi = ko[q] > hi ? ko[q] : hi;
+        }
+      nle = block_sum<NT>(nle, sw);
+      block_minmax<NT>(lo, hi, swl, swh);
+      if (threadIdx.x == 0) {
+        pt.cnt[t] = nle;
+        pt.lo[t] = lo;
+        pt.hi[t] = hi;
+      }
+    }
   } else {
     u32 tot;
     u32 o = block_scan<NT>(nk, &tot, sw);  // its barriers also end every walk's reads of sv / sk
-    u32 nle = 0;
-    u64 lo = KINF, hi = 0;
 #pragma unroll
     for (int q = 0; q < WE; ++q)
       if ((keep >> q) & 1u) {
@@ -391,11 +411,6 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
         sk[z] = ko[q];
         sv[z] = vo[q];
         ++o;
-        if (stats) {
-          nle += kv_le(KV{ko[q], vo[q]}, KV{a.pk, a.pv});
-          lo = ko[q] < lo ? ko[q] : lo;
-          hi = ko[q] > hi ? ko[q] : hi;
-        }
       }
     __syncthreads();
     const u32 base = toff[t];
@@ -408,24 +423,15 @@ __global__ __launch_bounds__(NT) void k_merge(MArgs a, const u32* part, u32* par
         a.cv[base + x] = sv[z];
       }
     }
-    if (stats) {
-      nle = block_sum<NT>(nle, sw);
-      block_minmax<NT>(lo, hi, swl, swh);
-      if (threadIdx.x == 0) {
-        pt.cnt[t] = nle;
-        pt.lo[t] = lo;
-        pt.hi[t] = hi;
-      }
-    }
   }
 }
 
 // A step published by the kernel that computes the last result the host
-// reads (a one-workgroup scan or reduction), instead of by k_post after the
-// step's last kernel: the host then reads the sizes and goes on while the
-// step's writing pass, whose output it never reads, still runs (its next
-// launches queue behind that pass on the stream).  mail == nullptr: the
-// kernel does not publish.
+// reads (the scan of a merge, split or compaction, which also folds the
+// merge's statistics), instead of by k_post after the step's last kernel:
+// the host then reads the sizes and goes on while the step's writing pass,
+// whose output it never reads, still runs (its next launches queue behind
+// that pass on the stream).  mail == nullptr: the kernel does not publish.
 struct Pub {
   const Mail* box;
   Mail* mail;
@@ -450,9 +456,8 @@ __device__ __forceinline__ void publish(const Pub& p) {
 }
 
 // Sums n partial counts into *sum (when sum != null) and folds the partial
-// key ranges into ctl->kmin / kmax.  One workgroup; publishes the step when
-// pub.mail is set.
-__global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32, u64* sum64, Ctl* c, Pub pub) {
+// key ranges into ctl->kmin / kmax.  One workgroup.
+__global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32, u64* sum64, Ctl* c) {
   __shared__ u32 sw[16];
   __shared__ u64 swl[16], swh[16];
   u64 tot = 0, lo = KINF, hi = 0;
@@ -473,18 +478,36 @@ __global__ __launch_bounds__(1024) void k_reduce(Partials pt, u32 n, u32* sum32,
       c->kmax = hi;
     }
   }
-  if (pub.mail) publish(pub);
 }
 
 // Exclusive scan of n tile counts (one workgroup of 1024); *total = the sum.
 // blockIdx.x selects one of several count arrays spaced `stride` apart.
-// With pub.mail set, the last of the workgroups to finish publishes the step
+// With fold.cnt set (one workgroup only) it also folds n per-tile partials:
+// *fold_sum = their count, ctl->kmin / kmax = their key range.  With
+// pub.mail set, the last of the workgroups to finish publishes the step
 // (ctl->scandone counts them; the totals are stored with agent-scope stores
 // so that it reads every one).
 __global__ __launch_bounds__(1024) void k_scan(const u32* cnt, u32 n, u32 stride, u32* off, u32* total, Ctl* ctl,
-                                               Pub pub) {
+                                               Pub pub, Partials fold, u32* fold_sum) {
   __shared__ u32 sw[16];
+  __shared__ u64 swl[16], swh[16];
   __shared__ int s_last;
+  if (fold.cnt) {
+    u32 c = 0;
+    u64 lo = KINF, hi = 0;
+    for (u32 x = threadIdx.x; x < n; x += 1024) {
+      c += fold.cnt[x];
+      lo = fold.lo[x] < lo ? fold.lo[x] : lo;
+      hi = fold.hi[x] > hi ? fold.hi[x] : hi;
+    }
+    c = block_sum<1024>(c, sw);
+    block_minmax<1024>(lo, hi, swl, swh);
+    if (threadIdx.x == 0) {
+      *fold_sum = c;
+      ctl->kmin = lo;
+      ctl->kmax = hi;
+    }
+  }
   cnt += (u64)blockIdx.x * stride;
   off += (u64)blockIdx.x * stride;
   u32 carry = 0;
@@ -1333,28 +1356,29 @@ int wmerge(WideScratch* w, Arr A, u32 na, Arr B, u32 nb, Arr C, const u64* cur, 
   const u32 nt = cdiv(total, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
   MArgs a{A.k, A.v, na, B.k, B.v, nb, C.k, C.v, cur, prefer, filterB ? 1 : 0, piv.k, piv.v};
-  plaunch(w, WK_MERGE_COUNT, 4ull * total, [&] {
-    hipLaunchKernelGGL(k_merge<false>, dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
-                       (const u32*)nullptr, w->pt, 0);
-  });
-  // The step is published by the scan (the output size) or, when the count
-  // of outputs <= the pivot is wanted, by the reduction after the writing
-  // pass.
+  // With stats the counting pass also stages the keys and counts the outputs
+  // <= piv and their key range; the scan folds those and publishes the step,
+  // so the host goes on while the writing pass runs.
+  if (stats)
+    plaunch(w, WK_MERGE_COUNT, 12ull * total, [&] {
+      hipLaunchKernelGGL((k_merge<false, true>), dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part, w->tc,
+                         (const u32*)nullptr, w->pt);
+    });
+  else
+    plaunch(w, WK_MERGE_COUNT, 4ull * total, [&] {
+      hipLaunchKernelGGL((k_merge<false, false>), dim3(nt), dim3(NT), 0, w->s, a, (const u32*)nullptr, w->part,
+                         w->tc, (const u32*)nullptr, w->pt);
+    });
   const u32 want = ++w->seq;
-  const Pub pub{w->box, w->mail_d, want}, none{nullptr, nullptr, 0u};
-  plaunch(w, WK_OTHER, 8ull * nt, [&] {
+  plaunch(w, WK_OTHER, (stats ? 28ull : 8ull) * nt, [&] {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total, w->ctl,
-                       stats ? none : pub);
+                       Pub{w->box, w->mail_d, want}, stats ? w->pt : Partials{nullptr, nullptr, nullptr},
+                       &w->box->num_le);
   });
   const int iw = plaunch(w, WK_MERGE_WRITE, 12ull * total, [&] {
-    hipLaunchKernelGGL(k_merge<true>, dim3(nt), dim3(NT), 0, w->s, a, w->part, (u32*)nullptr, (u32*)nullptr,
-                       w->toff, w->pt, stats ? 1 : 0);
+    hipLaunchKernelGGL((k_merge<true, true>), dim3(nt), dim3(NT), 0, w->s, a, (const u32*)w->part, (u32*)nullptr,
+                       (u32*)nullptr, (const u32*)w->toff, w->pt);
   });
-  if (stats)
-    plaunch(w, WK_OTHER, 20ull * nt, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, nt, &w->box->num_le, (u64*)nullptr, w->ctl,
-                         pub);
-    });
   if (int rc = launch_ok()) return rc;
   if (int rc = wait_mail(w, want)) return rc;
   *m = w->mail_h->total;
@@ -1377,8 +1401,7 @@ int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2
     const u32 gm = grid_for(n);
     plaunch(w, WK_OTHER, 8ull * n, [&] { hipLaunchKernelGGL(k_minmax, dim3(gm), dim3(NT), 0, w->s, A.k, n, w->pt); });
     plaunch(w, WK_OTHER, 20ull * gm, [&] {
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl,
-                         Pub{nullptr, nullptr, 0u});
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, w->pt, gm, (u32*)nullptr, (u64*)nullptr, w->ctl);
     });
   }
   const u32 g = grid_for(n), gh = std::min<u32>(g, GRID_HIST);
@@ -1429,7 +1452,7 @@ int wpartition3_sel(WideScratch* w, Arr A, u32 n, KV p1, KV p2, Arr O0, Arr O1, 
   const u32 want = ++w->seq;
   plaunch(w, WK_OTHER, 24ull * nt, [&] {
     hipLaunchKernelGGL(k_scan, dim3(3), dim3(1024), 0, w->s, w->tc, nt, w->maxtiles, w->toff, w->box->part, w->ctl,
-                       Pub{w->box, w->mail_d, want});
+                       Pub{w->box, w->mail_d, want}, Partials{nullptr, nullptr, nullptr}, (u32*)nullptr);
   });
   plaunch(w, WK_SPLIT_WRITE, 24ull * n, [&] {
     hipLaunchKernelGGL(k_part<true>, dim3(nt), dim3(NT), 0, w->s, a, (u32*)nullptr, w->toff, w->maxtiles);
@@ -1703,7 +1726,7 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
   });
   plaunch(w, WK_OTHER, 4ull * gi, [&] {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                       (u32*)nullptr, &w->box->newly, w->ctl, Pub{nullptr, nullptr, 0u});
+                       (u32*)nullptr, &w->box->newly, w->ctl);
   });
   const u32 nt = cdiv(h->nwords, TILE);
   if (nt > w->maxtiles) return E_INTERNAL;
@@ -1719,7 +1742,7 @@ int wide_bulk_update(WideScratch* w, WideHeap* h, const u64* keys, const u32* id
   const u32 want = ++w->seq;
   plaunch(w, WK_OTHER, 8ull * nt, [&] {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, w->s, w->tc, nt, 0u, w->toff, &w->box->total, w->ctl,
-                       Pub{w->box, w->mail_d, want});
+                       Pub{w->box, w->mail_d, want}, Partials{nullptr, nullptr, nullptr}, (u32*)nullptr);
   });
   const int ib = plaunch(w, WK_BITS_WRITE, nmark, [&] {
     hipLaunchKernelGGL(k_bits<true>, dim3(nt), dim3(NT), 0, w->s, w->marks, h->nwords, (u32*)nullptr, w->toff,
@@ -1764,7 +1787,7 @@ int wide_delete(WideScratch* w, WideHeap* h, const u32* ids, u64 count) {
           [&] { hipLaunchKernelGGL(k_delete, dim3(gi), dim3(NT), 0, w->s, ids, count, h->cur, w->pt); });
   plaunch(w, WK_OTHER, 4ull * gi, [&] {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, w->s, Partials{w->pt.cnt, nullptr, nullptr}, gi,
-                       (u32*)nullptr, &w->box->newly, w->ctl, Pub{nullptr, nullptr, 0u});
+                       (u32*)nullptr, &w->box->newly, w->ctl);
   });
   if (int rc = launch_ok()) return rc;
   const Lvl a0 = st->L[0];
