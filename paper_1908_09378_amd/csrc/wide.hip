@@ -744,6 +744,9 @@ __global__ __launch_bounds__(NT) void k_sel_pass(const u64* K, const u32* V, u32
   }
   const int w = 96 - q.nb < SEL_BITS ? 96 - q.nb : SEL_BITS;
   const int p = 96 - q.nb - w;
+  // the ids take part only once the prefix or this pass's digit reaches
+  // them; until then the pass reads the keys alone
+  const bool needv = q.nb > 64 || p < 32;
   h[threadIdx.x] = 0;
   __syncthreads();
   const u64 step = (u64)gridDim.x * NT;
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(NT) void k_sel_pass(const u64* K, const u32* V, u32
     for (int j = 0; j < 4; ++j) {
       const u64 x = x0 + j * step;
       k[j] = x < n ? K[x] : KINF;
-      v[j] = x < n ? V[x] : 0u;
+      v[j] = needv && x < n ? V[x] : 0u;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -818,6 +821,7 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
   const u32 pv = c->spv;
   const int nb = c->snb;
   const u64 step = (u64)gridDim.x * NT;
+  const bool needv = nb > 64;  // otherwise the match reads the keys alone, and a candidate's id is read when found
   if (!c->sbad)
     for (u64 x0 = (u64)blockIdx.x * NT + threadIdx.x; x0 < n; x0 += 4 * step) {
       u64 k[4];
@@ -826,7 +830,7 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
       for (int j = 0; j < 4; ++j) {
         const u64 x = x0 + j * step;
         k[j] = x < n ? K[x] : KINF;
-        v[j] = x < n ? V[x] : 0u;
+        v[j] = needv && x < n ? V[x] : 0u;
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -834,7 +838,7 @@ __global__ __launch_bounds__(NT) void k_sel_collect(const u64* K, const u32* V, 
           const u32 o = atomic_add32(&c->sncand, 1u);
           if (o < CANDMAX) {
             st_a64(ck + o, k[j]);
-            st_a32(cv + o, v[j]);
+            st_a32(cv + o, needv ? v[j] : V[x0 + j * step]);
           }
         }
     }
@@ -1412,11 +1416,11 @@ int wselpart(WideScratch* w, Arr A, u32 n, u32 r, bool have_range, KV cap, KV p2
   for (int round = 0; round < 4; ++round) {
     int ip[3];
     for (int p = 0; p < 3; ++p)
-      ip[p] = plaunch(w, WK_SEL_PASS, 12ull * n, [&] {
+      ip[p] = plaunch(w, WK_SEL_PASS, 8ull * n, [&] {
         hipLaunchKernelGGL(k_sel_pass, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, r,
                            round == 0 && p == 0 ? 1 : 0);
       });
-    const int ic = plaunch(w, WK_SEL_GATHER, 12ull * n, [&] {
+    const int ic = plaunch(w, WK_SEL_GATHER, 8ull * n, [&] {
       hipLaunchKernelGGL(k_sel_collect, dim3(gh), dim3(NT), 0, w->s, A.k, A.v, n, w->ctl, w->cand_k, w->cand_v,
                          w->box);
     });
