@@ -194,8 +194,14 @@ __device__ void deep_worker(DevTeam<NT, true>& t, HeapState PBH_LDS* st, unsigne
 // the dynamic LDS block, deeper levels in the query's slice of the HBM arena.
 // FULL: the large-heap form (staging for HBM merges, deep-level workers when
 // p.deep is set); otherwise the plain form.  SPEC false: the plain rule only.
+// Inlined into its kernel: called, it received the kernel's parameters as a
+// copy in private (scratch) memory, read back with vector loads in the round
+// loop, and the call's register conventions left 248-256 VGPRs and a 350-byte
+// stack frame per lane (inlined: 126-193 VGPRs, no stack; learned ring 1.58
+// -> 1.37 s, the paper's DAG 2.08 -> 1.68 s, plain ring 11.56 -> 10.56 s).
 template <int NT, bool FULL, bool SPEC = true>
-__device__ void sssp_query(DevTeam<NT, FULL>& t, HeapState PBH_LDS* st, unsigned char* dyn, const SsspParams& p) {
+__device__ __attribute__((always_inline)) void sssp_query(DevTeam<NT, FULL>& t, HeapState PBH_LDS* st,
+                                                         unsigned char* dyn, const SsspParams& p) {
   Geom g = p.g;
   const u64 nl = lvl_off(g.d, g.qlds);
   g.lk = reinterpret_cast<u64*>(dyn);
