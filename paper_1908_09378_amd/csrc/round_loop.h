@@ -172,7 +172,8 @@ struct DevDeepSync {
 // A deep-level worker: Resolve(lvl) whenever the level above asks, until the
 // front has finished (or any team has failed).
 template <int NT>
-__device__ void deep_worker(DevTeam<NT, true>& t, HeapState PBH_LDS* st, unsigned char* dyn, const SsspParams& p,
+__device__ __attribute__((always_inline)) void deep_worker(DevTeam<NT, true>& t, HeapState PBH_LDS* st,
+                                                          unsigned char* dyn, const SsspParams& p,
                             int lvl) {
   Geom g = p.g;
   g.lk = nullptr;  // worker levels are never in LDS
