@@ -401,8 +401,9 @@ const char *sssp_nearfar_last_error(void);
  * the faster of those is written back into *opts (d, team, k_max; the other
  * fields, k_scale and deep_level included, are kept and used for the
  * trials).  With the learned rule and opts->k_every == 0, the winner also
- * runs once with the model every fourth round, and opts->k_every becomes 4
- * or 1, whichever was faster.  A query that finishes within a frontier
+ * runs once with the model every 4th and once with it every 16th round, and
+ * opts->k_every becomes 1, 4 or 16, whichever was fastest.  A query that
+ * finishes within a frontier
  * trial skips the later stages.
  * dist_out is used as scratch.  Errors: those of sssp_ex.
  */

@@ -1177,18 +1177,25 @@ int sssp_autotune(const uint64_t* offsets, const uint32_t* targets, const uint32
   opts->team = ranked[0].team;
   opts->k_scale = opts->k_scale > 0.0f ? opts->k_scale : 1.0f;
   // Learned rule, k_every left to the tuner: the winner (whose time is that
-  // of a whole run) also runs with the model every fourth round; the faster
-  // of the two stays.
+  // of a whole run) also runs with the model every 4th and every 16th round;
+  // the fastest of the three stays.
   if (opts->k_rule == 2 && opts->k_every == 0 && ranked[0].kmax != 1) {
     sssp_opts t = *opts;
     t.stop_key = 0;
     t.max_rounds = 0;
     t.trace_features = nullptr;
-    t.k_every = 4;
-    sssp_stats st;
-    rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
-    if (rc) return rc;
-    opts->k_every = st.kernel_ms < ranked[0].ms ? 4u : 1u;
+    double best = ranked[0].ms;
+    opts->k_every = 1;
+    for (u32 ke : {4u, 16u}) {
+      t.k_every = ke;
+      sssp_stats st;
+      rc = sssp_ex(offsets, targets, weights, n, m, source, dist_out, &t, &st, stream);
+      if (rc) return rc;
+      if (st.kernel_ms < best) {
+        best = st.kernel_ms;
+        opts->k_every = ke;
+      }
+    }
   }
   return PBH_OK;
 }
